@@ -1,0 +1,148 @@
+"""N-Queens counting oracle -- test infrastructure, not part of the product.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``liboracle.so`` (plain C,
+board arrays, built from ``oracle.c`` by ``oracle/build.py``) and shares no code
+with the GPU library.  What each function computes, and the readings of the
+paper it takes, are stated in ``oracle.c``.
+
+Functions
+---------
+queens(n)                      -> (Q(n), nodes from row 0)
+count_prefix(n, prefix)        -> (completions, nodes in rows k..n-2)
+brute_count(n, prefix=())      -> completions by permutation enumeration (n <= 11)
+frontier(n, k)                 -> (prefixes int32[F, k], weights uint8[F])
+frontier_size(n, k)            -> F
+prefix_masks(n, prefix)        -> (cols, ld, rd) attack masks on row len(prefix)
+frontier_masks(n, k)           -> (cols, ld, rd uint32[F], weights uint8[F])
+count_prefixes(n, prefixes, threads) -> (counts uint64[F], nodes uint64[F])
+"""
+from __future__ import annotations
+
+import ctypes as _ct
+import os as _os
+
+import numpy as _np
+
+from . import build as _build
+
+_HERE = _os.path.dirname(_os.path.abspath(__file__))
+_LIB = None
+
+OQ_OK, OQ_EINVAL, OQ_ERANGE, OQ_ENOMEM = 0, -1, -2, -3
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = _os.path.join(_HERE, "liboracle.so")
+        if not _os.path.exists(path):
+            _build.build()
+        lib = _ct.CDLL(path)
+        u64p = _ct.POINTER(_ct.c_uint64)
+        u32p = _ct.POINTER(_ct.c_uint32)
+        i32p = _ct.POINTER(_ct.c_int)
+        u8p = _ct.POINTER(_ct.c_uint8)
+        lib.oq_queens.argtypes = [_ct.c_int, u64p, u64p]
+        lib.oq_count_prefix.argtypes = [_ct.c_int, _ct.c_int, i32p, u64p, u64p]
+        lib.oq_brute_count.argtypes = [_ct.c_int, _ct.c_int, i32p, u64p]
+        lib.oq_frontier.argtypes = [_ct.c_int, _ct.c_int, i32p, u8p, _ct.c_uint64, u64p]
+        lib.oq_prefix_masks.argtypes = [_ct.c_int, _ct.c_int, i32p, u32p, u32p, u32p]
+        lib.oq_count_prefixes.argtypes = [_ct.c_int, _ct.c_int, i32p, _ct.c_uint64, _ct.c_int,
+                                          u64p, u64p]
+        for f in (lib.oq_queens, lib.oq_count_prefix, lib.oq_brute_count, lib.oq_frontier,
+                  lib.oq_prefix_masks, lib.oq_count_prefixes):
+            f.restype = _ct.c_int
+        _LIB = lib
+    return _LIB
+
+
+def _check(rc, what):
+    if rc != OQ_OK:
+        raise OracleError(f"{what} failed with status {rc}")
+
+
+def _iarr(seq):
+    a = _np.ascontiguousarray(_np.asarray(seq, dtype=_np.int32))
+    return a, a.ctypes.data_as(_ct.POINTER(_ct.c_int))
+
+
+def queens(n: int):
+    """Q(n) by plain backtracking over every column of every row."""
+    c, nd = _ct.c_uint64(), _ct.c_uint64()
+    _check(_lib().oq_queens(n, _ct.byref(c), _ct.byref(nd)), "oq_queens")
+    return c.value, nd.value
+
+
+def count_prefix(n: int, prefix):
+    """Completions of rows len(prefix)..n-1 below ``prefix`` and the node count."""
+    a, p = _iarr(prefix)
+    c, nd = _ct.c_uint64(), _ct.c_uint64()
+    _check(_lib().oq_count_prefix(n, len(a), p, _ct.byref(c), _ct.byref(nd)), "oq_count_prefix")
+    return c.value, nd.value
+
+
+def brute_count(n: int, prefix=()):
+    """Completions of ``prefix`` by enumerating permutations (n <= 11)."""
+    a, p = _iarr(list(prefix) if len(prefix) else [0])
+    c = _ct.c_uint64()
+    _check(_lib().oq_brute_count(n, len(prefix), p, _ct.byref(c)), "oq_brute_count")
+    return c.value
+
+
+def frontier_size(n: int, k: int) -> int:
+    ln = _ct.c_uint64()
+    _check(_lib().oq_frontier(n, k, None, None, 0, _ct.byref(ln)), "oq_frontier(size)")
+    return ln.value
+
+
+def frontier(n: int, k: int):
+    """Symmetry-reduced prefixes (int32[F, k]) and weights (uint8[F]) in canonical order."""
+    size = frontier_size(n, k)
+    pre = _np.zeros((max(size, 1), max(k, 1)), dtype=_np.int32)
+    w = _np.zeros(max(size, 1), dtype=_np.uint8)
+    ln = _ct.c_uint64()
+    _check(_lib().oq_frontier(n, k, pre.ctypes.data_as(_ct.POINTER(_ct.c_int)),
+                              w.ctypes.data_as(_ct.POINTER(_ct.c_uint8)), size, _ct.byref(ln)),
+           "oq_frontier")
+    return pre[:size, :k], w[:size]
+
+
+def prefix_masks(n: int, prefix):
+    a, p = _iarr(list(prefix) if len(prefix) else [0])
+    c, l, r = _ct.c_uint32(), _ct.c_uint32(), _ct.c_uint32()
+    _check(_lib().oq_prefix_masks(n, len(prefix), p, _ct.byref(c), _ct.byref(l), _ct.byref(r)),
+           "oq_prefix_masks")
+    return c.value, l.value, r.value
+
+
+def frontier_masks(n: int, k: int):
+    """(cols, ld, rd) uint32[F] for every frontier prefix, plus weights uint8[F]."""
+    pre, w = frontier(n, k)
+    f = len(w)
+    cols = _np.zeros(f, dtype=_np.uint32)
+    ld = _np.zeros(f, dtype=_np.uint32)
+    rd = _np.zeros(f, dtype=_np.uint32)
+    for i in range(f):
+        cols[i], ld[i], rd[i] = prefix_masks(n, pre[i])
+    return cols, ld, rd, w
+
+
+def count_prefixes(n: int, prefixes, threads: int = 1):
+    """Completions and nodes of each row of ``prefixes`` (int[F, k])."""
+    pre = _np.ascontiguousarray(_np.asarray(prefixes, dtype=_np.int32))
+    if pre.ndim == 1:
+        pre = pre.reshape(-1, 0) if pre.size == 0 else pre.reshape(1, -1)
+    m, k = pre.shape
+    counts = _np.zeros(max(m, 1), dtype=_np.uint64)
+    nodes = _np.zeros(max(m, 1), dtype=_np.uint64)
+    buf = pre if pre.size else _np.zeros(1, dtype=_np.int32)
+    _check(_lib().oq_count_prefixes(n, k, buf.ctypes.data_as(_ct.POINTER(_ct.c_int)), m, threads,
+                                    counts.ctypes.data_as(_ct.POINTER(_ct.c_uint64)),
+                                    nodes.ctypes.data_as(_ct.POINTER(_ct.c_uint64))),
+           "oq_count_prefixes")
+    return counts[:m], nodes[:m]
