@@ -15,6 +15,7 @@ frontier(n, k)                 -> (prefixes int32[F, k], weights uint8[F])
 frontier_size(n, k)            -> F
 prefix_masks(n, prefix)        -> (cols, ld, rd) attack masks on row len(prefix)
 frontier_masks(n, k)           -> (cols, ld, rd uint32[F], weights uint8[F])
+prefixes_masks(n, prefixes)    -> (cols, ld, rd uint32[m]) for many prefixes
 count_prefixes(n, prefixes, threads) -> (counts uint64[F], nodes uint64[F])
 """
 from __future__ import annotations
@@ -52,10 +53,12 @@ def _lib():
         lib.oq_brute_count.argtypes = [_ct.c_int, _ct.c_int, i32p, u64p]
         lib.oq_frontier.argtypes = [_ct.c_int, _ct.c_int, i32p, u8p, _ct.c_uint64, u64p]
         lib.oq_prefix_masks.argtypes = [_ct.c_int, _ct.c_int, i32p, u32p, u32p, u32p]
+        lib.oq_prefixes_masks.argtypes = [_ct.c_int, _ct.c_int, i32p, _ct.c_uint64, u32p, u32p,
+                                          u32p]
         lib.oq_count_prefixes.argtypes = [_ct.c_int, _ct.c_int, i32p, _ct.c_uint64, _ct.c_int,
                                           u64p, u64p]
         for f in (lib.oq_queens, lib.oq_count_prefix, lib.oq_brute_count, lib.oq_frontier,
-                  lib.oq_prefix_masks, lib.oq_count_prefixes):
+                  lib.oq_prefix_masks, lib.oq_prefixes_masks, lib.oq_count_prefixes):
             f.restype = _ct.c_int
         _LIB = lib
     return _LIB
@@ -123,13 +126,21 @@ def prefix_masks(n: int, prefix):
 def frontier_masks(n: int, k: int):
     """(cols, ld, rd) uint32[F] for every frontier prefix, plus weights uint8[F]."""
     pre, w = frontier(n, k)
-    f = len(w)
-    cols = _np.zeros(f, dtype=_np.uint32)
-    ld = _np.zeros(f, dtype=_np.uint32)
-    rd = _np.zeros(f, dtype=_np.uint32)
-    for i in range(f):
-        cols[i], ld[i], rd[i] = prefix_masks(n, pre[i])
-    return cols, ld, rd, w
+    return prefixes_masks(n, pre) + (w,)
+
+
+def prefixes_masks(n: int, prefixes):
+    """(cols, ld, rd) uint32[m] for each row of ``prefixes`` (int[m, k])."""
+    pre = _np.ascontiguousarray(_np.asarray(prefixes, dtype=_np.int32))
+    m, k = pre.shape
+    cols = _np.zeros(max(m, 1), dtype=_np.uint32)
+    ld = _np.zeros(max(m, 1), dtype=_np.uint32)
+    rd = _np.zeros(max(m, 1), dtype=_np.uint32)
+    buf = pre if pre.size else _np.zeros(1, dtype=_np.int32)
+    u32 = lambda a: a.ctypes.data_as(_ct.POINTER(_ct.c_uint32))  # noqa: E731
+    _check(_lib().oq_prefixes_masks(n, k, buf.ctypes.data_as(_ct.POINTER(_ct.c_int)), m,
+                                    u32(cols), u32(ld), u32(rd)), "oq_prefixes_masks")
+    return cols[:m], ld[:m], rd[:m]
 
 
 def count_prefixes(n: int, prefixes, threads: int = 1):

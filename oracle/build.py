@@ -9,7 +9,7 @@ def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "oracle.c")
     out = os.path.join(HERE, "liboracle.so")
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-pthread",
+    cmd = ["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-pthread",
            src, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -54,7 +54,7 @@ static void board_init(board_t* b, int n) {
 }
 
 static int board_free(const board_t* b, int r, int c) {
-    return !b->col[c] && !b->dsum[r + c] && !b->ddif[r - c + b->n - 1];
+    return !(b->col[c] | b->dsum[r + c] | b->ddif[r - c + b->n - 1]);
 }
 
 static void board_set(board_t* b, int r, int c, unsigned char v) {
@@ -257,6 +257,17 @@ int oq_prefix_masks(int n, int k, const int* prefix, uint32_t* cols, uint32_t* l
         if (c - d >= 0) R |= (uint32_t)1 << (c - d);
     }
     *cols = C; *ld = L; *rd = R;
+    return OQ_OK;
+}
+
+/* Attack masks of m prefixes of length k (oq_prefix_masks applied to each). */
+int oq_prefixes_masks(int n, int k, const int* prefixes, uint64_t m, uint32_t* cols,
+                      uint32_t* ld, uint32_t* rd) {
+    if (!valid_nk(n, k) || !cols || !ld || !rd || (m > 0 && k > 0 && !prefixes)) return OQ_EINVAL;
+    for (uint64_t i = 0; i < m; ++i) {
+        int rc = oq_prefix_masks(n, k, prefixes + i * (uint64_t)k, cols + i, ld + i, rd + i);
+        if (rc != OQ_OK) return rc;
+    }
     return OQ_OK;
 }
 

@@ -1,0 +1,65 @@
+"""Writes oracle_runs.txt: per-frontier oracle results used as stored expected values.
+
+Calls only the oracle package.  For each (N, k) it enumerates the symmetry-reduced
+frontier, counts every prefix's completions and nodes with the oracle, and
+records: F, the weighted total, the node total, and SHA-256 digests of the
+per-prefix counts and nodes (little-endian uint64 in canonical frontier order),
+so that a test can check every per-subproblem result without rerunning the
+oracle.  Usage:  python tests/golden/make_golden.py N:k [N:k ...] [--threads T]
+An existing line for the same (N, k) is replaced.
+"""
+import argparse
+import hashlib
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+
+OUT = os.path.join(HERE, "oracle_runs.txt")
+HEADER = """# Oracle results per frontier, written by tests/golden/make_golden.py (oracle only).
+# N k F weighted_total node_total sha256(counts u64 LE) sha256(nodes u64 LE) oracle_seconds threads
+"""
+
+
+def digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<u8").tobytes()).hexdigest()
+
+
+def run(n, k, threads):
+    t0 = time.time()
+    pre, w = oracle.frontier(n, k)
+    counts, nodes = oracle.count_prefixes(n, pre, threads=threads)
+    secs = time.time() - t0
+    total = int(np.sum(counts.astype(object) * w.astype(object))) if len(w) else 0
+    return (f"{n} {k} {len(w)} {total} {int(nodes.sum())} {digest(counts)} {digest(nodes)} "
+            f"{secs:.1f} {threads}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cases", nargs="+")
+    ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
+    args = ap.parse_args()
+    for case in args.cases:
+        n, k = (int(x) for x in case.split(":"))
+        line = run(n, k, args.threads)
+        print(line, flush=True)
+        lines = []
+        if os.path.exists(OUT):
+            with open(OUT) as f:
+                lines = [ln for ln in f if ln.strip() and not ln.startswith("#")]
+        lines = [ln for ln in lines if ln.split()[:2] != [str(n), str(k)]] + [line + "\n"]
+        lines.sort(key=lambda ln: (int(ln.split()[0]), int(ln.split()[1])))
+        with open(OUT, "w") as f:
+            f.write(HEADER)
+            f.writelines(lines)
+
+
+if __name__ == "__main__":
+    main()
