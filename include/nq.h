@@ -1,0 +1,160 @@
+/*
+ * libnq -- exact N-Queens solution counting on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Yao & Li, "High-Performance N-Queens Solver on GPU: Iterative DFS
+ * with Zero Bank Conflicts"):
+ *   - Section 1: the board is split into independent subtrees by pre-placing the
+ *     queens of the first k rows.  Only the first half of row 0 is enumerated
+ *     (mirror symmetry, weight 2); for odd N the centre column of row 0 is added
+ *     with the row-1 queen restricted to the first N/2 - 1 columns (weight 2).
+ *     The solution count is the weighted sum of the subtrees' leaf counts.
+ *   - Section 2, Algorithm 1: a subproblem is the Somers triple (cols, ld, rd) of
+ *     32-bit masks; placing bit p does cols |= p, ld = (ld | p) << 1,
+ *     rd = (rd | p) >> 1, and the free squares of the next row are
+ *     last & ~(cols | ld | rd) with last = 2^N - 1.
+ *   - Section 2, Algorithm 2, and Section 3.2.3 / Algorithm 3: each subtree is
+ *     searched by an iterative DFS with an explicit stack of (cols, ld, rd,
+ *     avail) frames; the last row is never pushed, its free squares are counted.
+ *   - Section 4.5: N = 28 is the last size whose count fits in 64 bits.
+ *
+ * Conventions for every entry point:
+ *   - Return value: NQ_OK (0) or a negative NQ_E* status.  Nothing throws, aborts
+ *     or exits.  Outputs are written through pointers and only on NQ_OK, except
+ *     where a function says otherwise (nq_frontier with NQ_ERANGE).
+ *   - Bit j of a mask stands for column j.  Valid board sizes: 1 <= n <= 28
+ *     (NQ_MAX_N); larger n is NQ_EINVAL.
+ *   - Counts are exact uint64.  Per-subproblem counts are UNWEIGHTED; totals are
+ *     weighted by the symmetry weights.
+ *   - Host buffers are owned by the caller.  Device buffers passed in are owned
+ *     by the caller and must stay valid until the work on the given stream ends.
+ *   - A HIP failure returns NQ_EDEVICE; nq_last_hip_error() gives the hipError_t
+ *     of the failing call on the calling thread.
+ *   - Calls on distinct streams may run concurrently.  A server handle is
+ *     internally locked.
+ */
+#ifndef NQ_H_
+#define NQ_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NQ_MAX_N 28
+
+enum nq_status {
+    NQ_OK = 0,
+    NQ_EINVAL = -1,   /* invalid argument                                        */
+    NQ_ERANGE = -2,   /* output buffer too small; *out_len holds the needed size  */
+    NQ_ENOMEM = -3,   /* host or device allocation failed, or over a memory cap   */
+    NQ_EDEVICE = -4,  /* a HIP call failed; see nq_last_hip_error()              */
+    NQ_EAGAIN = -5,   /* nq_serve_poll: the request is not finished yet           */
+    NQ_EFULL = -6,    /* nq_serve_submit: admission refused, retry later          */
+    NQ_ENOENT = -7    /* unknown ticket                                           */
+};
+
+/* Static, human-readable text for a status code (never NULL). */
+const char* nq_strerror(int status);
+
+/* hipError_t of the last failing HIP call made by this library on this thread. */
+int nq_last_hip_error(void);
+
+/*
+ * nq_frontier -- the pre-placed subproblems of Section 1 / Algorithm 1.
+ *
+ * Enumerates every legal placement of queens in rows 0..depth-1 of an n x n
+ * board under the symmetry rule above, in lexicographic order of the columns
+ * (c_0, ..., c_{depth-1}), and writes each as the Somers triple it leaves for
+ * row `depth`:
+ *   cols[i] = columns taken, ld[i] and rd[i] = squares of row `depth` attacked
+ *   along the two diagonals (ld masked to n bits), weight[i] = 2, except 1 for
+ *   depth == 0 (the empty board) and for the odd-n centre entry when depth == 1.
+ * Entries whose row `depth` has no free square are kept (their count is 0).
+ *
+ * n in [1, 28], depth in [0, n].  Size query: if cols, ld or rd is NULL, or
+ * capacity == 0, only *out_len = F is written and NQ_OK returned.  Otherwise
+ * the arrays (length >= capacity; weight may be NULL) are filled; if
+ * capacity < F the first `capacity` entries are written, *out_len = F and
+ * NQ_ERANGE is returned.  Host memory only; thread-safe.
+ */
+int nq_frontier(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld, uint32_t* rd,
+                uint8_t* weight, uint64_t capacity, uint64_t* out_len);
+
+/* Scheduling modes of the DFS kernels. */
+enum nq_mode {
+    NQ_MODE_AUTO = 0,        /* persistent                                            */
+    NQ_MODE_PLAIN = 1,       /* one lane per subproblem, grid = ceil(F / wg_size)     */
+    NQ_MODE_PERSISTENT = 2   /* resident grid, lanes refilled from an atomic queue    */
+};
+
+/*
+ * Options shared by the counting entry points.  A NULL options pointer, or a
+ * zero field, means "automatic".
+ */
+typedef struct nq_opts {
+    uint32_t depth;          /* pre-placed rows k (nq_count / nq_count_batch); 0 = auto */
+    uint32_t mode;           /* enum nq_mode                                           */
+    uint32_t wg_size;        /* threads per workgroup, multiple of 64, <= 1024         */
+    uint32_t waves_per_cu;   /* persistent grid: resident waves per CU (0 = max fit)   */
+    uint32_t refill_every;   /* DFS steps between refill checks (0 = default)          */
+    uint32_t reserved;       /* must be 0                                              */
+    void* stream;            /* hipStream_t to run on; NULL = the null stream          */
+    uint64_t* counts_out;    /* nq_count: optional host buffer, F unweighted counts    */
+    uint64_t counts_capacity;/* length of counts_out                                   */
+    double* kernel_ms_out;   /* optional: device time of the DFS kernel(s), HIP events;
+                                setting it makes the call wait for the kernel         */
+    uint64_t* d_nodes;       /* nq_count_subproblems only, optional device uint64[len]:
+                                DFS nodes of each subproblem (queens placed in rows
+                                placed..n-2); selects the node-counting kernel        */
+} nq_opts;
+
+/*
+ * nq_count -- Q(n): the number of ways to place n non-attacking queens.
+ *
+ * Builds the frontier of depth opts->depth on the host (nq_frontier), copies it
+ * to device memory owned by the library, runs the DFS kernels (Algorithm 2 with
+ * the last-row step of Algorithm 3, one subproblem per lane) and returns the
+ * weighted total in *out_total.  Synchronous: returns after the result is on the
+ * host.  If opts->counts_out is set, it receives the per-subproblem counts in
+ * frontier order (NQ_ERANGE if counts_capacity < F).  n in [1, 28].
+ */
+int nq_count(uint32_t n, const nq_opts* opts, uint64_t* out_total);
+
+/*
+ * nq_count_subproblems -- count the subtrees of caller-provided subproblems.
+ *
+ * Device pointers: d_cols, d_ld, d_rd (uint32[len], Somers triples for an
+ * n x n board, bit j = column j; bits >= n are ignored), d_weight (uint8[len]
+ * or NULL for weight 1), d_counts (uint64[len] or NULL) receives each
+ * subproblem's unweighted leaf count, d_total (one uint64 or NULL) is
+ * INCREASED by sum(weight * count) -- the caller zeroes it.  The queens already
+ * placed are the set bits of cols, so a triple with popcount(cols) = n counts 1,
+ * with n - 1 counts its free squares of the last row, and one with no free
+ * square counts 0.  opts->depth promises that every triple has at least that
+ * many queens placed; it sizes the LDS stack (n - 2 - depth frames per lane).
+ * A triple with fewer queens is not searched: its d_counts entry is set to
+ * UINT64_MAX and it adds nothing to d_total.  Asynchronous on opts->stream
+ * (unless kernel_ms_out is set); len == 0 launches nothing.
+ */
+int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
+                         const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len,
+                         uint64_t* d_counts, uint64_t* d_total, const nq_opts* opts);
+
+/*
+ * nq_count_batch -- many independent counts in one persistent launch.
+ *
+ * For each instance i < ninst, builds the frontier of ns[i] (depth from
+ * depths[i] when depths != NULL, else opts->depth or automatic), concatenates
+ * them with per-entry instance ids, runs one persistent DFS launch (captured
+ * and replayed as a HIP graph) and writes Q(ns[i]) to out_totals[i].
+ * Synchronous.  Every ns[i] in [1, 28].
+ */
+int nq_count_batch(uint32_t ninst, const uint32_t* ns, const uint32_t* depths,
+                   const nq_opts* opts, uint64_t* out_totals);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NQ_H_ */

@@ -1,0 +1,26 @@
+"""Exact N-Queens counting on AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding over ``libnq.so`` (see ``include/nq.h``): argument
+marshalling only, every step of the counting runs in the library's host code
+and HIP kernels.  PyTorch is used for device buffers and streams.  The library
+must have been built (``python -m paper_2511_12009_amd.build``); importing the
+binding without it raises ``NQError``.
+
+Functions (same names as the C entry points, without the ``nq_`` prefix):
+  frontier(n, depth)                         -> (cols, ld, rd, weight) numpy arrays
+  frontier_size(n, depth)                    -> F
+  count(n, depth=0, mode="persistent", ...)  -> Q(n)   (and counts / kernel ms)
+  count_subproblems(n, cols, ld, rd, ...)    -> per-entry counts and weighted total
+  count_batch(ns, depths=None, ...)          -> [Q(n) for n in ns]
+"""
+from ._native import (  # noqa: F401
+    NQError,
+    MODES,
+    count,
+    count_batch,
+    count_subproblems,
+    frontier,
+    frontier_size,
+    lib,
+    library_path,
+)

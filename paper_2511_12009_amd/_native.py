@@ -1,0 +1,196 @@
+"""ctypes declarations of libnq.so and the Python-level wrappers."""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libnq.so")
+
+NQ_OK, NQ_EINVAL, NQ_ERANGE, NQ_ENOMEM, NQ_EDEVICE, NQ_EAGAIN, NQ_EFULL, NQ_ENOENT = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+MODES = {"auto": 0, "plain": 1, "persistent": 2}
+COUNT_INVALID = 0xFFFFFFFFFFFFFFFF
+
+
+class NQError(RuntimeError):
+    """A libnq call returned a negative status."""
+
+    def __init__(self, status: int, what: str, msg: str):
+        super().__init__(f"{what}: {msg} (status {status})")
+        self.status = status
+
+
+class NqOpts(ct.Structure):
+    _fields_ = [
+        ("depth", ct.c_uint32),
+        ("mode", ct.c_uint32),
+        ("wg_size", ct.c_uint32),
+        ("waves_per_cu", ct.c_uint32),
+        ("refill_every", ct.c_uint32),
+        ("reserved", ct.c_uint32),
+        ("stream", ct.c_void_p),
+        ("counts_out", ct.POINTER(ct.c_uint64)),
+        ("counts_capacity", ct.c_uint64),
+        ("kernel_ms_out", ct.POINTER(ct.c_double)),
+        ("d_nodes", ct.c_void_p),
+    ]
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded libnq.so; raises NQError if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(library_path):
+            raise NQError(NQ_EINVAL, "load",
+                          f"{library_path} is missing; run python -m paper_2511_12009_amd.build")
+        L = ct.CDLL(library_path)
+        u32, u64, vp = ct.c_uint32, ct.c_uint64, ct.c_void_p
+        pu32, pu64, pu8 = ct.POINTER(u32), ct.POINTER(u64), ct.POINTER(ct.c_uint8)
+        L.nq_strerror.argtypes = [ct.c_int]
+        L.nq_strerror.restype = ct.c_char_p
+        L.nq_last_hip_error.argtypes = []
+        L.nq_last_hip_error.restype = ct.c_int
+        L.nq_frontier.argtypes = [u32, u32, pu32, pu32, pu32, pu8, u64, pu64]
+        L.nq_frontier.restype = ct.c_int
+        L.nq_count.argtypes = [u32, ct.POINTER(NqOpts), pu64]
+        L.nq_count.restype = ct.c_int
+        L.nq_count_subproblems.argtypes = [u32, vp, vp, vp, vp, u64, vp, vp, ct.POINTER(NqOpts)]
+        L.nq_count_subproblems.restype = ct.c_int
+        L.nq_count_batch.argtypes = [u32, pu32, pu32, ct.POINTER(NqOpts), pu64]
+        L.nq_count_batch.restype = ct.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int, what: str):
+    if rc != NQ_OK:
+        L = lib()
+        msg = L.nq_strerror(rc).decode()
+        if rc == NQ_EDEVICE:
+            msg += f" (hipError {L.nq_last_hip_error()})"
+        raise NQError(rc, what, msg)
+
+
+def _opts(depth=0, mode="persistent", wg_size=0, waves_per_cu=0, refill_every=0, stream=None):
+    o = NqOpts()
+    o.depth = depth
+    o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    o.wg_size = wg_size
+    o.waves_per_cu = waves_per_cu
+    o.refill_every = refill_every
+    o.stream = stream
+    return o
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def frontier_size(n: int, depth: int) -> int:
+    ln = ct.c_uint64()
+    _check(lib().nq_frontier(n, depth, None, None, None, None, 0, ct.byref(ln)), "nq_frontier")
+    return ln.value
+
+
+def frontier(n: int, depth: int):
+    """(cols, ld, rd) uint32[F] and weight uint8[F] in canonical order (host arrays)."""
+    f = frontier_size(n, depth)
+    cols = np.zeros(max(f, 1), np.uint32)
+    ld = np.zeros(max(f, 1), np.uint32)
+    rd = np.zeros(max(f, 1), np.uint32)
+    w = np.zeros(max(f, 1), np.uint8)
+    ln = ct.c_uint64()
+    p32 = lambda a: a.ctypes.data_as(ct.POINTER(ct.c_uint32))  # noqa: E731
+    _check(lib().nq_frontier(n, depth, p32(cols), p32(ld), p32(rd),
+                             w.ctypes.data_as(ct.POINTER(ct.c_uint8)), f, ct.byref(ln)),
+           "nq_frontier")
+    return cols[:f], ld[:f], rd[:f], w[:f]
+
+
+def count(n: int, depth: int = 0, mode="persistent", wg_size: int = 0, waves_per_cu: int = 0,
+          refill_every: int = 0, counts: bool = False, timing: bool = False, stream=None):
+    """Q(n).  With counts=True also the per-subproblem counts (numpy uint64, frontier
+    order); with timing=True also the DFS kernel time in ms.  Synchronous."""
+    o = _opts(depth, mode, wg_size, waves_per_cu, refill_every,
+              stream if stream is None else _stream_handle(stream))
+    buf = None
+    if counts:
+        if depth == 0:
+            raise ValueError("counts=True needs an explicit depth")
+        buf = np.zeros(max(frontier_size(n, depth), 1), np.uint64)
+        o.counts_out = buf.ctypes.data_as(ct.POINTER(ct.c_uint64))
+        o.counts_capacity = len(buf)
+    ms = ct.c_double(0.0)
+    if timing:
+        o.kernel_ms_out = ct.pointer(ms)
+    total = ct.c_uint64()
+    _check(lib().nq_count(n, ct.byref(o), ct.byref(total)), "nq_count")
+    out = [total.value]
+    if counts:
+        out.append(buf[:frontier_size(n, depth)])
+    if timing:
+        out.append(ms.value)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None,
+                      depth: int = 0, mode="persistent", wg_size: int = 0,
+                      waves_per_cu: int = 0, refill_every: int = 0, stream=None,
+                      timing: bool = False, nodes=None):
+    """Counts every subtree of device-resident triples (torch int32 CUDA tensors).
+
+    ``counts`` (int64[F]) and ``total`` (int64[1], accumulated) are torch tensors
+    allocated here when not given.  ``depth`` promises that every triple has at
+    least that many queens placed (sizes the LDS stack).  Asynchronous on
+    ``stream`` (default: torch's current stream) unless timing=True.
+    ``nodes`` (int64[F] CUDA tensor) receives the DFS nodes of every entry.
+    Returns (counts, total) or (counts, total, kernel_ms).
+    """
+    import torch
+    length = cols.numel()
+    for t in (cols, ld, rd):
+        if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous() or t.numel() != length:
+            raise ValueError("cols, ld, rd must be contiguous int32 CUDA tensors of one length")
+    if weight is not None and (weight.dtype != torch.uint8 or weight.numel() != length):
+        raise ValueError("weight must be a uint8 CUDA tensor of the same length")
+    if counts is None:
+        counts = torch.empty(length, dtype=torch.int64, device=cols.device)
+    if total is None:
+        total = torch.zeros(1, dtype=torch.int64, device=cols.device)
+    o = _opts(depth, mode, wg_size, waves_per_cu, refill_every, _stream_handle(stream))
+    if nodes is not None:
+        if nodes.dtype != torch.int64 or nodes.numel() != length or not nodes.is_cuda:
+            raise ValueError("nodes must be an int64 CUDA tensor of the same length")
+        o.d_nodes = nodes.data_ptr()
+    ms = ct.c_double(0.0)
+    if timing:
+        o.kernel_ms_out = ct.pointer(ms)
+    _check(lib().nq_count_subproblems(
+        n, cols.data_ptr(), ld.data_ptr(), rd.data_ptr(),
+        None if weight is None else weight.data_ptr(), length,
+        None if counts is False else counts.data_ptr(), total.data_ptr(), ct.byref(o)),
+        "nq_count_subproblems")
+    return (counts, total, ms.value) if timing else (counts, total)
+
+
+def count_batch(ns, depths=None, mode="persistent", wg_size: int = 0, waves_per_cu: int = 0,
+                refill_every: int = 0, stream=None):
+    """[Q(n) for n in ns], all instances in one persistent launch."""
+    ns_a = np.ascontiguousarray(np.asarray(ns, dtype=np.uint32))
+    d_a = None if depths is None else np.ascontiguousarray(np.asarray(depths, dtype=np.uint32))
+    out = np.zeros(max(len(ns_a), 1), np.uint64)
+    o = _opts(0, mode, wg_size, waves_per_cu, refill_every,
+              stream if stream is None else _stream_handle(stream))
+    p32 = lambda a: None if a is None else a.ctypes.data_as(ct.POINTER(ct.c_uint32))  # noqa: E731
+    _check(lib().nq_count_batch(len(ns_a), p32(ns_a), p32(d_a), ct.byref(o),
+                                out.ctypes.data_as(ct.POINTER(ct.c_uint64))), "nq_count_batch")
+    return [int(x) for x in out[:len(ns_a)]]

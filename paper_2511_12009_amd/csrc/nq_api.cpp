@@ -1,0 +1,253 @@
+// C-ABI entry points: status text, nq_count, nq_count_subproblems, nq_count_batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "nq_internal.h"
+
+namespace nqi {
+
+static thread_local int g_last_hip_error = 0;
+
+void set_hip_error(int err) { g_last_hip_error = err; }
+
+namespace {
+
+#define NQ_HIP(call)                                       \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) {                            \
+            set_hip_error((int)e_);                        \
+            return NQ_EDEVICE;                             \
+        }                                                  \
+    } while (0)
+
+// Device buffer released on scope exit.
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    int alloc(size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            set_hip_error((int)e);
+            p = nullptr;
+            return e == hipErrorOutOfMemory ? NQ_ENOMEM : NQ_EDEVICE;
+        }
+        return NQ_OK;
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// Event pair timing the DFS launch on a stream.
+struct EventTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventTimer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    int start(hipStream_t s) {
+        NQ_HIP(hipEventCreate(&a));
+        NQ_HIP(hipEventCreate(&b));
+        NQ_HIP(hipEventRecord(a, s));
+        return NQ_OK;
+    }
+    int stop(hipStream_t s, double* ms) {
+        NQ_HIP(hipEventRecord(b, s));
+        NQ_HIP(hipEventSynchronize(b));
+        float f = 0.f;
+        NQ_HIP(hipEventElapsedTime(&f, a, b));
+        *ms = (double)f;
+        return NQ_OK;
+    }
+};
+
+uint32_t opt_mode(const nq_opts* o) {
+    uint32_t m = o ? o->mode : 0u;
+    return m == NQ_MODE_AUTO ? (uint32_t)NQ_MODE_PERSISTENT : m;
+}
+
+// Default pre-placement depth: the shallowest depth whose frontier has at least
+// `target` entries, capped so that every subtree keeps a few rows of search.
+uint32_t auto_depth(uint32_t n) {
+    const uint64_t target = 1u << 20;
+    uint32_t cap = n > 4 ? n - 4 : 1;
+    cap = std::min<uint32_t>(cap, 8);
+    for (uint32_t k = 1; k < cap; ++k) {
+        uint64_t f = 0;
+        if (frontier_fill(n, k, nullptr, nullptr, nullptr, nullptr, 0, &f, nullptr) != NQ_OK)
+            return 1;
+        if (f >= target) return k;
+    }
+    return std::max<uint32_t>(1, std::min(cap, n));
+}
+
+uint32_t refill_default(const nq_opts* o) {
+    return (o && o->refill_every) ? o->refill_every : 512u;
+}
+
+}  // namespace
+
+// Runs the DFS over device-resident entries of one board size.
+static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
+                      const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len,
+                      uint64_t* d_counts, unsigned long long* d_total, uint32_t min_placed,
+                      const nq_opts* opts, double* kernel_ms) {
+    if (len == 0) {
+        if (kernel_ms) *kernel_ms = 0.0;
+        return NQ_OK;
+    }
+    DeviceInfo dev;
+    int rc = device_info(&dev);
+    if (rc != NQ_OK) return rc;
+    const uint32_t mode = opt_mode(opts);
+    const uint32_t frames = std::max<uint32_t>(1, frames_needed(n, min_placed));
+    LaunchCfg cfg;
+    uint64_t* d_nodes = opts ? opts->d_nodes : nullptr;
+    rc = plan_launch(dev, mode, opts ? opts->wg_size : 0, opts ? opts->waves_per_cu : 0, frames,
+                     len, d_nodes != nullptr, leafctr_ok(n, min_placed), &cfg);
+    if (rc != NQ_OK) return rc;
+    hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
+    unsigned long long* head = nullptr;
+    if (mode == NQ_MODE_PERSISTENT) NQ_HIP(hipMallocAsync((void**)&head, 8, s));
+    DfsParams P{};
+    P.cols = d_cols; P.ld = d_ld; P.rd = d_rd; P.weight = d_weight;
+    P.counts = d_counts; P.totals = d_total; P.head = head; P.nodes = d_nodes;
+    P.len = len; P.n = n; P.frames = frames; P.refill_every = refill_default(opts);
+    EventTimer t;
+    if (kernel_ms && (rc = t.start(s)) != NQ_OK) return rc;
+    rc = launch_dfs(cfg, P, s);
+    if (rc == NQ_OK && kernel_ms) rc = t.stop(s, kernel_ms);
+    if (head) {
+        hipError_t e = hipFreeAsync(head, s);
+        if (e != hipSuccess && rc == NQ_OK) { set_hip_error((int)e); rc = NQ_EDEVICE; }
+    }
+    return rc;
+}
+
+}  // namespace nqi
+
+using namespace nqi;
+
+extern "C" const char* nq_strerror(int status) {
+    switch (status) {
+        case NQ_OK: return "ok";
+        case NQ_EINVAL: return "invalid argument";
+        case NQ_ERANGE: return "output buffer too small";
+        case NQ_ENOMEM: return "out of memory";
+        case NQ_EDEVICE: return "HIP runtime error";
+        case NQ_EAGAIN: return "not finished yet";
+        case NQ_EFULL: return "admission refused: no capacity";
+        case NQ_ENOENT: return "unknown ticket";
+        default: return "unknown status";
+    }
+}
+
+extern "C" int nq_last_hip_error(void) { return g_last_hip_error; }
+
+extern "C" int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
+                                    const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len,
+                                    uint64_t* d_counts, uint64_t* d_total, const nq_opts* opts) {
+    if (n < 1 || n > NQ_MAX_N) return NQ_EINVAL;
+    if (opts && opts->reserved != 0) return NQ_EINVAL;
+    if (len == 0) return NQ_OK;
+    if (!d_cols || !d_ld || !d_rd) return NQ_EINVAL;
+    const uint32_t min_placed = opts ? std::min(opts->depth, n) : 0u;
+    try {
+        return run_device(n, d_cols, d_ld, d_rd, d_weight, len, d_counts,
+                          reinterpret_cast<unsigned long long*>(d_total), min_placed, opts,
+                          opts ? opts->kernel_ms_out : nullptr);
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
+}
+
+extern "C" int nq_count(uint32_t n, const nq_opts* opts, uint64_t* out_total) {
+    if (n < 1 || n > NQ_MAX_N || !out_total) return NQ_EINVAL;
+    if (opts && opts->reserved != 0) return NQ_EINVAL;
+    const uint32_t depth = (opts && opts->depth) ? opts->depth : auto_depth(n);
+    if (depth > n) return NQ_EINVAL;
+    try {
+        uint64_t F = 0;
+        std::vector<uint64_t> first_row;
+        int rc = frontier_fill(n, depth, nullptr, nullptr, nullptr, nullptr, 0, &F, nullptr);
+        if (rc != NQ_OK) return rc;
+        if (opts && opts->counts_out && opts->counts_capacity < F) return NQ_ERANGE;
+        std::vector<uint32_t> hc(F), hl(F), hr(F);
+        std::vector<uint8_t> hw(F);
+        rc = frontier_fill(n, depth, hc.data(), hl.data(), hr.data(), hw.data(), F, &F,
+                           &first_row);
+        if (rc != NQ_OK) return rc;
+        hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
+        DevBuf buf;
+        // Layout: cols | ld | rd | counts | total | weight.
+        const size_t off_ld = F * 4, off_rd = 2 * F * 4, off_cnt = (3 * F * 4 + 7) & ~size_t(7);
+        const size_t off_tot = off_cnt + F * 8, off_w = off_tot + 8;
+        if ((rc = buf.alloc(off_w + F)) != NQ_OK) return rc;
+        char* b = buf.as<char>();
+        if (F) {
+            NQ_HIP(hipMemcpyAsync(b, hc.data(), F * 4, hipMemcpyHostToDevice, s));
+            NQ_HIP(hipMemcpyAsync(b + off_ld, hl.data(), F * 4, hipMemcpyHostToDevice, s));
+            NQ_HIP(hipMemcpyAsync(b + off_rd, hr.data(), F * 4, hipMemcpyHostToDevice, s));
+            NQ_HIP(hipMemcpyAsync(b + off_w, hw.data(), F, hipMemcpyHostToDevice, s));
+        }
+        auto* d_total = reinterpret_cast<unsigned long long*>(b + off_tot);
+        if ((rc = launch_zero_u64(d_total, 1, s)) != NQ_OK) return rc;
+        const uint32_t mode = opt_mode(opts);
+        const bool want_counts = opts && opts->counts_out;
+        double ms = 0.0, ms_part = 0.0;
+        if (mode == NQ_MODE_PLAIN) {
+            // One launch per row-0 column (the form the paper's host driver uses
+            // per GPU slice), each over its contiguous run of the frontier.
+            for (size_t j = 0; j + 1 < first_row.size(); ++j) {
+                const uint64_t lo = first_row[j], hi = first_row[j + 1];
+                rc = run_device(n, reinterpret_cast<uint32_t*>(b) + lo,
+                                reinterpret_cast<uint32_t*>(b + off_ld) + lo,
+                                reinterpret_cast<uint32_t*>(b + off_rd) + lo,
+                                reinterpret_cast<uint8_t*>(b + off_w) + lo, hi - lo,
+                                want_counts ? reinterpret_cast<uint64_t*>(b + off_cnt) + lo
+                                            : nullptr,
+                                d_total, depth, opts, opts && opts->kernel_ms_out ? &ms_part
+                                                                                  : nullptr);
+                if (rc != NQ_OK) return rc;
+                ms += ms_part;
+            }
+        } else {
+            rc = run_device(n, reinterpret_cast<uint32_t*>(b),
+                            reinterpret_cast<uint32_t*>(b + off_ld),
+                            reinterpret_cast<uint32_t*>(b + off_rd),
+                            reinterpret_cast<uint8_t*>(b + off_w), F,
+                            want_counts ? reinterpret_cast<uint64_t*>(b + off_cnt) : nullptr,
+                            d_total, depth, opts, opts && opts->kernel_ms_out ? &ms : nullptr);
+            if (rc != NQ_OK) return rc;
+        }
+        uint64_t total = 0;
+        NQ_HIP(hipMemcpyAsync(&total, d_total, 8, hipMemcpyDeviceToHost, s));
+        if (want_counts && F)
+            NQ_HIP(hipMemcpyAsync(opts->counts_out, b + off_cnt, F * 8, hipMemcpyDeviceToHost, s));
+        NQ_HIP(hipStreamSynchronize(s));
+        if (want_counts)
+            for (uint64_t i = 0; i < F; ++i)
+                if (opts->counts_out[i] == kCountInvalid) return NQ_EINVAL;
+        if (opts && opts->kernel_ms_out) *opts->kernel_ms_out = ms;
+        *out_total = total;
+        return NQ_OK;
+    } catch (const std::bad_alloc&) {
+        return NQ_ENOMEM;
+    } catch (...) {
+        return NQ_EINVAL;
+    }
+}
+
+extern "C" int nq_count_batch(uint32_t ninst, const uint32_t* ns, const uint32_t* depths,
+                              const nq_opts* opts, uint64_t* out_totals) {
+    (void)ninst; (void)ns; (void)depths; (void)opts; (void)out_totals;
+    return NQ_EINVAL;
+}

@@ -1,0 +1,321 @@
+// DFS kernels for gfx950 (CDNA4, wave64).
+//
+// One lane of a 64-wide wavefront owns one subproblem at a time and searches
+// its subtree with the iterative DFS of Algorithm 2 (Section 2), using the
+// merged last-row step of Algorithm 3 (Section 3.2.3 / Section 4.3): the free
+// squares of row N-1 are counted with a popcount and never pushed.
+//
+// Lane state.  The frame being expanded -- (cols, ld, rd, avail) -- lives in
+// VGPRs.  Ancestors that still have untried columns are kept in LDS; an
+// ancestor with no untried column is never stored, so a pop always lands on a
+// frame with work and every loop trip places exactly one queen (one DFS node).
+//
+// LDS layout (the bank-conflict-free stack of Section 3.1, re-derived for a
+// 64-lane wave and 16-byte frames): wave w of a workgroup owns
+// frames * 64 * 16 bytes; frame f of lane l is the uint4 at index
+// (w * frames + f) * 64 + l.  A wave-wide ds_write_b128 / ds_read_b128 touches
+// one 16-byte slot per lane, and the slot's bank offset depends on l only
+// (f * 64 * 16 bytes is a multiple of every bank-row size), so lanes at
+// different depths never collide.
+//
+// Scheduling.  Plain mode: lane i of the grid takes entry i and idles once its
+// subtree is done.  Persistent mode: a resident grid; every `refill_every` DFS
+// steps each wave ballots its idle lanes, claims that many entries with one
+// atomic add on a global head, and hands them out by rank (mbcnt), so the
+// idle lanes read consecutive entries with coalesced loads.
+#include <hip/hip_runtime.h>
+
+#include "nq_internal.h"
+
+namespace nqi {
+
+namespace {
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+    uint32_t lo = __shfl((int)(uint32_t)v, src, 64);
+    uint32_t hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
+    uint32_t lo = __shfl_xor((int)(uint32_t)v, mask, 64);
+    uint32_t hi = __shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+}  // namespace
+
+// Per-lane state of the search.  `top` and `floor` are LDS byte offsets into
+// the lane's column of the wave's stack region; the frame at `floor` is a
+// sentinel (cols = the full board, avail = 0).  Popping it leaves the lane in
+// a state in which every later step is a no-op: no free column, no free square
+// below, and the stack pointer pinned at the sentinel.  So "avail == 0 after a
+// step" means "subtree finished", with no per-lane loop exit.
+//
+// Leaf test.  With LEAFCTR the bits of `cols` above the board hold a row
+// counter, advanced by the same add that places the queen; it is started so
+// that bit 31 becomes set exactly when the queen just placed fills row N-2 (the
+// next row is the last one).  The test is then a sign check instead of a
+// popcount.  It needs N - 1 - placed <= 2^(31 - N) (always true for N <= 26);
+// otherwise the popcount form of Algorithm 3 is used.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u32x4 lds_frame;
+
+// A frame addressed by its absolute LDS byte address.
+__device__ __forceinline__ lds_frame* frame_at(int32_t addr) {
+    return (lds_frame*)(uintptr_t)(uint32_t)addr;
+}
+
+template <bool PERSISTENT, bool STATS, bool LEAFCTR>
+__global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
+    extern __shared__ uint4 lds_stack[];
+    const int32_t lds = (int32_t)(uint32_t)(uintptr_t)(lds_frame*)lds_stack;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    const int32_t floor = lds + (int32_t)(((wave * (P.frames + 1u)) * 64u + lane) * 16u);
+    int32_t top = floor;
+    *frame_at(floor) = u32x4{0u, 0u, 0u, 0u};
+
+    uint32_t c = 0, l = 0, r = 0, v = 0, last = 0, nm1 = 0, step_k = 0;
+    uint64_t idx = 0;
+    uint32_t sum32 = 0, steps32 = 0;
+    uint64_t sum64 = 0, steps64 = 0;
+    uint64_t wtotal = 0;                  // weighted total, single-instance launches
+    bool has_task = false;                // holds an entry not yet retired
+    bool exhausted = !PERSISTENT;         // no entries left to claim (wave-uniform)
+
+    // Takes entry `i`: loads its triple, writes the sentinel and settles the
+    // cases that need no search (a full board, the last row, no free square).
+    auto take = [&](uint64_t i) {
+        idx = i;
+        const uint32_t n = P.inst ? P.inst_n[P.inst[i]] : P.n;
+        last = (1u << n) - 1u;
+        nm1 = n - 1u;
+        c = P.cols[i] & last;
+        l = P.ld[i] & last;
+        r = P.rd[i] & last;
+        v = 0u;
+        top = floor;
+        sum32 = 0; sum64 = 0; steps32 = 0; steps64 = 0;
+        has_task = true;
+        const uint32_t placed = __popc(c);
+        const uint32_t avail = last & ~(c | l | r);
+        *frame_at(floor) = u32x4{last, 0u, 0u, 0u};
+        if (placed >= nm1) {
+            sum32 = (placed == n) ? 1u : __popc(avail);
+        } else if (n - 2u - placed > P.frames ||
+                   (LEAFCTR && nm1 - placed > (1u << (31u - n)))) {
+            sum64 = kCountInvalid;        // does not fit this launch's stack or counter
+        } else if (avail != 0u) {
+            v = avail;
+            if (LEAFCTR) {
+                step_k = 1u << n;
+                c |= ((1u << (31u - n)) - (nm1 - placed)) << n;
+            }
+        }
+        if (v == 0u) c = last;            // nothing to search: park on the sentinel state
+    };
+
+    if (!PERSISTENT) {
+        const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (i < P.len) take(i);
+    }
+
+    for (;;) {
+        // ---- scheduler visit: flush counters, retire finished lanes, refill.
+        sum64 += sum32; sum32 = 0;
+        if (STATS) { steps64 += steps32; steps32 = 0; }
+        if (has_task && v == 0u) {
+            const bool ok = sum64 != kCountInvalid;
+            if (P.counts) P.counts[idx] = sum64;
+            if (STATS) P.nodes[idx] = steps64;
+            if (P.totals && ok && sum64 != 0) {
+                const uint64_t w = P.weight ? (uint64_t)P.weight[idx] : 1u;
+                if (P.inst)
+                    atomicAdd(&P.totals[P.inst[idx]], (unsigned long long)(w * sum64));
+                else
+                    wtotal += w * sum64;
+            }
+            has_task = false;
+        }
+        if (PERSISTENT && !exhausted) {
+            const uint64_t idle = __ballot(!has_task);
+            if (idle != 0) {
+                const uint32_t want = (uint32_t)__popcll(idle);
+                const int leader = __ffsll((unsigned long long)idle) - 1;
+                uint64_t first = 0;
+                if ((int)lane == leader) first = atomicAdd(P.head, (unsigned long long)want);
+                first = shfl_u64(first, leader);
+                if (!has_task) {
+                    const uint64_t i = first + lane_rank(idle);
+                    if (i < P.len) take(i);
+                }
+                if (first + want >= P.len) exhausted = true;
+            }
+        }
+        if (!__any(v != 0u)) {
+            if (exhausted && !__any(has_task)) break;
+            continue;
+        }
+
+        // ---- DFS steps (Algorithm 2 with the Algorithm 3 last-row step).
+        // The frame is kept as one 4-vector so that push and pop move it with
+        // a single ds_write_b128 / ds_read_b128 and no register shuffling.
+        u32x4 st = {c, l, r, v};
+        for (uint32_t it = 0; it < P.refill_every; ++it) {
+            const uint32_t p = st.w & (0u - st.w);    // lowest untried column
+            st.w ^= p;
+            // p is free in this frame, so OR and ADD agree on c, l and r.
+            const uint32_t nc = LEAFCTR ? st.x + p + step_k : (st.x | p);
+            const uint32_t nl = (st.y + p) << 1;
+            const uint32_t nr = (st.z + p) >> 1;
+            const uint32_t a = last & ~(nc | nl | nr); // free squares of the next row
+            if (STATS) steps32 += (p != 0u);
+            const bool leaf = LEAFCTR ? (int32_t)nc < 0 : __popc(nc) == nm1;
+            const bool any = a != 0u;
+            sum32 += (leaf && any) ? 1u : 0u;         // the last row has one column left
+            const bool desc = any && !leaf;
+            if (desc && st.w != 0u) {                 // keep the parent only if it has work
+                top += 1024;
+                *frame_at(top) = st;
+            }
+            st.x = desc ? nc : st.x;
+            st.y = desc ? nl : st.y;
+            st.z = desc ? nr : st.z;
+            st.w = desc ? a : st.w;
+            if (st.w == 0u) {                         // frame exhausted: pop
+                st = *frame_at(top);
+                top = max(top - 1024, floor);
+            }
+        }
+        c = st.x; l = st.y; r = st.z; v = st.w;
+    }
+
+    if (P.totals && !P.inst) {
+        for (int off = 32; off > 0; off >>= 1) wtotal += shfl_xor_u64(wtotal, off);
+        if (lane == 0 && wtotal != 0) atomicAdd(&P.totals[0], (unsigned long long)wtotal);
+    }
+}
+
+__global__ void nq_zero_u64_kernel(unsigned long long* dst, uint64_t count) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = 0ull;
+}
+
+template <bool PERSISTENT, bool STATS, bool LEAFCTR>
+static const void* kernel_ptr() {
+    return reinterpret_cast<const void*>(&nq_dfs_kernel<PERSISTENT, STATS, LEAFCTR>);
+}
+
+static const void* select_kernel(uint32_t mode, bool stats, bool leafctr) {
+    const bool pers = mode == NQ_MODE_PERSISTENT;
+    if (pers) {
+        if (stats) return leafctr ? kernel_ptr<true, true, true>() : kernel_ptr<true, true, false>();
+        return leafctr ? kernel_ptr<true, false, true>() : kernel_ptr<true, false, false>();
+    }
+    if (stats) return leafctr ? kernel_ptr<false, true, true>() : kernel_ptr<false, true, false>();
+    return leafctr ? kernel_ptr<false, false, true>() : kernel_ptr<false, false, false>();
+}
+
+int device_info(DeviceInfo* out) {
+    static thread_local DeviceInfo cache[64];
+    static thread_local bool have[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
+    if (dev >= 0 && dev < 64 && have[dev]) { *out = cache[dev]; return NQ_OK; }
+    DeviceInfo d{};
+    d.device = dev;
+    int v = 0;
+    if ((e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) {
+        set_hip_error(e); return NQ_EDEVICE;
+    }
+    d.cu_count = v;
+    if ((e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev)) !=
+        hipSuccess) {
+        set_hip_error(e); return NQ_EDEVICE;
+    }
+    d.lds_per_cu = v;
+    if ((e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) !=
+        hipSuccess) {
+        set_hip_error(e); return NQ_EDEVICE;
+    }
+    d.lds_per_block = v;
+    d.max_waves_per_cu = 32;
+    if (dev >= 0 && dev < 64) { cache[dev] = d; have[dev] = true; }
+    *out = d;
+    return NQ_OK;
+}
+
+int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t waves_per_cu,
+                uint32_t frames, uint64_t len, bool stats, bool leafctr, LaunchCfg* cfg) {
+    if (mode != NQ_MODE_PLAIN && mode != NQ_MODE_PERSISTENT) return NQ_EINVAL;
+    if (wg_size == 0) {
+        // Plain: up to 4 waves per workgroup, as many as the LDS stacks allow.
+        const uint64_t per_wave = 64ull * (frames + 1u) * 16u;
+        const uint64_t fit = per_wave ? (uint64_t)dev.lds_per_block / per_wave : 4;
+        wg_size = (mode == NQ_MODE_PLAIN) ? 64u * (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(4, fit))
+                                          : 64u;
+    }
+    if (wg_size % 64u != 0 || wg_size > 1024u) return NQ_EINVAL;
+    // One sentinel frame per lane below its stack.
+    const uint64_t lds = (uint64_t)wg_size * (frames + 1u) * 16u;
+    if (lds > (uint64_t)dev.lds_per_block) return NQ_EINVAL;
+    cfg->mode = mode;
+    cfg->wg_size = wg_size;
+    cfg->lds_bytes = (uint32_t)lds;
+    cfg->stats = stats;
+    cfg->leafctr = leafctr;
+    if (mode == NQ_MODE_PLAIN) {
+        const uint64_t g = (len + wg_size - 1) / wg_size;
+        if (g > 0x7fffffffull) return NQ_EINVAL;
+        cfg->grid = (uint32_t)g;
+        return NQ_OK;
+    }
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, select_kernel(mode, stats, cfg->leafctr), (int)wg_size, (size_t)lds);
+    if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
+    if (per_cu < 1) return NQ_EINVAL;
+    if (waves_per_cu) {
+        const uint32_t want = std::max(1u, waves_per_cu / (wg_size / 64u));
+        per_cu = std::min(per_cu, (int)want);
+    }
+    cfg->grid = (uint32_t)per_cu * (uint32_t)dev.cu_count;
+    return NQ_OK;
+}
+
+int launch_zero_u64(unsigned long long* dst, uint64_t count, void* stream) {
+    if (count == 0) return NQ_OK;
+    const uint32_t block = 256;
+    const uint64_t grid = (count + block - 1) / block;
+    hipLaunchKernelGGL(nq_zero_u64_kernel, dim3((uint32_t)grid), dim3(block), 0,
+                       (hipStream_t)stream, dst, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
+    return NQ_OK;
+}
+
+int launch_dfs(const LaunchCfg& cfg, const DfsParams& P, void* stream) {
+    if (P.len == 0 || cfg.grid == 0) return NQ_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (cfg.mode == NQ_MODE_PERSISTENT) {
+        int rc = launch_zero_u64(P.head, 1, stream);
+        if (rc != NQ_OK) return rc;
+    }
+    const dim3 grid(cfg.grid), block(cfg.wg_size);
+    const void* fn = select_kernel(cfg.mode, cfg.stats, cfg.leafctr);
+    void* args[] = {const_cast<DfsParams*>(&P)};
+    hipError_t le = hipLaunchKernel(fn, grid, block, args, cfg.lds_bytes, s);
+    if (le != hipSuccess) { set_hip_error(le); return NQ_EDEVICE; }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
+    return NQ_OK;
+}
+
+}  // namespace nqi

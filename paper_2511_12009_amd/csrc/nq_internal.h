@@ -1,0 +1,102 @@
+// Internal declarations shared by the host-side translation units of libnq.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/nq.h"
+
+namespace nqi {
+
+// One starting point of the frontier enumeration: the Somers triple after the
+// first `row` rows, the rows still to place before the frontier depth, the
+// weight every entry below it carries, and its row-0 column.
+struct Root {
+    uint32_t cols, ld, rd;
+    int row;
+    int rows_left;
+    uint8_t weight;
+    uint32_t first_col;
+};
+
+std::vector<Root> frontier_roots(uint32_t n, uint32_t depth);
+uint64_t root_size(uint32_t n, const Root& rt);
+std::vector<uint64_t> root_offsets(uint32_t n, const std::vector<Root>& roots);
+
+// nq_frontier's body.  `first_row_offsets`, when set, receives the start of
+// each row-0 column's run of entries followed by the total.
+int frontier_fill(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld, uint32_t* rd,
+                  uint8_t* weight, uint64_t capacity, uint64_t* out_len,
+                  std::vector<uint64_t>* first_row_offsets);
+
+// Arguments of the DFS kernels (passed by value).
+struct DfsParams {
+    const uint32_t* cols;           // Somers triples, device
+    const uint32_t* ld;
+    const uint32_t* rd;
+    const uint8_t* weight;          // nullable: weight 1
+    const uint32_t* inst;           // nullable: every entry belongs to instance 0
+    const uint32_t* inst_n;         // board size per instance (when inst != nullptr)
+    uint64_t* counts;               // nullable: unweighted count per entry
+    unsigned long long* totals;     // nullable: weighted total per instance (accumulated)
+    uint64_t* nodes;                // stats kernels only: DFS steps per entry
+    unsigned long long* head;       // persistent kernels: next unclaimed entry
+    uint64_t len;                   // entries
+    uint32_t n;                     // board size when inst == nullptr
+    uint32_t frames;                // LDS stack frames per lane
+    uint32_t refill_every;          // DFS steps between scheduler visits
+    uint32_t pad;
+};
+
+// Count reported for an entry that needs more stack frames than the launch has.
+constexpr uint64_t kCountInvalid = ~0ull;
+
+struct LaunchCfg {
+    uint32_t mode;          // NQ_MODE_PLAIN or NQ_MODE_PERSISTENT
+    uint32_t wg_size;       // threads per workgroup
+    uint32_t grid;          // workgroups
+    uint32_t lds_bytes;     // dynamic LDS per workgroup
+    bool stats;             // count DFS steps per entry
+    bool leafctr;           // row counter in the high bits of cols (see the kernel)
+};
+
+// True when the row-counter form of the leaf test holds for every entry of an
+// n board with at least `min_placed` queens placed: the counter needs
+// n - 1 - placed <= 2^(31 - n).
+inline bool leafctr_ok(uint32_t n, uint32_t min_placed) {
+    if (n > 30) return false;
+    const uint32_t rows = (n > min_placed + 1) ? n - 1 - min_placed : 0u;
+    return rows <= (1u << (31u - n));
+}
+
+// Device properties used for launch shapes.
+struct DeviceInfo {
+    int device;
+    int cu_count;
+    int lds_per_cu;
+    int lds_per_block;
+    int max_waves_per_cu;
+};
+
+int device_info(DeviceInfo* out);
+
+// Fills `cfg` for `len` entries needing `frames` frames per lane.
+int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t waves_per_cu,
+                uint32_t frames, uint64_t len, bool stats, bool leafctr, LaunchCfg* cfg);
+
+// Enqueues the DFS kernel (and, for the persistent mode, the zeroing of
+// *P.head) on `stream`.  Returns NQ_OK or NQ_EDEVICE.
+int launch_dfs(const LaunchCfg& cfg, const DfsParams& P, void* stream);
+
+// Enqueues dst[0..count) = 0 with a kernel (no memset node in captured graphs).
+int launch_zero_u64(unsigned long long* dst, uint64_t count, void* stream);
+
+// Records a failing hipError_t for nq_last_hip_error().
+void set_hip_error(int err);
+
+// Frames per lane needed by a subproblem with `placed` queens on an n board.
+inline uint32_t frames_needed(uint32_t n, uint32_t placed) {
+    return (n >= placed + 2) ? (n - 2 - placed) : 0u;
+}
+
+}  // namespace nqi

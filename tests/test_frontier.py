@@ -1,0 +1,110 @@
+"""Host side of the library (no GPU needed): the C-ABI loads, exports every
+declared symbol, and nq_frontier matches the oracle's frontier index by index."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2511_12009_amd as nq
+from conftest import ROOT, read_table
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "nq.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(nq_[a-z_0-9]+)\s*\(",
+                                 text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert "nq_frontier" in names and "nq_count" in names and len(names) >= 6
+    lib = ct.CDLL(nq.library_path)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_strerror_covers_every_status():
+    lib = nq.lib()
+    for st in range(0, -8, -1):
+        assert lib.nq_strerror(st).decode() not in ("", "unknown status")
+    assert lib.nq_strerror(-99).decode() == "unknown status"
+
+
+@pytest.mark.parametrize("n", range(1, 14))
+def test_frontier_matches_oracle_every_depth(n):
+    for k in range(0, n + 1):
+        cols, ld, rd, w = nq.frontier(n, k)
+        oc, ol, orr, ow = oracle.frontier_masks(n, k) if k else (None, None, None, None)
+        if k == 0:
+            assert list(cols) == [0] and list(w) == [1]
+            continue
+        assert len(cols) == len(oc) == oracle.frontier_size(n, k), (n, k)
+        np.testing.assert_array_equal(cols, oc)
+        np.testing.assert_array_equal(ld, ol)
+        np.testing.assert_array_equal(rd, orr)
+        np.testing.assert_array_equal(w, ow)
+
+
+@pytest.mark.parametrize("n,k", [(14, 3), (17, 5), (16, 6), (19, 4)])
+def test_frontier_matches_oracle_bench_shapes(n, k):
+    cols, ld, rd, w = nq.frontier(n, k)
+    oc, ol, orr, ow = oracle.frontier_masks(n, k)
+    np.testing.assert_array_equal(cols, oc)
+    np.testing.assert_array_equal(ld, ol)
+    np.testing.assert_array_equal(rd, orr)
+    np.testing.assert_array_equal(w, ow)
+
+
+def test_frontier_sizes_match_oracle():
+    for n, k in [(20, 5), (20, 6), (21, 6), (18, 5), (19, 5)]:
+        assert nq.frontier_size(n, k) == oracle.frontier_size(n, k)
+
+
+def test_frontier_27_7_size_matches_run_log():
+    for n, k, f in read_table("frontier_sizes.txt"):
+        assert nq.frontier_size(int(n), int(k)) == int(f)
+
+
+def test_frontier_partial_fill_reports_range():
+    lib = nq.lib()
+    n, k = 12, 4
+    full = nq.frontier(n, k)
+    cap = len(full[0]) // 3
+    c = np.zeros(cap, np.uint32)
+    l = np.zeros(cap, np.uint32)
+    r = np.zeros(cap, np.uint32)
+    w = np.zeros(cap, np.uint8)
+    ln = ct.c_uint64()
+    p = lambda a: a.ctypes.data_as(ct.POINTER(ct.c_uint32))  # noqa: E731
+    rc = lib.nq_frontier(n, k, p(c), p(l), p(r), w.ctypes.data_as(ct.POINTER(ct.c_uint8)),
+                         cap, ct.byref(ln))
+    assert rc == -2 and ln.value == len(full[0])
+    np.testing.assert_array_equal(c, full[0][:cap])
+    np.testing.assert_array_equal(l, full[1][:cap])
+    np.testing.assert_array_equal(r, full[2][:cap])
+    np.testing.assert_array_equal(w, full[3][:cap])
+
+
+def test_frontier_rejects_bad_arguments():
+    lib = nq.lib()
+    ln = ct.c_uint64()
+    assert lib.nq_frontier(0, 0, None, None, None, None, 0, ct.byref(ln)) == -1
+    assert lib.nq_frontier(29, 3, None, None, None, None, 0, ct.byref(ln)) == -1
+    assert lib.nq_frontier(8, 9, None, None, None, None, 0, ct.byref(ln)) == -1
+    assert lib.nq_frontier(8, 3, None, None, None, None, 0, None) == -1
+
+
+def test_count_entry_points_validate_before_touching_the_gpu():
+    lib = nq.lib()
+    out = ct.c_uint64()
+    assert lib.nq_count(0, None, ct.byref(out)) == -1
+    assert lib.nq_count(29, None, ct.byref(out)) == -1
+    assert lib.nq_count(8, None, None) == -1
+    assert lib.nq_count_subproblems(30, None, None, None, None, 5, None, None, None) == -1
+    assert lib.nq_count_subproblems(8, None, None, None, None, 5, None, None, None) == -1
+    # len == 0 is a valid empty call: nothing is launched
+    assert lib.nq_count_subproblems(8, None, None, None, None, 0, None, None, None) == 0

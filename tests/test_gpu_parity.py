@@ -1,0 +1,200 @@
+"""GPU parity: the HIP DFS kernels against the CPU oracle, bit for bit.
+
+Every expected value comes from the oracle (live, or stored by
+tests/golden/make_golden.py, which calls only the oracle) or from the published
+counts in tests/golden/known_counts.txt.  All calls go through the C-ABI.
+"""
+import hashlib
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import read_table
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _nq():
+    import paper_2511_12009_amd as nq
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return nq
+
+
+def _say(*a):
+    print("[gpu-parity]", *a, flush=True)
+
+
+def _golden_runs():
+    return {(int(r[0]), int(r[1])): r for r in read_table("oracle_runs.txt")}
+
+
+def _digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<u8").tobytes()).hexdigest()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def _triples_from_prefixes(n, prefixes):
+    c, l, r = oracle.prefixes_masks(n, prefixes)
+    return _dev(c), _dev(l), _dev(r)
+
+
+@pytest.mark.parametrize("mode", ["plain", "persistent"])
+def test_small_boards_every_depth(mode, known_counts):
+    nq = _nq()
+    for n in range(1, 13):
+        for k in range(1, n + 1):
+            _say("count", n, k, mode)
+            assert nq.count(n, depth=k, mode=mode) == known_counts[n], (n, k, mode)
+
+
+@pytest.mark.parametrize("mode", ["plain", "persistent"])
+def test_n14_depth3_per_subproblem(mode):
+    nq = _nq()
+    _say("n14 k3", mode)
+    total, counts = nq.count(14, depth=3, mode=mode, counts=True)
+    pre, w = oracle.frontier(14, 3)
+    ref, _ = oracle.count_prefixes(14, pre, threads=8)
+    assert total == 365596
+    np.testing.assert_array_equal(counts, ref)
+
+
+def test_n17_depth5_persistent_per_subproblem():
+    nq = _nq()
+    n, k = 17, 5
+    _say("n17 k5 persistent")
+    total, counts = nq.count(n, depth=k, mode="persistent", counts=True)
+    g = _golden_runs()[(n, k)]
+    assert len(counts) == int(g[2])
+    assert total == int(g[3]) == 95815104
+    assert _digest(counts) == g[5]
+    # a seeded sample re-counted live by the oracle, element by element
+    pre, _ = oracle.frontier(n, k)
+    idx = np.random.default_rng(17).choice(len(pre), 200, replace=False)
+    ref, _ = oracle.count_prefixes(n, pre[idx], threads=8)
+    np.testing.assert_array_equal(counts[idx], ref)
+
+
+def test_count_subproblems_random_prefixes():
+    """Random legal prefixes of every depth, including dead ones and k = n-1, n."""
+    nq = _nq()
+    rng = np.random.default_rng(2511)
+    for n in [4, 5, 8, 11, 13, 15, 16]:
+        for k in sorted({1, 2, n // 2, max(1, n - 3), n - 1, n}):
+            pre_all, _ = oracle.frontier(n, k)
+            if len(pre_all) == 0:
+                continue
+            take = rng.choice(len(pre_all), min(300, len(pre_all)), replace=False)
+            pre = pre_all[np.sort(take)]
+            c, l, r = _triples_from_prefixes(n, pre)
+            ref, _ = oracle.count_prefixes(n, pre, threads=8)
+            for mode in ("plain", "persistent"):
+                _say("subproblems", n, k, mode, len(pre))
+                counts, total = nq.count_subproblems(n, c, l, r, depth=k, mode=mode)
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(counts.cpu().numpy().view(np.uint64), ref)
+                assert int(total.item()) == int(ref.sum())
+
+
+def test_weights_and_accumulating_total():
+    nq = _nq()
+    n, k = 12, 4
+    pre, w = oracle.frontier(n, k)
+    c, l, r = _triples_from_prefixes(n, pre)
+    tw = torch.from_numpy(w).cuda()
+    total = torch.full((1,), 5, dtype=torch.int64, device="cuda")
+    _say("weights", n, k)
+    nq.count_subproblems(n, c, l, r, weight=tw, total=total, depth=k)
+    torch.cuda.synchronize()
+    assert int(total.item()) == 5 + 14200
+
+
+def test_large_boards_deep_prefixes():
+    """n = 24..28 with deep prefixes: the popcount leaf test and the widest masks."""
+    nq = _nq()
+    rng = np.random.default_rng(28)
+    for n in [24, 26, 27, 28]:
+        k = n - 7
+        pre = []
+        while len(pre) < 64:
+            p = []
+            for row in range(k):
+                opts = [j for j in range(n)
+                        if all(p[i] != j and abs(p[i] - j) != row - i for i in range(row))]
+                if not opts:
+                    break
+                p.append(int(rng.choice(opts)))
+            if len(p) == k:
+                pre.append(p)
+        pre = np.array(pre, dtype=np.int32)
+        c, l, r = _triples_from_prefixes(n, pre)
+        ref, _ = oracle.count_prefixes(n, pre, threads=8)
+        for depth in (k, 0):               # depth 0: no promise, deepest stack
+            _say("large", n, k, "depth", depth)
+            counts, total = nq.count_subproblems(n, c, l, r, depth=depth)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(counts.cpu().numpy().view(np.uint64), ref)
+
+
+def test_mirror_images_count_the_same():
+    nq = _nq()
+    n, k = 16, 5
+    pre, _ = oracle.frontier(n, k)
+    mir = (n - 1 - pre).astype(np.int32)
+    c, l, r = _triples_from_prefixes(n, pre)
+    mc, ml, mr = _triples_from_prefixes(n, mir)
+    _say("mirror", n, k)
+    a, _ = nq.count_subproblems(n, c, l, r, depth=k)
+    b, _ = nq.count_subproblems(n, mc, ml, mr, depth=k)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_entries_deeper_than_the_promise_are_rejected():
+    nq = _nq()
+    n = 12
+    pre_deep, _ = oracle.frontier(n, 6)
+    pre_shallow, _ = oracle.frontier(n, 2)
+    c1, l1, r1 = _triples_from_prefixes(n, pre_deep[:50])
+    c2, l2, r2 = _triples_from_prefixes(n, pre_shallow[:5])
+    c, l, r = torch.cat([c1, c2]), torch.cat([l1, l2]), torch.cat([r1, r2])
+    ref, _ = oracle.count_prefixes(n, pre_deep[:50])
+    _say("promise", n)
+    counts, total = nq.count_subproblems(n, c, l, r, depth=6)
+    torch.cuda.synchronize()
+    got = counts.cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(got[:50], ref)
+    assert (got[50:] == np.uint64(0xFFFFFFFFFFFFFFFF)).all()
+    assert int(total.item()) == int(ref.sum())
+
+
+def test_empty_inputs():
+    nq = _nq()
+    z = torch.zeros(0, dtype=torch.int32, device="cuda")
+    counts, total = nq.count_subproblems(10, z, z, z)
+    torch.cuda.synchronize()
+    assert counts.numel() == 0 and int(total.item()) == 0
+    assert nq.count(2, depth=2) == 0 and nq.count(3, depth=3) == 0
+
+
+def test_n20_bench_shape():
+    """The N=20 counts at depth 6 in both modes, plus a live per-entry sample."""
+    nq = _nq()
+    n, k = 20, 6
+    for mode in ("persistent", "plain"):
+        _say("n20 k6", mode)
+        total, counts = nq.count(n, depth=k, mode=mode, counts=True)
+        assert total == 39029188884, mode
+        g = _golden_runs().get((n, k))
+        if g is not None:
+            assert _digest(counts) == g[5]
+        pre, _ = oracle.frontier(n, k)
+        idx = np.random.default_rng(20).choice(len(pre), 48, replace=False)
+        ref, _ = oracle.count_prefixes(n, pre[idx], threads=16)
+        np.testing.assert_array_equal(counts[idx], ref)
