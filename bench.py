@@ -36,32 +36,20 @@ INT_PEAK = 256 * 4 * 16 * 2.4e9
 
 
 def golden_nodes(n, k):
-    path = os.path.join(ROOT, "tests", "golden", "oracle_runs.txt")
-    with open(path) as f:
-        for line in f:
-            if line.startswith("#") or not line.strip():
-                continue
-            r = line.split()
-            if int(r[0]) == n and int(r[1]) == k:
-                return int(r[4]), int(r[3])
-    return None, None
-
-
-def oracle_nodes_at_depth(n, k):
-    """nodes(n, k) from a stored oracle run at another depth (even n):
-    nodes(k) = nodes(j) + F(k+1) + ... + F(j) for k < j, and the reverse."""
-    import oracle
-    for j in (k, 6, 5, 7):
-        nd, _ = golden_nodes(n, j)
-        if nd is None:
+    """nodes(n, k) stored by tests/golden/make_golden.py (oracle runs, and for even n
+    the other depths derived from them with the node identity), or None."""
+    for name in ("oracle_runs.txt", "oracle_nodes.txt"):
+        path = os.path.join(ROOT, "tests", "golden", name)
+        if not os.path.exists(path):
             continue
-        if j == k:
-            return nd, "oracle"
-        if n % 2 == 0:
-            if k < j:
-                return nd + sum(oracle.frontier_size(n, d) for d in range(k + 1, j + 1)), "oracle"
-            return nd - sum(oracle.frontier_size(n, d) for d in range(j + 1, k + 1)), "oracle"
-    return None, None
+        with open(path) as f:
+            for line in f:
+                if line.startswith("#") or not line.strip():
+                    continue
+                r = line.split()
+                if int(r[0]) == n and int(r[1]) == k:
+                    return int(r[4] if name == "oracle_runs.txt" else r[2])
+    return None
 
 
 def cpu_baseline(k, budget_s):
@@ -97,6 +85,7 @@ def main():
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
+    ap.add_argument("--forward", action="store_true", help="claim entries in frontier order")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -123,12 +112,21 @@ def main():
     host_total = torch.zeros(1, dtype=torch.int64).pin_memory()
     stream = torch.cuda.current_stream()
     kw = dict(depth=k, wg_size=args.wg, waves_per_cu=args.waves_per_cu,
-              refill_every=args.refill)
+              refill_every=args.refill, forward=args.forward)
+
+    runs = nq.frontier_runs(N, k)
 
     def step(mode):
         total.zero_()
-        nq.count_subproblems(N, t_cols, t_ld, t_rd, weight=t_w, counts=counts, total=total,
-                             mode=mode, stream=stream, **kw)
+        if mode == "plain":
+            # one launch per row-0 column, each over its run of the frontier
+            for lo, hi in zip(runs[:-1], runs[1:]):
+                nq.count_subproblems(N, t_cols[lo:hi], t_ld[lo:hi], t_rd[lo:hi],
+                                     weight=t_w[lo:hi], counts=counts[lo:hi], total=total,
+                                     mode=mode, stream=stream, **kw)
+        else:
+            nq.count_subproblems(N, t_cols, t_ld, t_rd, weight=t_w, counts=counts, total=total,
+                                 mode=mode, stream=stream, **kw)
         host_total.copy_(total, non_blocking=True)
 
     def timed(mode, steps, warmup):
@@ -165,7 +163,8 @@ def main():
     if e2e_total != EXPECT:
         raise SystemExit(f"bench.py: nq_count total {e2e_total} != {EXPECT}")
 
-    nodes, src = oracle_nodes_at_depth(N, k)
+    nodes = golden_nodes(N, k)
+    src = "oracle (tests/golden)" if nodes else None
     kern_ms = float(np.mean(ev_ms))
     out = {
         "metric": "DFS nodes/s (N=20 count, 1 MI355X, batched persistent launch, bit-exact)",

@@ -81,12 +81,34 @@ int nq_last_hip_error(void);
 int nq_frontier(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld, uint32_t* rd,
                 uint8_t* weight, uint64_t capacity, uint64_t* out_len);
 
+/*
+ * nq_frontier_runs -- where each row-0 column's entries start in the frontier.
+ *
+ * The frontier of (n, depth) is ordered by the row-0 column first, so the
+ * entries of each row-0 column (and, for odd n, of the centre column) form one
+ * contiguous run.  Writes the start offset of every run followed by F, i.e.
+ * runs + 1 values, into offsets (capacity >= runs + 1) and *out_runs = runs.
+ * With offsets == NULL only *out_runs is written.  n in [1, 28], depth in
+ * [1, n]; host only.
+ */
+int nq_frontier_runs(uint32_t n, uint32_t depth, uint64_t* offsets, uint32_t capacity,
+                     uint32_t* out_runs);
+
 /* Scheduling modes of the DFS kernels. */
 enum nq_mode {
     NQ_MODE_AUTO = 0,        /* persistent                                            */
     NQ_MODE_PLAIN = 1,       /* one lane per subproblem, grid = ceil(F / wg_size)     */
     NQ_MODE_PERSISTENT = 2   /* resident grid, lanes refilled from an atomic queue    */
 };
+
+/* Option flags. */
+enum nq_flags {
+    /* Persistent mode hands entries out in frontier order instead of the
+     * default reverse order (the last row-0 columns carry the largest subtrees,
+     * Section 4.5, so reverse order starts the longest work first). */
+    NQ_FLAG_FORWARD_ORDER = 1u
+};
+#define NQ_FLAGS_ALL 1u
 
 /*
  * Options shared by the counting entry points.  A NULL options pointer, or a
@@ -98,7 +120,7 @@ typedef struct nq_opts {
     uint32_t wg_size;        /* threads per workgroup, multiple of 64, <= 1024         */
     uint32_t waves_per_cu;   /* persistent grid: resident waves per CU (0 = max fit)   */
     uint32_t refill_every;   /* DFS steps between refill checks (0 = default)          */
-    uint32_t reserved;       /* must be 0                                              */
+    uint32_t flags;          /* NQ_FLAG_* bits; unknown bits are NQ_EINVAL             */
     void* stream;            /* hipStream_t to run on; NULL = the null stream          */
     uint64_t* counts_out;    /* nq_count: optional host buffer, F unweighted counts    */
     uint64_t counts_capacity;/* length of counts_out                                   */
@@ -148,10 +170,32 @@ int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const uint32_t* d_l
  * depths[i] when depths != NULL, else opts->depth or automatic), concatenates
  * them with per-entry instance ids, runs one persistent DFS launch (captured
  * and replayed as a HIP graph) and writes Q(ns[i]) to out_totals[i].
- * Synchronous.  Every ns[i] in [1, 28].
+ * Synchronous.  Every ns[i] in [1, 28]; ninst == 0 does nothing.
  */
 int nq_count_batch(uint32_t ninst, const uint32_t* ns, const uint32_t* depths,
                    const nq_opts* opts, uint64_t* out_totals);
+
+/*
+ * Reusable batch plan: nq_count_batch split into set-up and replay.
+ *
+ * nq_batch_create builds and uploads the concatenated frontiers of ninst >= 1
+ * instances (as nq_count_batch; depths[i] in [1, ns[i]] or NULL for
+ * min(opts->depth or 5, ns[i] - 2), at least 1), allocates every device and
+ * pinned host buffer the launch needs, and captures one HIP graph: zero the
+ * totals, zero the work head, the persistent DFS kernel, copy the totals to
+ * the host.  The plan owns a private stream.  nq_batch_run replays the graph,
+ * waits for it and writes the ninst totals; kernel_ms (nullable) receives the
+ * device time of the replay.  nq_batch_entries gives the number of concatenated
+ * subproblems.  nq_batch_destroy waits for the plan's stream and frees
+ * everything.  A plan may be replayed any number of times; replays of one plan
+ * must not overlap (calls on one plan are not thread-safe).
+ */
+typedef struct nq_batch nq_batch;
+int nq_batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths,
+                    const nq_opts* opts, nq_batch** out);
+int nq_batch_run(nq_batch* batch, uint64_t* out_totals, double* kernel_ms);
+uint64_t nq_batch_entries(const nq_batch* batch);
+int nq_batch_destroy(nq_batch* batch);
 
 #ifdef __cplusplus
 }

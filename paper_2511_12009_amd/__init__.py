@@ -9,17 +9,21 @@ binding without it raises ``NQError``.
 Functions (same names as the C entry points, without the ``nq_`` prefix):
   frontier(n, depth)                         -> (cols, ld, rd, weight) numpy arrays
   frontier_size(n, depth)                    -> F
+  frontier_runs(n, depth)                    -> start of each row-0 column's entries, then F
   count(n, depth=0, mode="persistent", ...)  -> Q(n)   (and counts / kernel ms)
   count_subproblems(n, cols, ld, rd, ...)    -> per-entry counts and weighted total
   count_batch(ns, depths=None, ...)          -> [Q(n) for n in ns]
+  Batch(ns, depths=None).run()               -> replayable batch plan (HIP graph)
 """
 from ._native import (  # noqa: F401
+    Batch,
     NQError,
     MODES,
     count,
     count_batch,
     count_subproblems,
     frontier,
+    frontier_runs,
     frontier_size,
     lib,
     library_path,

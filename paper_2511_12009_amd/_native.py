@@ -30,7 +30,7 @@ class NqOpts(ct.Structure):
         ("wg_size", ct.c_uint32),
         ("waves_per_cu", ct.c_uint32),
         ("refill_every", ct.c_uint32),
-        ("reserved", ct.c_uint32),
+        ("flags", ct.c_uint32),
         ("stream", ct.c_void_p),
         ("counts_out", ct.POINTER(ct.c_uint64)),
         ("counts_capacity", ct.c_uint64),
@@ -58,12 +58,22 @@ def lib():
         L.nq_last_hip_error.restype = ct.c_int
         L.nq_frontier.argtypes = [u32, u32, pu32, pu32, pu32, pu8, u64, pu64]
         L.nq_frontier.restype = ct.c_int
+        L.nq_frontier_runs.argtypes = [u32, u32, pu64, u32, pu32]
+        L.nq_frontier_runs.restype = ct.c_int
         L.nq_count.argtypes = [u32, ct.POINTER(NqOpts), pu64]
         L.nq_count.restype = ct.c_int
         L.nq_count_subproblems.argtypes = [u32, vp, vp, vp, vp, u64, vp, vp, ct.POINTER(NqOpts)]
         L.nq_count_subproblems.restype = ct.c_int
         L.nq_count_batch.argtypes = [u32, pu32, pu32, ct.POINTER(NqOpts), pu64]
         L.nq_count_batch.restype = ct.c_int
+        L.nq_batch_create.argtypes = [u32, pu32, pu32, ct.POINTER(NqOpts), ct.POINTER(vp)]
+        L.nq_batch_create.restype = ct.c_int
+        L.nq_batch_run.argtypes = [vp, pu64, ct.POINTER(ct.c_double)]
+        L.nq_batch_run.restype = ct.c_int
+        L.nq_batch_entries.argtypes = [vp]
+        L.nq_batch_entries.restype = u64
+        L.nq_batch_destroy.argtypes = [vp]
+        L.nq_batch_destroy.restype = ct.c_int
         _LIB = L
     return _LIB
 
@@ -77,8 +87,13 @@ def _check(rc: int, what: str):
         raise NQError(rc, what, msg)
 
 
-def _opts(depth=0, mode="persistent", wg_size=0, waves_per_cu=0, refill_every=0, stream=None):
+FLAG_FORWARD_ORDER = 1
+
+
+def _opts(depth=0, mode="persistent", wg_size=0, waves_per_cu=0, refill_every=0, stream=None,
+          flags=0):
     o = NqOpts()
+    o.flags = flags
     o.depth = depth
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.wg_size = wg_size
@@ -101,6 +116,16 @@ def frontier_size(n: int, depth: int) -> int:
     return ln.value
 
 
+def frontier_runs(n: int, depth: int):
+    """Start offset of each row-0 column's run of entries, followed by F."""
+    cnt = ct.c_uint32()
+    _check(lib().nq_frontier_runs(n, depth, None, 0, ct.byref(cnt)), "nq_frontier_runs")
+    off = np.zeros(cnt.value + 1, np.uint64)
+    _check(lib().nq_frontier_runs(n, depth, off.ctypes.data_as(ct.POINTER(ct.c_uint64)),
+                                  len(off), ct.byref(cnt)), "nq_frontier_runs")
+    return [int(x) for x in off]
+
+
 def frontier(n: int, depth: int):
     """(cols, ld, rd) uint32[F] and weight uint8[F] in canonical order (host arrays)."""
     f = frontier_size(n, depth)
@@ -117,11 +142,13 @@ def frontier(n: int, depth: int):
 
 
 def count(n: int, depth: int = 0, mode="persistent", wg_size: int = 0, waves_per_cu: int = 0,
-          refill_every: int = 0, counts: bool = False, timing: bool = False, stream=None):
+          refill_every: int = 0, counts: bool = False, timing: bool = False, stream=None,
+          forward: bool = False):
     """Q(n).  With counts=True also the per-subproblem counts (numpy uint64, frontier
     order); with timing=True also the DFS kernel time in ms.  Synchronous."""
     o = _opts(depth, mode, wg_size, waves_per_cu, refill_every,
-              stream if stream is None else _stream_handle(stream))
+              stream if stream is None else _stream_handle(stream),
+              FLAG_FORWARD_ORDER if forward else 0)
     buf = None
     if counts:
         if depth == 0:
@@ -145,7 +172,7 @@ def count(n: int, depth: int = 0, mode="persistent", wg_size: int = 0, waves_per
 def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None,
                       depth: int = 0, mode="persistent", wg_size: int = 0,
                       waves_per_cu: int = 0, refill_every: int = 0, stream=None,
-                      timing: bool = False, nodes=None):
+                      timing: bool = False, nodes=None, forward: bool = False):
     """Counts every subtree of device-resident triples (torch int32 CUDA tensors).
 
     ``counts`` (int64[F]) and ``total`` (int64[1], accumulated) are torch tensors
@@ -166,7 +193,8 @@ def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None
         counts = torch.empty(length, dtype=torch.int64, device=cols.device)
     if total is None:
         total = torch.zeros(1, dtype=torch.int64, device=cols.device)
-    o = _opts(depth, mode, wg_size, waves_per_cu, refill_every, _stream_handle(stream))
+    o = _opts(depth, mode, wg_size, waves_per_cu, refill_every, _stream_handle(stream),
+              FLAG_FORWARD_ORDER if forward else 0)
     if nodes is not None:
         if nodes.dtype != torch.int64 or nodes.numel() != length or not nodes.is_cuda:
             raise ValueError("nodes must be an int64 CUDA tensor of the same length")
@@ -194,3 +222,47 @@ def count_batch(ns, depths=None, mode="persistent", wg_size: int = 0, waves_per_
     _check(lib().nq_count_batch(len(ns_a), p32(ns_a), p32(d_a), ct.byref(o),
                                 out.ctypes.data_as(ct.POINTER(ct.c_uint64))), "nq_count_batch")
     return [int(x) for x in out[:len(ns_a)]]
+
+
+class Batch:
+    """A replayable batch plan (nq_batch_create / nq_batch_run / nq_batch_destroy)."""
+
+    def __init__(self, ns, depths=None, depth: int = 0, wg_size: int = 0, waves_per_cu: int = 0,
+                 refill_every: int = 0):
+        self.ns = np.ascontiguousarray(np.asarray(ns, dtype=np.uint32))
+        self._d = None if depths is None else np.ascontiguousarray(np.asarray(depths, np.uint32))
+        o = _opts(depth, "persistent", wg_size, waves_per_cu, refill_every, None)
+        h = ct.c_void_p()
+        p32 = lambda a: None if a is None else a.ctypes.data_as(ct.POINTER(ct.c_uint32))  # noqa
+        _check(lib().nq_batch_create(len(self.ns), p32(self.ns), p32(self._d), ct.byref(o),
+                                     ct.byref(h)), "nq_batch_create")
+        self._h = h
+
+    @property
+    def entries(self) -> int:
+        return int(lib().nq_batch_entries(self._h))
+
+    def run(self, timing: bool = False):
+        out = np.zeros(len(self.ns), np.uint64)
+        ms = ct.c_double(0.0)
+        _check(lib().nq_batch_run(self._h, out.ctypes.data_as(ct.POINTER(ct.c_uint64)),
+                                  ct.byref(ms) if timing else None), "nq_batch_run")
+        res = [int(x) for x in out]
+        return (res, ms.value) if timing else res
+
+    def close(self):
+        if self._h:
+            _check(lib().nq_batch_destroy(self._h), "nq_batch_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -121,6 +121,7 @@ static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
     P.cols = d_cols; P.ld = d_ld; P.rd = d_rd; P.weight = d_weight;
     P.counts = d_counts; P.totals = d_total; P.head = head; P.nodes = d_nodes;
     P.len = len; P.n = n; P.frames = frames; P.refill_every = refill_default(opts);
+    P.reverse = (opts && (opts->flags & NQ_FLAG_FORWARD_ORDER)) ? 0u : 1u;
     EventTimer t;
     if (kernel_ms && (rc = t.start(s)) != NQ_OK) return rc;
     rc = launch_dfs(cfg, P, s);
@@ -156,7 +157,7 @@ extern "C" int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const ui
                                     const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len,
                                     uint64_t* d_counts, uint64_t* d_total, const nq_opts* opts) {
     if (n < 1 || n > NQ_MAX_N) return NQ_EINVAL;
-    if (opts && opts->reserved != 0) return NQ_EINVAL;
+    if (opts && (opts->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
     if (len == 0) return NQ_OK;
     if (!d_cols || !d_ld || !d_rd) return NQ_EINVAL;
     const uint32_t min_placed = opts ? std::min(opts->depth, n) : 0u;
@@ -171,7 +172,7 @@ extern "C" int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const ui
 
 extern "C" int nq_count(uint32_t n, const nq_opts* opts, uint64_t* out_total) {
     if (n < 1 || n > NQ_MAX_N || !out_total) return NQ_EINVAL;
-    if (opts && opts->reserved != 0) return NQ_EINVAL;
+    if (opts && (opts->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
     const uint32_t depth = (opts && opts->depth) ? opts->depth : auto_depth(n);
     if (depth > n) return NQ_EINVAL;
     try {
@@ -244,10 +245,4 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts, uint64_t* out_total) {
     } catch (...) {
         return NQ_EINVAL;
     }
-}
-
-extern "C" int nq_count_batch(uint32_t ninst, const uint32_t* ns, const uint32_t* depths,
-                              const nq_opts* opts, uint64_t* out_totals) {
-    (void)ninst; (void)ns; (void)depths; (void)opts; (void)out_totals;
-    return NQ_EINVAL;
 }

@@ -22,7 +22,11 @@
 // subtree is done.  Persistent mode: a resident grid; every `refill_every` DFS
 // steps each wave ballots its idle lanes, claims that many entries with one
 // atomic add on a global head, and hands them out by rank (mbcnt), so the
-// idle lanes read consecutive entries with coalesced loads.
+// idle lanes read consecutive entries with coalesced loads.  By default the
+// entries are claimed from the end of the frontier down: subtrees below the
+// later row-0 columns are the larger ones (the per-GPU times of Section 4.5
+// grow with the position in the frontier), and starting them first shortens
+// the tail of the launch.
 #include <hip/hip_runtime.h>
 
 #include "nq_internal.h"
@@ -92,6 +96,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     // Takes entry `i`: loads its triple, writes the sentinel and settles the
     // cases that need no search (a full board, the last row, no free square).
     auto take = [&](uint64_t i) {
+        if (PERSISTENT && P.reverse) i = P.len - 1 - i;
         idx = i;
         const uint32_t n = P.inst ? P.inst_n[P.inst[i]] : P.n;
         last = (1u << n) - 1u;

@@ -194,6 +194,25 @@ int frontier_fill(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld, uint
 
 }  // namespace nqi
 
+extern "C" int nq_frontier_runs(uint32_t n, uint32_t depth, uint64_t* offsets, uint32_t capacity,
+                                uint32_t* out_runs) {
+    if (n < 1 || n > NQ_MAX_N || depth < 1 || depth > n || !out_runs) return NQ_EINVAL;
+    try {
+        std::vector<uint64_t> runs;
+        uint64_t total = 0;
+        int rc = nqi::frontier_fill(n, depth, nullptr, nullptr, nullptr, nullptr, 0, &total, &runs);
+        if (rc != NQ_OK) return rc;
+        const uint32_t count = (uint32_t)runs.size() - 1;
+        *out_runs = count;
+        if (!offsets) return NQ_OK;
+        if (capacity < count + 1) return NQ_ERANGE;
+        for (uint32_t i = 0; i <= count; ++i) offsets[i] = runs[i];
+        return NQ_OK;
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
+}
+
 extern "C" int nq_frontier(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld,
                            uint32_t* rd, uint8_t* weight, uint64_t capacity,
                            uint64_t* out_len) {

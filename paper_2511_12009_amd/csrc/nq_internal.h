@@ -45,7 +45,7 @@ struct DfsParams {
     uint32_t n;                     // board size when inst == nullptr
     uint32_t frames;                // LDS stack frames per lane
     uint32_t refill_every;          // DFS steps between scheduler visits
-    uint32_t pad;
+    uint32_t reverse;               // persistent: claim entries from the last one down
 };
 
 // Count reported for an entry that needs more stack frames than the launch has.

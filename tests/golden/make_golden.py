@@ -22,6 +22,14 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 
 OUT = os.path.join(HERE, "oracle_runs.txt")
+NODES_OUT = os.path.join(HERE, "oracle_nodes.txt")
+NODES_HEADER = """# Node counts nodes(N, k) (queens placed in rows k..N-2 below every frontier
+# prefix), written by tests/golden/make_golden.py.  "run" lines repeat an
+# oracle run of oracle_runs.txt; "derived" lines (even N only) follow from one by
+# the node identity nodes(k) = nodes(j) + F(k+1) + ... + F(j) for k < j (and the
+# same with the sign reversed for k > j), with F from the oracle's frontier.
+# N k nodes source
+"""
 HEADER = """# Oracle results per frontier, written by tests/golden/make_golden.py (oracle only).
 # N k F weighted_total node_total sha256(counts u64 LE) sha256(nodes u64 LE) oracle_seconds threads
 """
@@ -41,9 +49,35 @@ def run(n, k, threads):
             f"{secs:.1f} {threads}")
 
 
+def write_nodes():
+    """Node counts at depths 4..8 for every even N with an oracle run."""
+    runs = []
+    with open(OUT) as f:
+        runs = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+    lines = []
+    for r in runs:
+        n, j, nodes = int(r[0]), int(r[1]), int(r[4])
+        lines.append((n, j, nodes, "run"))
+        if n % 2:
+            continue
+        for k in range(max(1, j - 2), min(n, j + 3)):
+            if k == j or any(x[0] == n and x[1] == k for x in runs):
+                continue
+            if k < j:
+                v = nodes + sum(oracle.frontier_size(n, d) for d in range(k + 1, j + 1))
+            else:
+                v = nodes - sum(oracle.frontier_size(n, d) for d in range(j + 1, k + 1))
+            lines.append((n, k, v, f"derived-from-k{j}"))
+    lines.sort()
+    with open(NODES_OUT, "w") as f:
+        f.write(NODES_HEADER)
+        for n, k, v, src in lines:
+            f.write(f"{n} {k} {v} {src}\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cases", nargs="+")
+    ap.add_argument("cases", nargs="*")
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
     args = ap.parse_args()
     for case in args.cases:
@@ -59,6 +93,7 @@ def main():
         with open(OUT, "w") as f:
             f.write(HEADER)
             f.writelines(lines)
+    write_nodes()
 
 
 if __name__ == "__main__":

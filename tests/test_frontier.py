@@ -108,3 +108,11 @@ def test_count_entry_points_validate_before_touching_the_gpu():
     assert lib.nq_count_subproblems(8, None, None, None, None, 5, None, None, None) == -1
     # len == 0 is a valid empty call: nothing is launched
     assert lib.nq_count_subproblems(8, None, None, None, None, 0, None, None, None) == 0
+
+
+def test_frontier_runs_cover_row0_columns():
+    for n, k in [(20, 6), (17, 5), (9, 3)]:
+        runs = nq.frontier_runs(n, k)
+        pre, _ = oracle.frontier(n, k)
+        starts = [i for i in range(len(pre)) if i == 0 or pre[i][0] != pre[i - 1][0]]
+        assert runs == starts + [len(pre)]

@@ -198,3 +198,21 @@ def test_n20_bench_shape():
         idx = np.random.default_rng(20).choice(len(pre), 48, replace=False)
         ref, _ = oracle.count_prefixes(n, pre[idx], threads=16)
         np.testing.assert_array_equal(counts[idx], ref)
+
+
+@pytest.mark.parametrize("n,k", [(14, 3), (17, 5), (16, 4), (12, 2)])
+def test_node_counts_per_subproblem(n, k):
+    """DFS steps of the node-counting kernel equal the oracle's nodes entry by entry."""
+    nq = _nq()
+    g = _golden_runs()[(n, k)]
+    cols, ld, rd, w = nq.frontier(n, k)
+    t = [_dev(x) for x in (cols, ld, rd)]
+    nodes = torch.empty(len(cols), dtype=torch.int64, device="cuda")
+    for mode in ("persistent", "plain"):
+        _say("nodes", n, k, mode)
+        counts, _ = nq.count_subproblems(n, *t, depth=k, mode=mode, nodes=nodes)
+        torch.cuda.synchronize()
+        got_nodes = nodes.cpu().numpy().view(np.uint64)
+        assert int(got_nodes.sum()) == int(g[4])
+        assert _digest(got_nodes) == g[6]
+        assert _digest(counts.cpu().numpy().view(np.uint64)) == g[5]
