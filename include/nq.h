@@ -176,6 +176,29 @@ int nq_count_batch(uint32_t ninst, const uint32_t* ns, const uint32_t* depths,
                    const nq_opts* opts, uint64_t* out_totals);
 
 /*
+ * nq_autotune -- measure the best pre-placement depth and launch shape for n.
+ *
+ * Times complete persistent counts of n on the current device: every depth in
+ * [depth_lo, depth_hi] (0, 0 = a range around max(1, n - 14)) with the default
+ * launch shape, then, at the best depth, a few resident-wave counts per CU and
+ * scheduler-visit intervals, until budget_ms of device time is spent (0 = 60 s).
+ * The paper tunes the same choices by hand (Section 4.1 Table 3, Section 4.2
+ * Table 4).  Every trial must produce the same count (else NQ_EDEVICE).  The
+ * winner is written to *out and remembered for this process and device:
+ * nq_count with opts->depth == 0 then uses it.  n in [4, 28].
+ */
+typedef struct nq_tuned {
+    uint32_t depth;          /* pre-placed rows                                  */
+    uint32_t waves_per_cu;   /* 0 = as many as the LDS stacks allow              */
+    uint32_t refill_every;   /* DFS steps between scheduler visits               */
+    uint32_t trials;         /* timed counts made                                */
+    double ms;               /* best device time of one count                    */
+    uint64_t count;          /* the count every trial agreed on                  */
+} nq_tuned;
+int nq_autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
+                nq_tuned* out);
+
+/*
  * Reusable batch plan: nq_count_batch split into set-up and replay.
  *
  * nq_batch_create builds and uploads the concatenated frontiers of ninst >= 1

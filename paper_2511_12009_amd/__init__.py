@@ -14,11 +14,13 @@ Functions (same names as the C entry points, without the ``nq_`` prefix):
   count_subproblems(n, cols, ld, rd, ...)    -> per-entry counts and weighted total
   count_batch(ns, depths=None, ...)          -> [Q(n) for n in ns]
   Batch(ns, depths=None).run()               -> replayable batch plan (HIP graph)
+  autotune(n, depth_lo=0, depth_hi=0)        -> measured best depth and launch shape
 """
 from ._native import (  # noqa: F401
     Batch,
     NQError,
     MODES,
+    autotune,
     count,
     count_batch,
     count_subproblems,

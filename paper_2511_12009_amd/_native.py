@@ -39,6 +39,17 @@ class NqOpts(ct.Structure):
     ]
 
 
+class NqTuned(ct.Structure):
+    _fields_ = [
+        ("depth", ct.c_uint32),
+        ("waves_per_cu", ct.c_uint32),
+        ("refill_every", ct.c_uint32),
+        ("trials", ct.c_uint32),
+        ("ms", ct.c_double),
+        ("count", ct.c_uint64),
+    ]
+
+
 _LIB = None
 
 
@@ -66,6 +77,8 @@ def lib():
         L.nq_count_subproblems.restype = ct.c_int
         L.nq_count_batch.argtypes = [u32, pu32, pu32, ct.POINTER(NqOpts), pu64]
         L.nq_count_batch.restype = ct.c_int
+        L.nq_autotune.argtypes = [u32, u32, u32, ct.c_double, ct.POINTER(NqTuned)]
+        L.nq_autotune.restype = ct.c_int
         L.nq_batch_create.argtypes = [u32, pu32, pu32, ct.POINTER(NqOpts), ct.POINTER(vp)]
         L.nq_batch_create.restype = ct.c_int
         L.nq_batch_run.argtypes = [vp, pu64, ct.POINTER(ct.c_double)]
@@ -228,10 +241,11 @@ class Batch:
     """A replayable batch plan (nq_batch_create / nq_batch_run / nq_batch_destroy)."""
 
     def __init__(self, ns, depths=None, depth: int = 0, wg_size: int = 0, waves_per_cu: int = 0,
-                 refill_every: int = 0):
+                 refill_every: int = 0, forward: bool = False):
         self.ns = np.ascontiguousarray(np.asarray(ns, dtype=np.uint32))
         self._d = None if depths is None else np.ascontiguousarray(np.asarray(depths, np.uint32))
-        o = _opts(depth, "persistent", wg_size, waves_per_cu, refill_every, None)
+        o = _opts(depth, "persistent", wg_size, waves_per_cu, refill_every, None,
+                  FLAG_FORWARD_ORDER if forward else 0)
         h = ct.c_void_p()
         p32 = lambda a: None if a is None else a.ctypes.data_as(ct.POINTER(ct.c_uint32))  # noqa
         _check(lib().nq_batch_create(len(self.ns), p32(self.ns), p32(self._d), ct.byref(o),
@@ -266,3 +280,11 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def autotune(n: int, depth_lo: int = 0, depth_hi: int = 0, budget_ms: float = 0.0) -> dict:
+    """Measured best depth / waves per CU / visit interval for n (nq_autotune)."""
+    t = NqTuned()
+    _check(lib().nq_autotune(n, depth_lo, depth_hi, budget_ms, ct.byref(t)), "nq_autotune")
+    return {"depth": t.depth, "waves_per_cu": t.waves_per_cu, "refill_every": t.refill_every,
+            "trials": t.trials, "ms": t.ms, "count": t.count}

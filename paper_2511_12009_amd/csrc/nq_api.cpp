@@ -170,10 +170,24 @@ extern "C" int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const ui
     }
 }
 
-extern "C" int nq_count(uint32_t n, const nq_opts* opts, uint64_t* out_total) {
+extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total) {
     if (n < 1 || n > NQ_MAX_N || !out_total) return NQ_EINVAL;
-    if (opts && (opts->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
-    const uint32_t depth = (opts && opts->depth) ? opts->depth : auto_depth(n);
+    if (opts_in && (opts_in->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
+    // Automatic depth: the autotuner's choice for this n if it ran, else the
+    // frontier-size rule.  A tuned launch shape fills fields left at 0.
+    nq_opts local{};
+    if (opts_in) local = *opts_in;
+    local.d_nodes = nullptr;          // per-entry nodes are a nq_count_subproblems output
+    const nq_opts* opts = &local;
+    if (local.depth == 0) {
+        nq_tuned t;
+        if (tune_lookup(n, &t) == NQ_OK) {
+            local.depth = t.depth;
+            if (!local.waves_per_cu) local.waves_per_cu = t.waves_per_cu;
+            if (!local.refill_every) local.refill_every = t.refill_every;
+        }
+    }
+    const uint32_t depth = local.depth ? local.depth : auto_depth(n);
     if (depth > n) return NQ_EINVAL;
     try {
         uint64_t F = 0;
@@ -237,7 +251,7 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts, uint64_t* out_total) {
         if (want_counts)
             for (uint64_t i = 0; i < F; ++i)
                 if (opts->counts_out[i] == kCountInvalid) return NQ_EINVAL;
-        if (opts && opts->kernel_ms_out) *opts->kernel_ms_out = ms;
+        if (opts_in && opts_in->kernel_ms_out) *opts_in->kernel_ms_out = ms;
         *out_total = total;
         return NQ_OK;
     } catch (const std::bad_alloc&) {

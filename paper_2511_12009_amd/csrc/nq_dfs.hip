@@ -54,12 +54,15 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
 
 }  // namespace
 
-// Per-lane state of the search.  `top` and `floor` are LDS byte offsets into
+// Per-lane state of the search.  `top` and `floor` are LDS byte addresses in
 // the lane's column of the wave's stack region; the frame at `floor` is a
-// sentinel (cols = the full board, avail = 0).  Popping it leaves the lane in
+// sentinel (cols = all 32 bits set, avail = 0).  Popping it leaves the lane in
 // a state in which every later step is a no-op: no free column, no free square
-// below, and the stack pointer pinned at the sentinel.  So "avail == 0 after a
-// step" means "subtree finished", with no per-lane loop exit.
+// below (cols + step keeps every column bit set, whatever the step), no leaf
+// (bit 31 clear after the wrap-around), and the stack pointer pinned at the
+// sentinel.  So "avail == 0 after a step" means "subtree finished", with no
+// per-lane loop exit.  A lane whose entry needs no search parks in the same
+// state.
 //
 // Leaf test.  With LEAFCTR the bits of `cols` above the board hold a row
 // counter, advanced by the same add that places the queen; it is started so
@@ -68,6 +71,9 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
 // popcount.  It needs N - 1 - placed <= 2^(31 - N) (always true for N <= 26);
 // otherwise the popcount form of Algorithm 3 is used.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// cols of a parked or finished lane (see the kernel comment).
+constexpr uint32_t kParked = 0xffffffffu;
 typedef __attribute__((address_space(3))) u32x4 lds_frame;
 
 // A frame addressed by its absolute LDS byte address.
@@ -83,9 +89,9 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     const uint32_t wave = threadIdx.x >> 6;
     const int32_t floor = lds + (int32_t)(((wave * (P.frames + 1u)) * 64u + lane) * 16u);
     int32_t top = floor;
-    *frame_at(floor) = u32x4{0u, 0u, 0u, 0u};
+    *frame_at(floor) = u32x4{kParked, 0u, 0u, 0u};
 
-    uint32_t c = 0, l = 0, r = 0, v = 0, last = 0, nm1 = 0, step_k = 0;
+    uint32_t c = kParked, l = 0, r = 0, v = 0, last = 0, nm1 = 0, step_k = 0;
     uint64_t idx = 0;
     uint32_t sum32 = 0, steps32 = 0;
     uint64_t sum64 = 0, steps64 = 0;
@@ -110,7 +116,8 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         has_task = true;
         const uint32_t placed = __popc(c);
         const uint32_t avail = last & ~(c | l | r);
-        *frame_at(floor) = u32x4{last, 0u, 0u, 0u};
+        step_k = LEAFCTR ? (1u << n) : 0u;
+        *frame_at(floor) = u32x4{kParked, 0u, 0u, 0u};
         if (placed >= nm1) {
             sum32 = (placed == n) ? 1u : __popc(avail);
         } else if (n - 2u - placed > P.frames ||
@@ -118,12 +125,9 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
             sum64 = kCountInvalid;        // does not fit this launch's stack or counter
         } else if (avail != 0u) {
             v = avail;
-            if (LEAFCTR) {
-                step_k = 1u << n;
-                c |= ((1u << (31u - n)) - (nm1 - placed)) << n;
-            }
+            if (LEAFCTR) c |= ((1u << (31u - n)) - (nm1 - placed)) << n;
         }
-        if (v == 0u) c = last;            // nothing to search: park on the sentinel state
+        if (v == 0u) c = kParked;         // nothing to search: park like a finished lane
     };
 
     if (!PERSISTENT) {

@@ -91,6 +91,9 @@ int launch_dfs(const LaunchCfg& cfg, const DfsParams& P, void* stream);
 // Enqueues dst[0..count) = 0 with a kernel (no memset node in captured graphs).
 int launch_zero_u64(unsigned long long* dst, uint64_t count, void* stream);
 
+// Tuning results remembered for this process (nq_autotune), by device and n.
+int tune_lookup(uint32_t n, nq_tuned* out);
+
 // Records a failing hipError_t for nq_last_hip_error().
 void set_hip_error(int err);
 

@@ -44,6 +44,21 @@ def test_count_batch_mixed_sizes_and_depths(known_counts):
     assert nq.count_batch(ns, depths=full) == exp
 
 
+def test_batch_alternating_sizes_with_dead_entries(known_counts):
+    """Consecutive entries of different board sizes, many of which need no search
+    (dead entries, last-row entries): a lane that parks on such an entry after a
+    task of another size must stay parked."""
+    nq = _nq()
+    ns = [8, 13, 9, 12, 10, 14, 8, 11] * 4
+    depths = [n - 2 if i % 2 else n - 3 for i, n in enumerate(ns)]
+    exp = _expected(ns, known_counts)
+    for fwd in (False, True):
+        _say("alternating sizes, forward", fwd)
+        with nq.Batch(ns, depths=depths) as b:
+            for rep in range(2):
+                assert b.run() == exp, (fwd, rep)
+
+
 def test_count_batch_edges():
     nq = _nq()
     assert nq.count_batch([]) == []
