@@ -220,6 +220,64 @@ int nq_batch_run(nq_batch* batch, uint64_t* out_totals, double* kernel_ms);
 uint64_t nq_batch_entries(const nq_batch* batch);
 int nq_batch_destroy(nq_batch* batch);
 
+/*
+ * Serving: continuous batching of count requests on one GPU.
+ *
+ * Not in the paper (its runs are single counts); the unit of work is still the
+ * pre-placed subproblem of Section 1, searched by the DFS of Algorithm 2 /
+ * Algorithm 3.  Requests:
+ *   NQ_REQ_COUNT  Q(n); depth = pre-placement depth (0 = the server picks the
+ *                 shallowest depth with >= 4096 subproblems).
+ *   NQ_REQ_SLICE  sum(weight * count) over entries [start, start + len) of the
+ *                 (n, depth) frontier in nq_frontier order; the frontier is
+ *                 built once and kept in device memory, slices are copied out
+ *                 of it on the device.
+ * A scheduler thread owned by the server admits requests in arrival order while
+ * request slots (4096), work-ring space and the LDS stack of the epoch kernel
+ * allow, and launches bounded persistent "epochs" over the newly admitted
+ * subproblems on two alternating streams, so new work overlaps the tail of
+ * older work.  A request's result is published to pinned host memory by the
+ * GPU lane that retires its last subproblem.
+ *
+ * nq_serve_create: opts may set depth (= the LDS stack frames per lane of the
+ * epoch kernel, default 14: a request whose subproblems need more stack than
+ * that is refused with NQ_EINVAL at submit), wg_size, waves_per_cu and
+ * refill_every; hbm_budget_bytes (0 = 1 GiB) is split between the work ring
+ * (17 B per subproblem) and the resident slice frontiers.
+ * nq_serve_submit: non-blocking; NQ_EINVAL for a malformed request, NQ_EFULL
+ * when 65536 requests are already waiting.  A request larger than the ring, or
+ * a slice past the end of its frontier, completes with that status in
+ * nq_result.status.
+ * nq_serve_poll: NQ_OK (result written, ticket released), NQ_EAGAIN (not done),
+ * NQ_ENOENT (unknown or already collected ticket).  nq_serve_wait: the same,
+ * blocking up to timeout_ns.  Timestamps are CLOCK_MONOTONIC nanoseconds:
+ * submit, admission (subproblems enqueued), completion seen by the scheduler.
+ * nq_serve_destroy: drops requests not yet admitted, waits for admitted ones,
+ * frees everything.  All calls on one server are thread-safe.
+ */
+enum nq_request_kind { NQ_REQ_COUNT = 1, NQ_REQ_SLICE = 2 };
+typedef struct nq_request {
+    uint32_t kind;           /* enum nq_request_kind                              */
+    uint32_t n;              /* board size, 1..28                                  */
+    uint32_t depth;          /* pre-placement depth (see above)                    */
+    uint32_t reserved;       /* must be 0                                          */
+    uint64_t start;          /* NQ_REQ_SLICE: first entry                          */
+    uint64_t len;            /* NQ_REQ_SLICE: number of entries                    */
+} nq_request;
+typedef struct nq_result {
+    int32_t status;          /* NQ_OK or why the request failed                    */
+    uint32_t reserved;
+    uint64_t count;          /* Q(n), or the slice's weighted sum                  */
+    uint64_t entries;        /* subproblems searched for this request              */
+    uint64_t t_submit_ns, t_admit_ns, t_done_ns;
+} nq_result;
+typedef struct nq_server nq_server;
+int nq_serve_create(const nq_opts* opts, uint64_t hbm_budget_bytes, nq_server** out);
+int nq_serve_submit(nq_server* server, const nq_request* req, uint64_t* out_ticket);
+int nq_serve_poll(nq_server* server, uint64_t ticket, nq_result* out);
+int nq_serve_wait(nq_server* server, uint64_t ticket, nq_result* out, uint64_t timeout_ns);
+int nq_serve_destroy(nq_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,11 +15,13 @@ Functions (same names as the C entry points, without the ``nq_`` prefix):
   count_batch(ns, depths=None, ...)          -> [Q(n) for n in ns]
   Batch(ns, depths=None).run()               -> replayable batch plan (HIP graph)
   autotune(n, depth_lo=0, depth_hi=0)        -> measured best depth and launch shape
+  Server(...).submit_count / submit_slice / poll / wait -> continuous-batching serving
 """
 from ._native import (  # noqa: F401
     Batch,
     NQError,
     MODES,
+    Server,
     autotune,
     count,
     count_batch,

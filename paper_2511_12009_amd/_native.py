@@ -50,6 +50,31 @@ class NqTuned(ct.Structure):
     ]
 
 
+class NqRequest(ct.Structure):
+    _fields_ = [
+        ("kind", ct.c_uint32),
+        ("n", ct.c_uint32),
+        ("depth", ct.c_uint32),
+        ("reserved", ct.c_uint32),
+        ("start", ct.c_uint64),
+        ("len", ct.c_uint64),
+    ]
+
+
+class NqResult(ct.Structure):
+    _fields_ = [
+        ("status", ct.c_int32),
+        ("reserved", ct.c_uint32),
+        ("count", ct.c_uint64),
+        ("entries", ct.c_uint64),
+        ("t_submit_ns", ct.c_uint64),
+        ("t_admit_ns", ct.c_uint64),
+        ("t_done_ns", ct.c_uint64),
+    ]
+
+
+REQ_COUNT, REQ_SLICE = 1, 2
+
 _LIB = None
 
 
@@ -77,6 +102,16 @@ def lib():
         L.nq_count_subproblems.restype = ct.c_int
         L.nq_count_batch.argtypes = [u32, pu32, pu32, ct.POINTER(NqOpts), pu64]
         L.nq_count_batch.restype = ct.c_int
+        L.nq_serve_create.argtypes = [ct.POINTER(NqOpts), u64, ct.POINTER(vp)]
+        L.nq_serve_create.restype = ct.c_int
+        L.nq_serve_submit.argtypes = [vp, ct.POINTER(NqRequest), pu64]
+        L.nq_serve_submit.restype = ct.c_int
+        L.nq_serve_poll.argtypes = [vp, u64, ct.POINTER(NqResult)]
+        L.nq_serve_poll.restype = ct.c_int
+        L.nq_serve_wait.argtypes = [vp, u64, ct.POINTER(NqResult), u64]
+        L.nq_serve_wait.restype = ct.c_int
+        L.nq_serve_destroy.argtypes = [vp]
+        L.nq_serve_destroy.restype = ct.c_int
         L.nq_autotune.argtypes = [u32, u32, u32, ct.c_double, ct.POINTER(NqTuned)]
         L.nq_autotune.restype = ct.c_int
         L.nq_batch_create.argtypes = [u32, pu32, pu32, ct.POINTER(NqOpts), ct.POINTER(vp)]
@@ -288,3 +323,70 @@ def autotune(n: int, depth_lo: int = 0, depth_hi: int = 0, budget_ms: float = 0.
     _check(lib().nq_autotune(n, depth_lo, depth_hi, budget_ms, ct.byref(t)), "nq_autotune")
     return {"depth": t.depth, "waves_per_cu": t.waves_per_cu, "refill_every": t.refill_every,
             "trials": t.trials, "ms": t.ms, "count": t.count}
+
+
+class Server:
+    """Continuous-batching count server (nq_serve_*).
+
+    submit_count(n, depth=0) / submit_slice(n, depth, start, length) return a
+    ticket; poll(ticket) returns None while the request runs, else a dict with
+    status, count, entries and the submit/admit/done timestamps (ns).
+    """
+
+    def __init__(self, hbm_budget: int = 0, max_frames: int = 0, wg_size: int = 0,
+                 waves_per_cu: int = 0, refill_every: int = 0):
+        o = _opts(max_frames, "persistent", wg_size, waves_per_cu, refill_every, None)
+        h = ct.c_void_p()
+        _check(lib().nq_serve_create(ct.byref(o), hbm_budget, ct.byref(h)), "nq_serve_create")
+        self._h = h
+
+    def _submit(self, kind, n, depth, start, length):
+        rq = NqRequest(kind, n, depth, 0, start, length)
+        t = ct.c_uint64()
+        _check(lib().nq_serve_submit(self._h, ct.byref(rq), ct.byref(t)), "nq_serve_submit")
+        return t.value
+
+    def submit_count(self, n: int, depth: int = 0) -> int:
+        return self._submit(REQ_COUNT, n, depth, 0, 0)
+
+    def submit_slice(self, n: int, depth: int, start: int, length: int) -> int:
+        return self._submit(REQ_SLICE, n, depth, start, length)
+
+    @staticmethod
+    def _res(r):
+        return {"status": r.status, "count": r.count, "entries": r.entries,
+                "t_submit_ns": r.t_submit_ns, "t_admit_ns": r.t_admit_ns,
+                "t_done_ns": r.t_done_ns}
+
+    def poll(self, ticket: int):
+        r = NqResult()
+        rc = lib().nq_serve_poll(self._h, ticket, ct.byref(r))
+        if rc == NQ_EAGAIN:
+            return None
+        _check(rc, "nq_serve_poll")
+        return self._res(r)
+
+    def wait(self, ticket: int, timeout_s: float = 60.0):
+        r = NqResult()
+        rc = lib().nq_serve_wait(self._h, ticket, ct.byref(r), int(timeout_s * 1e9))
+        if rc == NQ_EAGAIN:
+            raise TimeoutError(f"ticket {ticket} not done after {timeout_s} s")
+        _check(rc, "nq_serve_wait")
+        return self._res(r)
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, None
+            _check(lib().nq_serve_destroy(h), "nq_serve_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -144,6 +144,7 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
         P.inst = reinterpret_cast<uint32_t*>(d + o_inst);
         P.weight = reinterpret_cast<uint8_t*>(d + o_w);
         P.inst_n = reinterpret_cast<uint32_t*>(d + o_n);
+        P.ninst = ninst;
         P.totals = b->d_totals;
         P.head = reinterpret_cast<unsigned long long*>(d + o_head);
         P.counts = nullptr;

@@ -29,9 +29,14 @@
 // the tail of the launch.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "nq_internal.h"
 
 namespace nqi {
+
+// Default inner-loop form of the DFS kernels (see nq_dfs_kernel).
+constexpr int kDefaultLoop = 0;
 
 namespace {
 
@@ -53,6 +58,22 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
 }
 
 }  // namespace
+
+// Serving: counts one retired entry of instance s; the lane that retires the
+// last one publishes the instance's total to host memory (value first, then
+// the generation flag, each as a system-scope store, so a host that sees the
+// flag also sees the value).
+__device__ __noinline__ void publish_if_last(const DfsParams& P, uint32_t s) {
+    __threadfence();                                      // totals add before the count
+    const uint32_t before = atomicSub(&P.remaining[s], 1u);
+    if (before == 1u) {
+        __threadfence();
+        const unsigned long long t = atomicAdd(&P.totals[s], 0ull);
+        __hip_atomic_store(&P.host_val[s], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&P.host_flag[s], (unsigned long long)P.inst_gen[s], __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
 
 // Per-lane state of the search.  `top` and `floor` are LDS byte addresses in
 // the lane's column of the wave's stack region; the frame at `floor` is a
@@ -81,7 +102,82 @@ __device__ __forceinline__ lds_frame* frame_at(int32_t addr) {
     return (lds_frame*)(uintptr_t)(uint32_t)addr;
 }
 
-template <bool PERSISTENT, bool STATS, bool LEAFCTR>
+// Exec-masked helpers for the hand-scheduled loop (LOOP >= 1).  Each block
+// switches exec to the given lane mask, does its LDS access and stack-pointer
+// update, and restores exec before the block ends.
+
+// Push: frame -> [top + 1024], top += 1024 for the lanes in `m`.
+__device__ __forceinline__ void isa_push(u32x4 st, int32_t& top, uint64_t m) {
+    uint64_t sv;
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[m]\n\t"
+        "ds_write_b128 %[top], %[st] offset:1024\n\t"
+        "v_add_u32 %[top], 0x400, %[top]\n\t"
+        "s_mov_b64 exec, %[sv]"
+        : [top] "+v"(top), [sv] "=&s"(sv)
+        : [m] "s"(m), [st] "v"(st)
+        : "memory");
+}
+
+// Pop: frame <- [top], top = max(top - 1024, floor) for the lanes in `m`; the
+// loaded frame is waited for before the block ends.
+__device__ __forceinline__ void isa_pop(u32x4& st, int32_t& top, int32_t floor, uint64_t m) {
+    uint64_t sv;
+    int32_t t;
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[m]\n\t"
+        "ds_read_b128 %[st], %[top]\n\t"
+        "v_add_u32 %[t], 0xfffffc00, %[top]\n\t"
+        "v_max_i32 %[top], %[t], %[fl]\n\t"
+        "s_mov_b64 exec, %[sv]\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [st] "+v"(st), [top] "+v"(top), [sv] "=&s"(sv), [t] "=&v"(t)
+        : [m] "s"(m), [fl] "v"(floor)
+        : "memory");
+}
+
+// Prefetch the frame a pop would restore: nxt <- [top] for every lane.
+__device__ __forceinline__ void isa_prefetch(u32x4& nxt, int32_t top) {
+    asm volatile("ds_read_b128 %[nx], %[top]" : [nx] "=v"(nxt) : [top] "v"(top) : "memory");
+}
+
+// Pop from the prefetched frame: wait for it, then st <- nxt and
+// top = max(top - 1024, floor) for the lanes in `m`.
+__device__ __forceinline__ void isa_pop_prefetched(u32x4& st, u32x4& nxt, int32_t& top,
+                                                   int32_t floor, uint64_t m) {
+    int32_t t;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_cndmask_b32 %[s0], %[s0], %[n0], %[m]\n\t"
+        "v_cndmask_b32 %[s1], %[s1], %[n1], %[m]\n\t"
+        "v_cndmask_b32 %[s2], %[s2], %[n2], %[m]\n\t"
+        "v_cndmask_b32 %[s3], %[s3], %[n3], %[m]\n\t"
+        "v_add_u32 %[t], 0xfffffc00, %[top]\n\t"
+        "v_max_i32 %[t], %[t], %[fl]\n\t"
+        "v_cndmask_b32 %[top], %[top], %[t], %[m]"
+        : [s0] "+v"(st.x), [s1] "+v"(st.y), [s2] "+v"(st.z), [s3] "+v"(st.w), [top] "+v"(top),
+          [t] "=&v"(t)
+        : [n0] "v"(nxt.x), [n1] "v"(nxt.y), [n2] "v"(nxt.z), [n3] "v"(nxt.w), [m] "s"(m),
+          [fl] "v"(floor)
+        : "memory");
+}
+
+// Select: d = m ? a : d per lane (v_cndmask with an SGPR lane mask).
+__device__ __forceinline__ uint32_t isa_sel(uint64_t m, uint32_t a, uint32_t d) {
+    asm("v_cndmask_b32 %0, %0, %1, %2" : "+v"(d) : "v"(a), "s"(m));
+    return d;
+}
+
+// sum += 1 for the lanes in `m` (carry-in add).
+__device__ __forceinline__ void isa_count(uint32_t& sum, uint64_t m) {
+    uint64_t junk;
+    asm("v_addc_co_u32 %0, %1, %0, 0, %2" : "+v"(sum), "=s"(junk) : "s"(m));
+}
+
+// LOOP selects the inner-loop form: 0 = plain C++ (the compiler places the
+// exec masks), 1 = hand-placed exec masks with a direct pop, 2 = as 1 but the
+// frame a pop needs is read one step ahead, so the pop does not wait on LDS.
+template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP>
 __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     extern __shared__ uint4 lds_stack[];
     const int32_t lds = (int32_t)(uint32_t)(uintptr_t)(lds_frame*)lds_stack;
@@ -103,8 +199,18 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     // cases that need no search (a full board, the last row, no free square).
     auto take = [&](uint64_t i) {
         if (PERSISTENT && P.reverse) i = P.len - 1 - i;
+        if (P.wrap) {
+            i += P.base;
+            if (i >= P.wrap) i -= P.wrap;
+        }
         idx = i;
-        const uint32_t n = P.inst ? P.inst_n[P.inst[i]] : P.n;
+        uint32_t n = P.n;
+        bool bad_inst = false;
+        if (P.inst) {
+            const uint32_t s = P.inst[i];
+            bad_inst = s >= P.ninst;
+            n = bad_inst ? 1u : P.inst_n[s];
+        }
         last = (1u << n) - 1u;
         nm1 = n - 1u;
         c = P.cols[i] & last;
@@ -118,7 +224,9 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         const uint32_t avail = last & ~(c | l | r);
         step_k = LEAFCTR ? (1u << n) : 0u;
         *frame_at(floor) = u32x4{kParked, 0u, 0u, 0u};
-        if (placed >= nm1) {
+        if (bad_inst || n < 1u || n > NQ_MAX_N) {
+            sum64 = kCountInvalid;        // instance id or board size out of range
+        } else if (placed >= nm1) {
             sum32 = (placed == n) ? 1u : __popc(avail);
         } else if (n - 2u - placed > P.frames ||
                    (LEAFCTR && nm1 - placed > (1u << (31u - n)))) {
@@ -143,13 +251,16 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
             const bool ok = sum64 != kCountInvalid;
             if (P.counts) P.counts[idx] = sum64;
             if (STATS) P.nodes[idx] = steps64;
+            const uint32_t s = P.inst ? P.inst[idx] : 0u;
+            const bool inst_ok = !P.inst || s < P.ninst;
             if (P.totals && ok && sum64 != 0) {
                 const uint64_t w = P.weight ? (uint64_t)P.weight[idx] : 1u;
                 if (P.inst)
-                    atomicAdd(&P.totals[P.inst[idx]], (unsigned long long)(w * sum64));
+                    atomicAdd(&P.totals[s], (unsigned long long)(w * sum64));
                 else
                     wtotal += w * sum64;
             }
+            if (P.remaining && inst_ok) publish_if_last(P, s);
             has_task = false;
         }
         if (PERSISTENT && !exhausted) {
@@ -176,6 +287,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         // The frame is kept as one 4-vector so that push and pop move it with
         // a single ds_write_b128 / ds_read_b128 and no register shuffling.
         u32x4 st = {c, l, r, v};
+        if (LOOP == 0) {
         for (uint32_t it = 0; it < P.refill_every; ++it) {
             const uint32_t p = st.w & (0u - st.w);    // lowest untried column
             st.w ^= p;
@@ -202,6 +314,44 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 top = max(top - 1024, floor);
             }
         }
+        } else {
+        // Same step with the lane masks kept in SGPR pairs: the push, the
+        // selects, the pop and the leaf count use them directly.
+        u32x4 nxt;
+        if (LOOP == 2) isa_prefetch(nxt, top);
+        // The trip count is wave-uniform; readfirstlane keeps it in an SGPR.
+        uint32_t trips = __builtin_amdgcn_readfirstlane(P.refill_every);
+        do {
+            const uint32_t p = st.w & (0u - st.w);
+            const uint32_t rest = st.w ^ p;
+            const uint32_t nc = LEAFCTR ? st.x + p + step_k : (st.x | p);
+            const uint32_t nl = (st.y + p) << 1;
+            const uint32_t nr = (st.z + p) >> 1;
+            const uint32_t a = last & ~(nc | nl | nr);
+            if (STATS) steps32 += (p != 0u);
+            const uint64_t leafm = __builtin_amdgcn_ballot_w64(
+                LEAFCTR ? (int32_t)nc < 0 : __popc(nc) == nm1);
+            const uint64_t anym = __builtin_amdgcn_ballot_w64(a != 0u);
+            const uint64_t restm = __builtin_amdgcn_ballot_w64(rest != 0u);
+            const uint64_t descm = anym & ~leafm;
+            isa_count(sum32, anym & leafm);
+            st.w = rest;
+            isa_push(st, top, descm & restm);
+            st.x = isa_sel(descm, nc, st.x);
+            st.y = isa_sel(descm, nl, st.y);
+            st.z = isa_sel(descm, nr, st.z);
+            st.w = isa_sel(descm, a, st.w);
+            const uint64_t popm = __builtin_amdgcn_ballot_w64(st.w == 0u);
+            if (LOOP == 2) {
+                isa_pop_prefetched(st, nxt, top, floor, popm);
+                isa_prefetch(nxt, top);
+            } else {
+                isa_pop(st, top, floor, popm);
+            }
+            trips = __builtin_amdgcn_readfirstlane(trips - 1u);
+        } while (trips != 0u);
+        if (LOOP == 2) asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(nxt)::"memory");
+        }
         c = st.x; l = st.y; r = st.z; v = st.w;
     }
 
@@ -211,24 +361,59 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     }
 }
 
+__global__ void nq_slot_init_kernel(const SlotInit* recs, uint32_t count, uint32_t* inst_n,
+                                    uint32_t* remaining, unsigned long long* totals,
+                                    uint32_t* gen) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        const SlotInit r = recs[i];
+        inst_n[r.slot] = r.n;
+        remaining[r.slot] = r.entries;
+        totals[r.slot] = 0ull;
+        gen[r.slot] = r.gen;
+    }
+}
+
 __global__ void nq_zero_u64_kernel(unsigned long long* dst, uint64_t count) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) dst[i] = 0ull;
 }
 
-template <bool PERSISTENT, bool STATS, bool LEAFCTR>
+template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP>
 static const void* kernel_ptr() {
-    return reinterpret_cast<const void*>(&nq_dfs_kernel<PERSISTENT, STATS, LEAFCTR>);
+    return reinterpret_cast<const void*>(&nq_dfs_kernel<PERSISTENT, STATS, LEAFCTR, LOOP>);
+}
+
+template <int LOOP>
+static const void* select_kernel_loop(uint32_t mode, bool stats, bool leafctr) {
+    const bool pers = mode == NQ_MODE_PERSISTENT;
+    if (pers) {
+        if (stats)
+            return leafctr ? kernel_ptr<true, true, true, LOOP>() : kernel_ptr<true, true, false, LOOP>();
+        return leafctr ? kernel_ptr<true, false, true, LOOP>() : kernel_ptr<true, false, false, LOOP>();
+    }
+    if (stats)
+        return leafctr ? kernel_ptr<false, true, true, LOOP>() : kernel_ptr<false, true, false, LOOP>();
+    return leafctr ? kernel_ptr<false, false, true, LOOP>() : kernel_ptr<false, false, false, LOOP>();
+}
+
+// Inner-loop form: NQ_DFS_LOOP=0/1/2 in the environment overrides the default
+// (for measurements).
+static int loop_form() {
+    static const int form = [] {
+        const char* e = std::getenv("NQ_DFS_LOOP");
+        if (e && (e[0] == '0' || e[0] == '1' || e[0] == '2') && e[1] == 0) return e[0] - '0';
+        return kDefaultLoop;
+    }();
+    return form;
 }
 
 static const void* select_kernel(uint32_t mode, bool stats, bool leafctr) {
-    const bool pers = mode == NQ_MODE_PERSISTENT;
-    if (pers) {
-        if (stats) return leafctr ? kernel_ptr<true, true, true>() : kernel_ptr<true, true, false>();
-        return leafctr ? kernel_ptr<true, false, true>() : kernel_ptr<true, false, false>();
+    switch (loop_form()) {
+        case 1: return select_kernel_loop<1>(mode, stats, leafctr);
+        case 2: return select_kernel_loop<2>(mode, stats, leafctr);
+        default: return select_kernel_loop<0>(mode, stats, leafctr);
     }
-    if (stats) return leafctr ? kernel_ptr<false, true, true>() : kernel_ptr<false, true, false>();
-    return leafctr ? kernel_ptr<false, false, true>() : kernel_ptr<false, false, false>();
 }
 
 int device_info(DeviceInfo* out) {
@@ -305,6 +490,17 @@ int launch_zero_u64(unsigned long long* dst, uint64_t count, void* stream) {
     const uint64_t grid = (count + block - 1) / block;
     hipLaunchKernelGGL(nq_zero_u64_kernel, dim3((uint32_t)grid), dim3(block), 0,
                        (hipStream_t)stream, dst, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
+    return NQ_OK;
+}
+
+int launch_slot_init(const SlotInit* recs, uint32_t count, uint32_t* inst_n, uint32_t* remaining,
+                     unsigned long long* totals, uint32_t* gen, void* stream) {
+    if (count == 0) return NQ_OK;
+    const uint32_t block = 256;
+    hipLaunchKernelGGL(nq_slot_init_kernel, dim3((count + block - 1) / block), dim3(block), 0,
+                       (hipStream_t)stream, recs, count, inst_n, remaining, totals, gen);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
     return NQ_OK;

@@ -46,6 +46,29 @@ struct DfsParams {
     uint32_t frames;                // LDS stack frames per lane
     uint32_t refill_every;          // DFS steps between scheduler visits
     uint32_t reverse;               // persistent: claim entries from the last one down
+    // Serving (all null / 0 otherwise).  Entries live in a ring: logical entry
+    // i is physical (base + i) mod wrap.  Every retired entry decrements
+    // remaining[inst]; the lane that takes it to zero publishes the instance's
+    // total to host-visible memory: host_val[inst] = total, then
+    // host_flag[inst] = inst_gen[inst].
+    uint64_t base;
+    uint64_t wrap;
+    uint32_t ninst;                 // instances (slots) when inst != nullptr: ids >= ninst
+                                    // are never used to index (the entry is rejected)
+    uint32_t pad2;
+    uint32_t* remaining;
+    const uint32_t* inst_gen;
+    unsigned long long* host_val;
+    unsigned long long* host_flag;
+};
+
+// One request slot initialisation (serving): slot id, board size, entries,
+// generation.  Applied by a kernel before the epoch that uses the slot.
+struct SlotInit {
+    uint32_t slot;
+    uint32_t n;
+    uint32_t entries;
+    uint32_t gen;
 };
 
 // Count reported for an entry that needs more stack frames than the launch has.
@@ -87,6 +110,11 @@ int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t
 // Enqueues the DFS kernel (and, for the persistent mode, the zeroing of
 // *P.head) on `stream`.  Returns NQ_OK or NQ_EDEVICE.
 int launch_dfs(const LaunchCfg& cfg, const DfsParams& P, void* stream);
+
+// Enqueues the slot initialisations recs[0..count) (device array) on `stream`:
+// inst_n[slot] = n, remaining[slot] = entries, totals[slot] = 0, gen[slot] = gen.
+int launch_slot_init(const SlotInit* recs, uint32_t count, uint32_t* inst_n, uint32_t* remaining,
+                     unsigned long long* totals, uint32_t* gen, void* stream);
 
 // Enqueues dst[0..count) = 0 with a kernel (no memset node in captured graphs).
 int launch_zero_u64(unsigned long long* dst, uint64_t count, void* stream);

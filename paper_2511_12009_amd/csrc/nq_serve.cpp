@@ -1,0 +1,583 @@
+// Serving loop: continuous batching of count requests on one GPU.
+//
+// Requests (a full count Q(n), or the weighted sum over a contiguous slice of
+// a device-resident frontier) arrive at any time.  A scheduler thread admits
+// them in arrival order while request slots, work-ring space and the stack
+// frames of the epoch kernel allow, writes their subproblems into a
+// device-resident ring (host frontier + H2D for counts, device-to-device copies
+// out of the resident frontier for slices), and launches a bounded "epoch": one
+// persistent DFS launch over exactly the entries admitted since the previous
+// epoch.  Epochs alternate between two streams, so the next epoch is queued
+// while the previous one still runs and its waves fill the CUs as the older
+// epoch drains.  Every retired subproblem decrements its request's remaining
+// counter on the device; the lane that retires the last one publishes the
+// request's total to pinned host memory (value, then a generation flag), where
+// the scheduler sees it without waiting for the epoch to end.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "nq_internal.h"
+
+namespace {
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+enum class ReqState { Pending, Admitted, Done };
+
+struct Req {
+    nq_request rq{};
+    ReqState state = ReqState::Pending;
+    int status = NQ_OK;
+    uint64_t count = 0;
+    uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+    uint32_t slot = 0, gen = 0;
+    uint64_t ring_start = 0, ring_len = 0;
+    uint32_t depth = 0;          // COUNT: chosen pre-placement depth
+    uint64_t entries = 0;        // subproblems of this request
+};
+
+struct Resident {                // a frontier kept on the device for slices
+    void* dev = nullptr;
+    uint64_t len = 0;
+    uint32_t *cols = nullptr, *ld = nullptr, *rd = nullptr;
+    uint8_t* w = nullptr;
+};
+
+struct Epoch {
+    hipEvent_t done = nullptr;
+    std::vector<nqi::SlotInit> inits;      // host staging kept alive until `done`
+    std::vector<uint32_t> hc, hl, hr, hi;
+    std::vector<uint8_t> hw;
+};
+
+constexpr uint32_t kHeads = 64;
+constexpr size_t kRingEntryBytes = 4 * 4 + 1;   // cols, ld, rd, inst + weight
+
+}  // namespace
+
+struct nq_server {
+    // configuration
+    uint32_t max_frames = 14;
+    uint32_t max_slots = 4096;
+    uint64_t ring_cap = 0;
+    uint64_t budget = 0;
+    uint64_t resident_bytes = 0;
+    nq_opts launch{};
+    uint32_t cu_count = 0;
+    nqi::LaunchCfg cfg{};
+
+    // device memory
+    void* dev = nullptr;
+    uint32_t *r_cols = nullptr, *r_ld = nullptr, *r_rd = nullptr, *r_inst = nullptr;
+    uint8_t* r_w = nullptr;
+    uint32_t *s_n = nullptr, *s_rem = nullptr, *s_gen = nullptr;
+    unsigned long long* s_tot = nullptr;
+    unsigned long long* heads = nullptr;
+    nqi::SlotInit* d_init = nullptr;       // max_slots records per epoch parity
+    unsigned long long *h_val = nullptr, *h_flag = nullptr;   // pinned, host view
+    unsigned long long *d_val = nullptr, *d_flag = nullptr;   // device view
+    hipStream_t streams[2] = {nullptr, nullptr};
+    std::map<std::pair<uint32_t, uint32_t>, Resident> resident;
+
+    // scheduling state (guarded by mu)
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<uint64_t> pending;
+    std::unordered_map<uint64_t, Req> reqs;
+    struct Admit {                          // a request on the device, in ring order
+        uint64_t ticket, ring_start, ring_len;
+        uint32_t slot, gen;
+        bool done;
+    };
+    std::deque<Admit> admitted;
+    std::vector<uint32_t> free_slots;
+    std::vector<uint32_t> slot_gen;
+    uint64_t next_ticket = 1;
+    uint64_t ring_head = 0, ring_tail = 0;  // logical positions, tail - head in use
+    uint64_t epoch_no = 0;
+    std::deque<Epoch> epochs;
+    bool stop = false;
+    int fatal = NQ_OK;
+    std::thread worker;
+};
+
+namespace nqi {
+
+namespace {
+
+// Smallest depth whose frontier has at least `target` entries, within the
+// server's stack budget (frames) and at most n - 2.
+uint32_t count_depth(uint32_t n, uint32_t max_frames) {
+    if (n <= 3) return n;                       // tiny boards: full pre-placement
+    const uint32_t hi = n - 2;
+    const uint32_t lo = (n >= max_frames + 2) ? std::max<uint32_t>(1, n - 2 - max_frames) : 1u;
+    for (uint32_t k = lo; k <= hi; ++k) {
+        uint64_t f = 0;
+        if (frontier_fill(n, k, nullptr, nullptr, nullptr, nullptr, 0, &f, nullptr) != NQ_OK)
+            break;
+        if (f >= 4096) return k;
+    }
+    return hi;
+}
+
+int ensure_resident(nq_server* s, uint32_t n, uint32_t depth, Resident** out) {
+    auto key = std::make_pair(n, depth);
+    auto it = s->resident.find(key);
+    if (it != s->resident.end()) {
+        *out = &it->second;
+        return NQ_OK;
+    }
+    uint64_t F = 0;
+    int rc = frontier_fill(n, depth, nullptr, nullptr, nullptr, nullptr, 0, &F, nullptr);
+    if (rc != NQ_OK) return rc;
+    const uint64_t bytes = F * 13 + 64;
+    if (s->resident_bytes + bytes > s->budget / 2) return NQ_ENOMEM;
+    std::vector<uint32_t> hc(F), hl(F), hr(F);
+    std::vector<uint8_t> hw(F);
+    rc = frontier_fill(n, depth, hc.data(), hl.data(), hr.data(), hw.data(), F, &F, nullptr);
+    if (rc != NQ_OK) return rc;
+    Resident r;
+    r.len = F;
+    hipError_t e = hipMalloc(&r.dev, bytes);
+    if (e != hipSuccess) { set_hip_error(e); return NQ_ENOMEM; }
+    char* b = static_cast<char*>(r.dev);
+    r.cols = reinterpret_cast<uint32_t*>(b);
+    r.ld = reinterpret_cast<uint32_t*>(b + F * 4);
+    r.rd = reinterpret_cast<uint32_t*>(b + F * 8);
+    r.w = reinterpret_cast<uint8_t*>(b + F * 12);
+    if (F && ((e = hipMemcpy(r.cols, hc.data(), F * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+              (e = hipMemcpy(r.ld, hl.data(), F * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+              (e = hipMemcpy(r.rd, hr.data(), F * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+              (e = hipMemcpy(r.w, hw.data(), F, hipMemcpyHostToDevice)) != hipSuccess)) {
+        set_hip_error(e);
+        (void)hipFree(r.dev);
+        return NQ_EDEVICE;
+    }
+    s->resident_bytes += bytes;
+    auto ins = s->resident.emplace(key, r);
+    *out = &ins.first->second;
+    return NQ_OK;
+}
+
+// Copies `len` entries into the ring at logical position `pos` (wrapping).
+template <class CopyFn>
+void ring_segments(const nq_server* s, uint64_t pos, uint64_t len, CopyFn&& fn) {
+    uint64_t phys = pos % s->ring_cap, done = 0;
+    while (done < len) {
+        const uint64_t take = std::min(len - done, s->ring_cap - phys);
+        fn(phys, done, take);
+        done += take;
+        phys = 0;
+    }
+}
+
+// Collects finished requests and frees their slots and ring space.  mu held.
+void collect(nq_server* s) {
+    const uint64_t t = now_ns();
+    for (auto& a : s->admitted) {
+        if (a.done) continue;
+        const unsigned long long flag = __atomic_load_n(&s->h_flag[a.slot], __ATOMIC_ACQUIRE);
+        if (flag != a.gen) continue;
+        Req& r = s->reqs.at(a.ticket);                 // present until done and polled
+        r.count = __atomic_load_n(&s->h_val[a.slot], __ATOMIC_ACQUIRE);
+        r.t_done = t;
+        r.state = ReqState::Done;
+        a.done = true;
+        s->free_slots.push_back(a.slot);
+    }
+    // Ring space is reclaimed in admission order.
+    while (!s->admitted.empty() && s->admitted.front().done) {
+        s->ring_head = s->admitted.front().ring_start + s->admitted.front().ring_len;
+        s->admitted.pop_front();
+    }
+    if (s->admitted.empty()) s->ring_head = s->ring_tail;
+    // Retire finished epochs' staging buffers.
+    while (!s->epochs.empty() && hipEventQuery(s->epochs.front().done) == hipSuccess) {
+        (void)hipEventDestroy(s->epochs.front().done);
+        s->epochs.pop_front();
+    }
+    s->cv.notify_all();
+}
+
+// Admits pending requests and launches one epoch over them.  mu held; the
+// HIP calls are made with it held too (they only enqueue work).
+int admit_and_launch(nq_server* s) {
+    if (s->pending.empty() || s->free_slots.empty()) return NQ_OK;
+    Epoch ep;
+    const uint64_t epoch_start = s->ring_tail;
+    std::vector<uint64_t> taken;
+    struct SliceCopy { Resident* res; uint64_t src, pos, len; };
+    std::vector<SliceCopy> slices;
+    while (!s->pending.empty() && !s->free_slots.empty()) {
+        Req& r = s->reqs.at(s->pending.front());
+        uint64_t F = 0;
+        Resident* res = nullptr;
+        std::vector<uint32_t> c, l, rr;
+        std::vector<uint8_t> w;
+        if (r.rq.kind == NQ_REQ_COUNT) {
+            int rc = frontier_fill(r.rq.n, r.depth, nullptr, nullptr, nullptr, nullptr, 0, &F,
+                                   nullptr);
+            if (rc != NQ_OK) { r.status = rc; r.state = ReqState::Done; r.t_done = now_ns(); s->pending.pop_front(); continue; }
+        } else {
+            int rc = ensure_resident(s, r.rq.n, r.rq.depth, &res);
+            if (rc != NQ_OK || r.rq.start + r.rq.len > res->len) {
+                r.status = rc != NQ_OK ? rc : NQ_EINVAL;
+                r.state = ReqState::Done;
+                r.t_done = now_ns();
+                s->pending.pop_front();
+                continue;
+            }
+            F = r.rq.len;
+        }
+        if (F > s->ring_cap) {                       // can never fit
+            r.status = NQ_ENOMEM; r.state = ReqState::Done; r.t_done = now_ns();
+            s->pending.pop_front();
+            continue;
+        }
+        if (s->ring_tail + F - s->ring_head > s->ring_cap) break;   // wait for space
+        if (F == 0) {                                  // nothing to search
+            r.count = 0; r.state = ReqState::Done; r.t_admit = r.t_done = now_ns();
+            s->pending.pop_front();
+            continue;
+        }
+        const uint32_t slot = s->free_slots.back();
+        s->free_slots.pop_back();
+        r.slot = slot;
+        r.gen = ++s->slot_gen[slot];
+        r.ring_start = s->ring_tail;
+        r.ring_len = F;
+        r.entries = F;
+        s->ring_tail += F;
+        ep.inits.push_back({slot, r.rq.n, (uint32_t)F, r.gen});
+        if (r.rq.kind == NQ_REQ_COUNT) {
+            const size_t o = ep.hc.size();
+            ep.hc.resize(o + F); ep.hl.resize(o + F); ep.hr.resize(o + F); ep.hw.resize(o + F);
+            uint64_t got = 0;
+            frontier_fill(r.rq.n, r.depth, ep.hc.data() + o, ep.hl.data() + o, ep.hr.data() + o,
+                          ep.hw.data() + o, F, &got, nullptr);
+            ep.hi.insert(ep.hi.end(), F, slot);
+        } else {
+            slices.push_back({res, r.rq.start, r.ring_start, F});
+            ep.hi.insert(ep.hi.end(), F, slot);
+        }
+        r.state = ReqState::Admitted;
+        r.t_admit = now_ns();
+        taken.push_back(s->pending.front());
+        s->admitted.push_back({s->pending.front(), r.ring_start, r.ring_len, slot, r.gen, false});
+        s->pending.pop_front();
+    }
+    if (taken.empty()) return NQ_OK;
+    const uint64_t n_entries = s->ring_tail - epoch_start;
+    hipStream_t st = s->streams[s->epoch_no & 1u];
+    hipError_t e = hipSuccess;
+    // 1. slot records, 2. instance ids of every entry, 3. count frontiers,
+    // 4. slices (device to device).  Host-staged copies go in ring order.
+    const size_t init_off = (s->epoch_no & 1u) * s->max_slots;
+    nqi::SlotInit* d_init = s->d_init + init_off;
+    if ((e = hipMemcpyAsync(d_init, ep.inits.data(), ep.inits.size() * sizeof(SlotInit),
+                            hipMemcpyHostToDevice, st)) != hipSuccess) {
+        set_hip_error(e);
+        return NQ_EDEVICE;
+    }
+    int rc = launch_slot_init(d_init, (uint32_t)ep.inits.size(), s->s_n, s->s_rem, s->s_tot,
+                              s->s_gen, st);
+    if (rc != NQ_OK) return rc;
+    ring_segments(s, epoch_start, n_entries, [&](uint64_t phys, uint64_t off, uint64_t len) {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->r_inst + phys, ep.hi.data() + off, len * 4,
+                               hipMemcpyHostToDevice, st);
+    });
+    // count entries are staged in ring order, skipping the slices' ranges
+    uint64_t staged = 0;
+    uint64_t pos = epoch_start;
+    for (uint64_t tk : taken) {
+        const Req& r = s->reqs.at(tk);
+        if (r.rq.kind == NQ_REQ_COUNT) {
+            ring_segments(s, pos, r.ring_len, [&](uint64_t phys, uint64_t off, uint64_t len) {
+                if (e != hipSuccess) return;
+                const uint64_t so = staged + off;
+                if ((e = hipMemcpyAsync(s->r_cols + phys, ep.hc.data() + so, len * 4,
+                                        hipMemcpyHostToDevice, st)) != hipSuccess) return;
+                if ((e = hipMemcpyAsync(s->r_ld + phys, ep.hl.data() + so, len * 4,
+                                        hipMemcpyHostToDevice, st)) != hipSuccess) return;
+                if ((e = hipMemcpyAsync(s->r_rd + phys, ep.hr.data() + so, len * 4,
+                                        hipMemcpyHostToDevice, st)) != hipSuccess) return;
+                e = hipMemcpyAsync(s->r_w + phys, ep.hw.data() + so, len,
+                                   hipMemcpyHostToDevice, st);
+            });
+            staged += r.ring_len;
+        }
+        pos += r.ring_len;
+    }
+    for (const SliceCopy& sc : slices) {
+        ring_segments(s, sc.pos, sc.len, [&](uint64_t phys, uint64_t off, uint64_t len) {
+            if (e != hipSuccess) return;
+            const uint64_t src = sc.src + off;
+            if ((e = hipMemcpyAsync(s->r_cols + phys, sc.res->cols + src, len * 4,
+                                    hipMemcpyDeviceToDevice, st)) != hipSuccess) return;
+            if ((e = hipMemcpyAsync(s->r_ld + phys, sc.res->ld + src, len * 4,
+                                    hipMemcpyDeviceToDevice, st)) != hipSuccess) return;
+            if ((e = hipMemcpyAsync(s->r_rd + phys, sc.res->rd + src, len * 4,
+                                    hipMemcpyDeviceToDevice, st)) != hipSuccess) return;
+            e = hipMemcpyAsync(s->r_w + phys, sc.res->w + src, len, hipMemcpyDeviceToDevice, st);
+        });
+    }
+    if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
+    // 5. the epoch: one persistent launch over [epoch_start, ring_tail).
+    DfsParams P{};
+    P.cols = s->r_cols; P.ld = s->r_ld; P.rd = s->r_rd; P.weight = s->r_w;
+    P.inst = s->r_inst; P.inst_n = s->s_n; P.ninst = s->max_slots;
+    P.totals = s->s_tot;
+    P.head = s->heads + (s->epoch_no % kHeads);
+    P.len = n_entries;
+    P.frames = s->max_frames;
+    P.refill_every = s->launch.refill_every ? s->launch.refill_every : 512u;
+    P.reverse = 0;                                      // arrival order
+    P.base = epoch_start % s->ring_cap;
+    P.wrap = s->ring_cap;
+    P.remaining = s->s_rem;
+    P.inst_gen = s->s_gen;
+    P.host_val = s->d_val;
+    P.host_flag = s->d_flag;
+    LaunchCfg cfg = s->cfg;
+    const uint64_t waves = (n_entries + 63) / 64;
+    const uint64_t per_wg = cfg.wg_size / 64u;
+    cfg.grid = (uint32_t)std::min<uint64_t>(cfg.grid, (waves + per_wg - 1) / per_wg);
+    if ((rc = launch_dfs(cfg, P, st)) != NQ_OK) return rc;
+    if ((e = hipEventCreateWithFlags(&ep.done, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventRecord(ep.done, st)) != hipSuccess) {
+        set_hip_error(e);
+        return NQ_EDEVICE;
+    }
+    s->epochs.push_back(std::move(ep));
+    ++s->epoch_no;
+    return NQ_OK;
+}
+
+void worker_main(nq_server* s) {
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        collect(s);
+        if (s->fatal == NQ_OK) {
+            int rc = admit_and_launch(s);
+            if (rc != NQ_OK) s->fatal = rc;
+        }
+        const bool busy = !s->admitted.empty() || !s->epochs.empty();
+        if (s->stop && !busy) break;
+        if (busy) {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        } else {
+            s->cv.wait_for(lk, std::chrono::milliseconds(2),
+                           [&] { return s->stop || !s->pending.empty(); });
+        }
+    }
+}
+
+void destroy_all(nq_server* s) {
+    for (hipStream_t st : s->streams)
+        if (st) (void)hipStreamSynchronize(st);
+    for (auto& ep : s->epochs)
+        if (ep.done) (void)hipEventDestroy(ep.done);
+    for (auto& kv : s->resident)
+        if (kv.second.dev) (void)hipFree(kv.second.dev);
+    if (s->dev) (void)hipFree(s->dev);
+    if (s->h_val) (void)hipHostFree(s->h_val);
+    if (s->h_flag) (void)hipHostFree(s->h_flag);
+    for (hipStream_t st : s->streams)
+        if (st) (void)hipStreamDestroy(st);
+    delete s;
+}
+
+}  // namespace
+
+int serve_create(const nq_opts* opts, uint64_t hbm_budget, nq_server** out) {
+    if (!out) return NQ_EINVAL;
+    if (opts && (opts->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
+    nq_server* s = new (std::nothrow) nq_server();
+    if (!s) return NQ_ENOMEM;
+    if (opts) s->launch = *opts;
+    s->budget = hbm_budget ? hbm_budget : (1ull << 30);
+    // Frames: requests whose subproblems need more are refused at submit.
+    s->max_frames = (opts && opts->depth) ? opts->depth : 14u;
+    // Half of the budget is the work ring, the other half resident frontiers.
+    s->ring_cap = std::min<uint64_t>(1ull << 31,
+                                     std::max<uint64_t>(1u << 16, (s->budget / 2) / kRingEntryBytes));
+    s->free_slots.reserve(s->max_slots);
+    for (uint32_t i = 0; i < s->max_slots; ++i) s->free_slots.push_back(s->max_slots - 1 - i);
+    s->slot_gen.assign(s->max_slots, 0);
+    hipError_t e;
+    auto fail = [&](int rc) {
+        destroy_all(s);
+        return rc;
+    };
+    DeviceInfo dev;
+    int rc = device_info(&dev);
+    if (rc != NQ_OK) return fail(rc);
+    s->cu_count = (uint32_t)dev.cu_count;
+    if ((rc = plan_launch(dev, NQ_MODE_PERSISTENT, opts ? opts->wg_size : 0,
+                          opts ? opts->waves_per_cu : 0, s->max_frames, 1, false,
+                          true, &s->cfg)) != NQ_OK)
+        return fail(rc);
+    const uint64_t R = s->ring_cap, S = s->max_slots;
+    const size_t o_ld = R * 4, o_rd = R * 8, o_inst = R * 12, o_w = R * 16;
+    const size_t o_sn = (o_w + R + 255) / 256 * 256, o_rem = o_sn + S * 4, o_gen = o_rem + S * 4;
+    const size_t o_tot = (o_gen + S * 4 + 255) / 256 * 256, o_heads = o_tot + S * 8;
+    const size_t o_init = o_heads + kHeads * 8, bytes = o_init + 2 * S * sizeof(SlotInit);
+    if ((e = hipMalloc(&s->dev, bytes)) != hipSuccess) {
+        set_hip_error(e);
+        return fail(e == hipErrorOutOfMemory ? NQ_ENOMEM : NQ_EDEVICE);
+    }
+    char* b = static_cast<char*>(s->dev);
+    s->r_cols = reinterpret_cast<uint32_t*>(b);
+    s->r_ld = reinterpret_cast<uint32_t*>(b + o_ld);
+    s->r_rd = reinterpret_cast<uint32_t*>(b + o_rd);
+    s->r_inst = reinterpret_cast<uint32_t*>(b + o_inst);
+    s->r_w = reinterpret_cast<uint8_t*>(b + o_w);
+    s->s_n = reinterpret_cast<uint32_t*>(b + o_sn);
+    s->s_rem = reinterpret_cast<uint32_t*>(b + o_rem);
+    s->s_gen = reinterpret_cast<uint32_t*>(b + o_gen);
+    s->s_tot = reinterpret_cast<unsigned long long*>(b + o_tot);
+    s->heads = reinterpret_cast<unsigned long long*>(b + o_heads);
+    s->d_init = reinterpret_cast<SlotInit*>(b + o_init);
+    const unsigned host_flags = hipHostMallocMapped | hipHostMallocCoherent;
+    if ((e = hipHostMalloc((void**)&s->h_val, S * 8, host_flags)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&s->h_flag, S * 8, host_flags)) != hipSuccess) {
+        set_hip_error(e);
+        return fail(NQ_ENOMEM);
+    }
+    std::memset(s->h_val, 0, S * 8);
+    std::memset(s->h_flag, 0, S * 8);
+    if ((e = hipHostGetDevicePointer((void**)&s->d_val, s->h_val, 0)) != hipSuccess ||
+        (e = hipHostGetDevicePointer((void**)&s->d_flag, s->h_flag, 0)) != hipSuccess) {
+        set_hip_error(e);
+        return fail(NQ_EDEVICE);
+    }
+    for (auto& st : s->streams)
+        if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) {
+            set_hip_error(e);
+            return fail(NQ_EDEVICE);
+        }
+    try {
+        s->worker = std::thread(worker_main, s);
+    } catch (...) {
+        return fail(NQ_ENOMEM);
+    }
+    *out = s;
+    return NQ_OK;
+}
+
+int serve_submit(nq_server* s, const nq_request* rq, uint64_t* ticket) {
+    if (!s || !rq || !ticket) return NQ_EINVAL;
+    if (rq->n < 1 || rq->n > NQ_MAX_N || rq->reserved != 0) return NQ_EINVAL;
+    Req r;
+    r.rq = *rq;
+    if (rq->kind == NQ_REQ_COUNT) {
+        r.depth = rq->depth ? rq->depth : count_depth(rq->n, s->max_frames);
+        if (r.depth > rq->n) return NQ_EINVAL;
+    } else if (rq->kind == NQ_REQ_SLICE) {
+        if (rq->depth < 1 || rq->depth > rq->n) return NQ_EINVAL;
+        if (rq->start + rq->len < rq->start) return NQ_EINVAL;
+        r.depth = rq->depth;
+    } else {
+        return NQ_EINVAL;
+    }
+    if (frames_needed(rq->n, r.depth) > s->max_frames) return NQ_EINVAL;   // LDS footprint
+    if (!leafctr_ok(rq->n, r.depth)) return NQ_EINVAL;                   // row counter range
+    r.t_submit = now_ns();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->fatal != NQ_OK) return s->fatal;
+    if (s->pending.size() >= 65536) return NQ_EFULL;
+    const uint64_t t = s->next_ticket++;
+    s->reqs.emplace(t, r);
+    s->pending.push_back(t);
+    *ticket = t;
+    s->cv.notify_all();
+    return NQ_OK;
+}
+
+int serve_poll(nq_server* s, uint64_t ticket, nq_result* out, uint64_t wait_ns) {
+    if (!s || !out) return NQ_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return NQ_ENOENT;
+    if (it->second.state != ReqState::Done && wait_ns) {
+        const auto deadline = std::chrono::steady_clock::now() + std::chrono::nanoseconds(wait_ns);
+        s->cv.wait_until(lk, deadline, [&] {
+            return s->fatal != NQ_OK || s->reqs.at(ticket).state == ReqState::Done;
+        });
+        it = s->reqs.find(ticket);
+    }
+    const Req& r = it->second;
+    if (r.state != ReqState::Done) return s->fatal != NQ_OK ? s->fatal : NQ_EAGAIN;
+    out->status = r.status;
+    out->reserved = 0;
+    out->count = r.count;
+    out->entries = r.entries;
+    out->t_submit_ns = r.t_submit;
+    out->t_admit_ns = r.t_admit;
+    out->t_done_ns = r.t_done;
+    s->reqs.erase(it);
+    return NQ_OK;
+}
+
+int serve_destroy(nq_server* s) {
+    if (!s) return NQ_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        // requests never admitted are dropped
+        for (uint64_t t : s->pending) s->reqs.erase(t);
+        s->pending.clear();
+        s->cv.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    const int fatal = s->fatal;
+    destroy_all(s);
+    return fatal;
+}
+
+}  // namespace nqi
+
+extern "C" int nq_serve_create(const nq_opts* opts, uint64_t hbm_budget_bytes, nq_server** out) {
+    try {
+        return nqi::serve_create(opts, hbm_budget_bytes, out);
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
+}
+
+extern "C" int nq_serve_submit(nq_server* s, const nq_request* req, uint64_t* out_ticket) {
+    try {
+        return nqi::serve_submit(s, req, out_ticket);
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
+}
+
+extern "C" int nq_serve_poll(nq_server* s, uint64_t ticket, nq_result* out) {
+    return nqi::serve_poll(s, ticket, out, 0);
+}
+
+extern "C" int nq_serve_wait(nq_server* s, uint64_t ticket, nq_result* out, uint64_t timeout_ns) {
+    return nqi::serve_poll(s, ticket, out, timeout_ns ? timeout_ns : 1);
+}
+
+extern "C" int nq_serve_destroy(nq_server* s) { return nqi::serve_destroy(s); }

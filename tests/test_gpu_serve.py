@@ -1,0 +1,87 @@
+"""GPU: the serving loop.  Results are exact, identical alone and in a mix of
+concurrent requests, and slices of the N=21 depth-6 frontier add up to Q(21)."""
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _nq():
+    import paper_2511_12009_amd as nq
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return nq
+
+
+def _say(*a):
+    print("[gpu-serve]", *a, flush=True)
+
+
+def test_counts_alone_and_in_a_mix(known_counts):
+    nq = _nq()
+    ns = seeded_inputs.serve_count_ns(40)
+    with nq.Server() as srv:
+        alone = {}
+        for n in sorted(set(ns)):
+            _say("alone", n)
+            r = srv.wait(srv.submit_count(n), timeout_s=60)
+            assert r["status"] == 0 and r["count"] == known_counts[n], n
+            alone[n] = r["count"]
+        _say("mix of", len(ns))
+        tickets = [srv.submit_count(n) for n in ns]
+        slices = [srv.submit_slice(16, 5, s, 200) for s in range(0, 4000, 400)]
+        for n, t in zip(ns, tickets):
+            r = srv.wait(t, timeout_s=120)
+            assert r["status"] == 0 and r["count"] == alone[n]
+            assert r["t_submit_ns"] <= r["t_admit_ns"] <= r["t_done_ns"]
+        pre, w = oracle.frontier(16, 5)
+        for i, t in enumerate(slices):
+            r = srv.wait(t, timeout_s=120)
+            lo = i * 400
+            ref, _ = oracle.count_prefixes(16, pre[lo:lo + 200], threads=8)
+            assert r["count"] == int((ref * w[lo:lo + 200].astype(np.uint64)).sum())
+            assert r["entries"] == 200
+
+
+def test_small_boards_and_bad_requests(known_counts):
+    nq = _nq()
+    with nq.Server() as srv:
+        for n in (1, 2, 3, 4, 5, 8):
+            r = srv.wait(srv.submit_count(n), timeout_s=30)
+            assert r["count"] == known_counts[n], n
+        with pytest.raises(nq.NQError):
+            srv.submit_count(29)
+        with pytest.raises(nq.NQError):
+            srv.submit_slice(21, 0, 0, 10)
+        with pytest.raises(nq.NQError):
+            srv.submit_count(24, depth=2)          # needs more stack than the server has
+        t = srv.submit_slice(12, 3, 10 ** 6, 5)   # past the end of the frontier
+        r = srv.wait(t, timeout_s=30)
+        assert r["status"] != 0
+        with pytest.raises(nq.NQError):
+            srv.poll(t)                            # ticket already collected
+
+
+def test_n21_slices_sum_to_q21(known_counts):
+    """Every 4096-entry slice of the N=21 depth-6 frontier (the last one short),
+    submitted at once; the weighted slice sums add up to Q(21)."""
+    nq = _nq()
+    F = nq.frontier_size(21, 6)
+    starts = list(range(0, F, 4096))
+    assert len(starts) == 1092
+    with nq.Server(hbm_budget=2 << 30) as srv:
+        _say("n21 slices", len(starts))
+        tickets = [srv.submit_slice(21, 6, s, min(4096, F - s)) for s in starts]
+        total = 0
+        for i, t in enumerate(tickets):
+            r = srv.wait(t, timeout_s=300)
+            assert r["status"] == 0
+            total += r["count"]
+            if i % 200 == 0:
+                _say("slices done", i)
+        assert total == known_counts[21]
