@@ -10,9 +10,12 @@ value = DFS nodes per second = nodes(20, k) / step time, where nodes(20, k) is
 the oracle's node count (queens placed in rows k..18 below every pre-placed
 prefix), read from tests/golden/oracle_runs.txt.
 
-Printed: one JSON line (rank 0) with the metric, the "plain" form (one launch
-per row-0 column over the same frontier), the end-to-end nq_count wall time,
-the int-ALU roofline of the DFS kernel and the oracle timed on the host cores.
+The pre-placement depth and launch shape come from nq_autotune (depths 5..8)
+unless --depth is given.  Printed: one JSON line with the metric, the "plain"
+form (one launch per row-0 column over the same frontier), the end-to-end
+nq_count wall time, the int-ALU roofline of the DFS kernel, the ragged
+256-instance batch (one graph replay), the serving loop at a few request
+rates (p50/p99 latency, throughput) and the oracle timed on the host cores.
 """
 import argparse
 import json
@@ -52,6 +55,108 @@ def golden_nodes(n, k):
     return None
 
 
+def known_counts():
+    """Published counts (tests/golden/known_counts.txt)."""
+    out = {}
+    with open(os.path.join(ROOT, "tests", "golden", "known_counts.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                n, c = line.split()[:2]
+                out[int(n)] = int(c)
+    return out
+
+
+def bench_batch(nq, known):
+    """Ragged batch: 256 board sizes N_i uniform in 8..19 (seeded), one graph replay."""
+    import seeded_inputs
+    ns = seeded_inputs.ragged_batch_ns()
+    t = time.perf_counter()
+    with nq.Batch(ns) as b:
+        build_ms = (time.perf_counter() - t) * 1e3
+        got, ms = b.run(timing=True)      # first replay (warm)
+        got, ms = b.run(timing=True)
+        entries = b.entries
+    ok = got == [known[n] for n in ns]
+    if not ok:
+        raise SystemExit("bench.py: ragged batch totals differ from the published counts")
+    return {"instances": len(ns), "subproblems": entries, "replay_ms": ms,
+            "build_ms": build_ms, "exact": ok,
+            "form": "one persistent launch over every instance's frontier, HIP graph replay"}
+
+
+def bench_serving(nq, known, rates, seconds):
+    """Poisson COUNT(N in 10..18) requests with N=21 depth-6 4096-entry slices
+    interleaved; per rate: p50/p99 latency and throughput."""
+    import seeded_inputs
+    F21 = nq.frontier_size(21, 6)
+    res = []
+    with nq.Server(hbm_budget=2 << 30) as srv:
+        srv.wait(srv.submit_slice(21, 6, 0, 1))          # builds the resident frontier
+        for rate in rates:
+            n_req = max(1, int(rate * seconds))
+            arr = seeded_inputs.poisson_arrivals(n_req, rate)
+            ns = seeded_inputs.serve_count_ns(n_req)
+            s_rate = max(1.0, rate / 8)
+            s_arr = seeded_inputs.poisson_arrivals(max(1, int(s_rate * seconds)), s_rate,
+                                                   seed=seeded_inputs.SERVE_SEED + 1)
+            events = sorted([(t, "count", i) for i, t in enumerate(arr)] +
+                            [(t, "slice", i) for i, t in enumerate(s_arr)])
+            tickets = []
+            t0 = time.perf_counter()
+            for t, kind, i in events:
+                dt = t - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                if kind == "count":
+                    tickets.append(("count", ns[i], srv.submit_count(ns[i])))
+                else:
+                    start = (i * 4096) % F21
+                    tickets.append(("slice", None, srv.submit_slice(21, 6, start,
+                                                                    min(4096, F21 - start))))
+            lat = {"count": [], "slice": []}
+            for kind, n, tk in tickets:
+                r = srv.wait(tk, timeout_s=300)
+                if r["status"] != 0 or (kind == "count" and r["count"] != known[n]):
+                    raise SystemExit(f"bench.py: serving result wrong ({kind}, N={n})")
+                lat[kind].append((r["t_done_ns"] - r["t_submit_ns"]) / 1e6)
+            wall = time.perf_counter() - t0
+            row = {"rate_count_per_s": rate, "rate_slice_per_s": s_rate,
+                   "requests": len(tickets), "wall_s": wall,
+                   "throughput_req_per_s": len(tickets) / wall}
+            for kind in ("count", "slice"):
+                if lat[kind]:
+                    row[f"{kind}_p50_ms"] = float(np.percentile(lat[kind], 50))
+                    row[f"{kind}_p99_ms"] = float(np.percentile(lat[kind], 99))
+            res.append(row)
+            print(f"[bench] serving {json.dumps(row)}", file=sys.stderr, flush=True)
+    return res
+
+
+def profile_run(nq, torch, k, args):
+    """A short program for rocprofv3 counter passes: a plain copy of known size,
+    then one DFS launch of the benchmark workload."""
+    dev = torch.device("cuda:0")
+    src = torch.empty(64 << 20, dtype=torch.int32, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)                                   # 256 MiB read + 256 MiB written
+    torch.cuda.synchronize()
+    del src, dst
+    cols, ld, rd, w = nq.frontier(N, k)
+    t = [torch.from_numpy(x.view(np.int32)).to(dev) for x in (cols, ld, rd)]
+    tw = torch.from_numpy(w).to(dev)
+    counts = torch.empty(len(cols), dtype=torch.int64, device=dev)
+    total = torch.zeros(1, dtype=torch.int64, device=dev)
+    _, _, ms = nq.count_subproblems(N, *t, weight=tw, counts=counts, total=total, depth=k,
+                                    timing=True, waves_per_cu=args.waves_per_cu,
+                                    refill_every=args.refill)
+    if int(total.item()) != EXPECT:
+        raise SystemExit(f"bench.py: profile total {int(total.item())} != {EXPECT}")
+    print(f"[bench] profile: copy 256 MiB, DFS N={N} k={k} F={len(cols)} kernel {ms:.1f} ms",
+          file=sys.stderr, flush=True)
+
+
 def cpu_baseline(k, budget_s):
     """The oracle on a seeded sample of the N=20 frontier, all host cores."""
     import oracle
@@ -81,7 +186,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--depth", type=int, default=6)
+    ap.add_argument("--depth", type=int, default=0, help="0 = autotune over 5..8")
+    ap.add_argument("--tune-ms", type=float, default=40000.0)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--serve-rates", default="25,100", help="COUNT requests/s, comma list")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
@@ -89,6 +198,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="counter runs: one 256 MiB device copy (calibrates the HBM byte "
+                         "counters), then one persistent DFS launch at --depth; no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -99,7 +211,24 @@ def main():
     import torch
     import paper_2511_12009_amd as nq
 
-    k = args.depth
+    if args.profile:
+        profile_run(nq, torch, args.depth or 8, args)
+        return
+
+    tuned = None
+    if args.depth == 0:
+        print("[bench] autotune N=20 over depths 5..8", file=sys.stderr, flush=True)
+        tuned = nq.autotune(N, 5, 8, budget_ms=args.tune_ms)
+        print(f"[bench] tuned {tuned}", file=sys.stderr, flush=True)
+        if tuned["count"] != EXPECT:
+            raise SystemExit(f"bench.py: autotune count {tuned['count']} != {EXPECT}")
+        k = tuned["depth"]
+        if not args.waves_per_cu:
+            args.waves_per_cu = tuned["waves_per_cu"]
+        if not args.refill:
+            args.refill = tuned["refill_every"]
+    else:
+        k = args.depth
     cols, ld, rd, w = nq.frontier(N, k)
     F = len(cols)
     dev = torch.device("cuda:0")
@@ -195,6 +324,18 @@ def main():
         out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK / 1e12,
                            "unit": "Tint32op/s", "frac": achieved / INT_PEAK, "traffic": None,
                            "ops_per_node": OPS_PER_NODE, "kernel_ms": kern_ms}
+    out["launch"] = {"waves_per_cu": args.waves_per_cu, "refill_every": args.refill,
+                     "wg_size": args.wg, "autotune": tuned}
+    del t_cols, t_ld, t_rd, t_w, counts
+    torch.cuda.empty_cache()
+    known = known_counts()
+    if not args.no_batch:
+        print("[bench] ragged batch (256 instances)", file=sys.stderr, flush=True)
+        out["batch"] = bench_batch(nq, known)
+    rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
+    if rates:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        out["serving"] = bench_serving(nq, known, rates, args.serve_seconds)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(k, args.cpu_seconds)
