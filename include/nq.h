@@ -94,6 +94,25 @@ int nq_frontier(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld, uint32
 int nq_frontier_runs(uint32_t n, uint32_t depth, uint64_t* offsets, uint32_t capacity,
                      uint32_t* out_runs);
 
+/*
+ * nq_expand -- the frontier `rows` rows deeper, computed on the device.
+ *
+ * Algorithm 1 continued on the GPU: for len device-resident subproblems
+ * (d_cols, d_ld, d_rd; d_weight nullable) of an n board, writes every placement
+ * of rows (1..3) more queens below each of them, as Somers triples of the
+ * deeper row, into d_ocols, d_old, d_ord (d_oweight nullable; children inherit
+ * their parent's weight, 1 when d_weight is NULL).  Order: all children of entry
+ * 0 (lowest column first), then entry 1, ...; expanding nq_frontier(n, k) gives
+ * nq_frontier(n, k + rows) exactly.  With d_ocols, d_old or d_ord NULL only
+ * *out_len (the number of children) is computed; capacity < *out_len is
+ * NQ_ERANGE.  The call allocates scratch device memory and waits on `stream`
+ * (hipStream_t or NULL) for the size and, when writing, for the result.
+ */
+int nq_expand(uint32_t n, uint32_t rows, const uint32_t* d_cols, const uint32_t* d_ld,
+              const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len, uint32_t* d_ocols,
+              uint32_t* d_old, uint32_t* d_ord, uint8_t* d_oweight, uint64_t capacity,
+              uint64_t* out_len, void* stream);
+
 /* Scheduling modes of the DFS kernels. */
 enum nq_mode {
     NQ_MODE_AUTO = 0,        /* persistent                                            */
@@ -134,8 +153,9 @@ typedef struct nq_opts {
 /*
  * nq_count -- Q(n): the number of ways to place n non-attacking queens.
  *
- * Builds the frontier of depth opts->depth on the host (nq_frontier), copies it
- * to device memory owned by the library, runs the DFS kernels (Algorithm 2 with
+ * Builds the frontier of depth opts->depth (on the host, nq_frontier; for depth
+ * >= 7 a shallower one on the host that nq_expand deepens on the device) in
+ * device memory owned by the library, runs the DFS kernels (Algorithm 2 with
  * the last-row step of Algorithm 3, one subproblem per lane) and returns the
  * weighted total in *out_total.  Synchronous: returns after the result is on the
  * host.  If opts->counts_out is set, it receives the per-subproblem counts in

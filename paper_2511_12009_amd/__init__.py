@@ -10,6 +10,7 @@ Functions (same names as the C entry points, without the ``nq_`` prefix):
   frontier(n, depth)                         -> (cols, ld, rd, weight) numpy arrays
   frontier_size(n, depth)                    -> F
   frontier_runs(n, depth)                    -> start of each row-0 column's entries, then F
+  expand(n, rows, cols, ld, rd, weight=None)  -> the frontier rows deeper, on the device
   count(n, depth=0, mode="persistent", ...)  -> Q(n)   (and counts / kernel ms)
   count_subproblems(n, cols, ld, rd, ...)    -> per-entry counts and weighted total
   count_batch(ns, depths=None, ...)          -> [Q(n) for n in ns]
@@ -26,6 +27,7 @@ from ._native import (  # noqa: F401
     count,
     count_batch,
     count_subproblems,
+    expand,
     frontier,
     frontier_runs,
     frontier_size,

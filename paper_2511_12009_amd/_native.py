@@ -96,6 +96,8 @@ def lib():
         L.nq_frontier.restype = ct.c_int
         L.nq_frontier_runs.argtypes = [u32, u32, pu64, u32, pu32]
         L.nq_frontier_runs.restype = ct.c_int
+        L.nq_expand.argtypes = [u32, u32, vp, vp, vp, vp, u64, vp, vp, vp, vp, u64, pu64, vp]
+        L.nq_expand.restype = ct.c_int
         L.nq_count.argtypes = [u32, ct.POINTER(NqOpts), pu64]
         L.nq_count.restype = ct.c_int
         L.nq_count_subproblems.argtypes = [u32, vp, vp, vp, vp, u64, vp, vp, ct.POINTER(NqOpts)]
@@ -187,6 +189,27 @@ def frontier(n: int, depth: int):
                              w.ctypes.data_as(ct.POINTER(ct.c_uint8)), f, ct.byref(ln)),
            "nq_frontier")
     return cols[:f], ld[:f], rd[:f], w[:f]
+
+
+def expand(n: int, rows: int, cols, ld, rd, weight=None, stream=None):
+    """Children `rows` rows below device-resident triples (nq_expand): returns
+    (cols, ld, rd, weight) int32/uint8 CUDA tensors in canonical order."""
+    import torch
+    length = cols.numel()
+    st = _stream_handle(stream)
+    cnt = ct.c_uint64()
+    wp = None if weight is None else weight.data_ptr()
+    _check(lib().nq_expand(n, rows, cols.data_ptr(), ld.data_ptr(), rd.data_ptr(), wp, length,
+                           None, None, None, None, 0, ct.byref(cnt), st), "nq_expand")
+    m = cnt.value
+    oc = torch.empty(max(m, 1), dtype=torch.int32, device=cols.device)
+    ol = torch.empty_like(oc)
+    orr = torch.empty_like(oc)
+    ow = torch.empty(max(m, 1), dtype=torch.uint8, device=cols.device)
+    _check(lib().nq_expand(n, rows, cols.data_ptr(), ld.data_ptr(), rd.data_ptr(), wp, length,
+                           oc.data_ptr(), ol.data_ptr(), orr.data_ptr(), ow.data_ptr(), m,
+                           ct.byref(cnt), st), "nq_expand")
+    return oc[:m], ol[:m], orr[:m], ow[:m]
 
 
 def count(n: int, depth: int = 0, mode="persistent", wg_size: int = 0, waves_per_cu: int = 0,

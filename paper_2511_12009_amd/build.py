@@ -20,7 +20,7 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           f"--offload-arch={ARCH}", "-I", os.path.join(os.path.dirname(HERE), "include")]
 
-SOURCES = ["nq_frontier.cpp", "nq_dfs.hip", "nq_api.cpp", "nq_batch.cpp", "nq_tune.cpp",
+SOURCES = ["nq_frontier.cpp", "nq_dfs.hip", "nq_expand.hip", "nq_api.cpp", "nq_batch.cpp", "nq_tune.cpp",
            "nq_serve.cpp"]
 
 

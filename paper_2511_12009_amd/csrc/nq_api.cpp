@@ -153,6 +153,29 @@ extern "C" const char* nq_strerror(int status) {
 
 extern "C" int nq_last_hip_error(void) { return g_last_hip_error; }
 
+extern "C" int nq_expand(uint32_t n, uint32_t rows, const uint32_t* d_cols, const uint32_t* d_ld,
+                         const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len,
+                         uint32_t* d_ocols, uint32_t* d_old, uint32_t* d_ord, uint8_t* d_oweight,
+                         uint64_t capacity, uint64_t* out_len, void* stream) {
+    if (n < 1 || n > NQ_MAX_N || rows < 1 || rows > 3 || !out_len) return NQ_EINVAL;
+    if (len && (!d_cols || !d_ld || !d_rd)) return NQ_EINVAL;
+    try {
+        DevBuf scratch;
+        int rc = scratch.alloc(expand_scratch_bytes(len));
+        if (rc != NQ_OK) return rc;
+        rc = expand_device(n, rows, d_cols, d_ld, d_rd, d_weight, len, d_ocols, d_old, d_ord,
+                           d_oweight, capacity, out_len, scratch.p, stream);
+        if (rc == NQ_OK && d_ocols) {
+            // the scratch is freed on return: wait for the write pass
+            hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+            if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
+        }
+        return rc;
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
+}
+
 extern "C" int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
                                     const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len,
                                     uint64_t* d_counts, uint64_t* d_total, const nq_opts* opts) {
@@ -190,24 +213,68 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
     const uint32_t depth = local.depth ? local.depth : auto_depth(n);
     if (depth > n) return NQ_EINVAL;
     try {
-        uint64_t F = 0;
+        // Frontier: built on the host at a shallow depth and, for deep
+        // pre-placement, expanded on the device (nq_expand) by up to 2 rows.
+        const uint32_t host_depth = depth >= 7 ? depth - std::min<uint32_t>(2, depth - 5) : depth;
+        const uint32_t rows = depth - host_depth;
+        uint64_t Fh = 0;
         std::vector<uint64_t> first_row;
-        int rc = frontier_fill(n, depth, nullptr, nullptr, nullptr, nullptr, 0, &F, nullptr);
+        int rc = frontier_fill(n, host_depth, nullptr, nullptr, nullptr, nullptr, 0, &Fh, nullptr);
         if (rc != NQ_OK) return rc;
-        if (opts && opts->counts_out && opts->counts_capacity < F) return NQ_ERANGE;
-        std::vector<uint32_t> hc(F), hl(F), hr(F);
-        std::vector<uint8_t> hw(F);
-        rc = frontier_fill(n, depth, hc.data(), hl.data(), hr.data(), hw.data(), F, &F,
+        std::vector<uint32_t> hc(Fh), hl(Fh), hr(Fh);
+        std::vector<uint8_t> hw(Fh);
+        rc = frontier_fill(n, host_depth, hc.data(), hl.data(), hr.data(), hw.data(), Fh, &Fh,
                            &first_row);
         if (rc != NQ_OK) return rc;
         hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
+        DevBuf shallow, scratch;
+        uint64_t F = Fh;
+        if (rows) {
+            // shallow frontier + expansion scratch, then the size of the deep one
+            if ((rc = shallow.alloc(Fh * 13 + 64)) != NQ_OK) return rc;
+            char* sb = shallow.as<char>();
+            if (Fh) {
+                NQ_HIP(hipMemcpyAsync(sb, hc.data(), Fh * 4, hipMemcpyHostToDevice, s));
+                NQ_HIP(hipMemcpyAsync(sb + Fh * 4, hl.data(), Fh * 4, hipMemcpyHostToDevice, s));
+                NQ_HIP(hipMemcpyAsync(sb + Fh * 8, hr.data(), Fh * 4, hipMemcpyHostToDevice, s));
+                NQ_HIP(hipMemcpyAsync(sb + Fh * 12, hw.data(), Fh, hipMemcpyHostToDevice, s));
+            }
+            if ((rc = scratch.alloc(expand_scratch_bytes(Fh))) != NQ_OK) return rc;
+            rc = expand_device(n, rows, reinterpret_cast<uint32_t*>(sb),
+                               reinterpret_cast<uint32_t*>(sb + Fh * 4),
+                               reinterpret_cast<uint32_t*>(sb + Fh * 8),
+                               reinterpret_cast<uint8_t*>(sb + Fh * 12), Fh, nullptr, nullptr,
+                               nullptr, nullptr, 0, &F, scratch.p, s);
+            if (rc != NQ_OK) return rc;
+            // row-0 runs of the deep frontier: the expansion offsets of the
+            // shallow runs' starts (offsets[Fh] = F)
+            const uint64_t* offs = scratch.as<uint64_t>() + (Fh + 1);
+            for (auto& o : first_row) {
+                uint64_t v = 0;
+                NQ_HIP(hipMemcpy(&v, offs + o, 8, hipMemcpyDeviceToHost));
+                o = v;
+            }
+        }
+        if (opts && opts->counts_out && opts->counts_capacity < F) return NQ_ERANGE;
         DevBuf buf;
         // Layout: cols | ld | rd | counts | total | weight.
         const size_t off_ld = F * 4, off_rd = 2 * F * 4, off_cnt = (3 * F * 4 + 7) & ~size_t(7);
         const size_t off_tot = off_cnt + F * 8, off_w = off_tot + 8;
         if ((rc = buf.alloc(off_w + F)) != NQ_OK) return rc;
         char* b = buf.as<char>();
-        if (F) {
+        if (rows) {
+            char* sb = shallow.as<char>();
+            uint64_t got = 0;
+            rc = expand_device(n, rows, reinterpret_cast<uint32_t*>(sb),
+                               reinterpret_cast<uint32_t*>(sb + Fh * 4),
+                               reinterpret_cast<uint32_t*>(sb + Fh * 8),
+                               reinterpret_cast<uint8_t*>(sb + Fh * 12), Fh,
+                               reinterpret_cast<uint32_t*>(b),
+                               reinterpret_cast<uint32_t*>(b + off_ld),
+                               reinterpret_cast<uint32_t*>(b + off_rd),
+                               reinterpret_cast<uint8_t*>(b + off_w), F, &got, scratch.p, s);
+            if (rc != NQ_OK) return rc;
+        } else if (F) {
             NQ_HIP(hipMemcpyAsync(b, hc.data(), F * 4, hipMemcpyHostToDevice, s));
             NQ_HIP(hipMemcpyAsync(b + off_ld, hl.data(), F * 4, hipMemcpyHostToDevice, s));
             NQ_HIP(hipMemcpyAsync(b + off_rd, hr.data(), F * 4, hipMemcpyHostToDevice, s));

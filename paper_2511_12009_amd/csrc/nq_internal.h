@@ -119,6 +119,16 @@ int launch_slot_init(const SlotInit* recs, uint32_t count, uint32_t* inst_n, uin
 // Enqueues dst[0..count) = 0 with a kernel (no memset node in captured graphs).
 int launch_zero_u64(unsigned long long* dst, uint64_t count, void* stream);
 
+// Device frontier expansion (nq_expand.hip): scratch size for `len` parents,
+// and the expansion itself; *out_len gets the child count (the call waits on
+// the stream for it).  With null outputs only the size is computed; the scan
+// offsets stay in the scratch at uint64 index len + 1 + i.
+size_t expand_scratch_bytes(uint64_t len);
+int expand_device(uint32_t n, uint32_t rows, const uint32_t* cols, const uint32_t* ld,
+                  const uint32_t* rd, const uint8_t* w, uint64_t len, uint32_t* ocols,
+                  uint32_t* old, uint32_t* ord, uint8_t* ow, uint64_t cap, uint64_t* out_len,
+                  void* scratch, void* stream);
+
 // Tuning results remembered for this process (nq_autotune), by device and n.
 int tune_lookup(uint32_t n, nq_tuned* out);
 

@@ -216,3 +216,32 @@ def test_node_counts_per_subproblem(n, k):
         assert int(got_nodes.sum()) == int(g[4])
         assert _digest(got_nodes) == g[6]
         assert _digest(counts.cpu().numpy().view(np.uint64)) == g[5]
+
+
+@pytest.mark.parametrize("n,k,rows", [(12, 2, 1), (13, 3, 2), (16, 4, 3), (11, 1, 3), (20, 5, 2)])
+def test_device_expansion_matches_oracle_frontier(n, k, rows):
+    """nq_expand of the depth-k frontier is the oracle's depth k+rows frontier."""
+    nq = _nq()
+    cols, ld, rd, w = nq.frontier(n, k)
+    t = [_dev(x) for x in (cols, ld, rd)]
+    _say("expand", n, k, rows)
+    oc, ol, orr, ow = nq.expand(n, rows, *t, weight=torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    rc, rl, rr, rw = oracle.frontier_masks(n, k + rows)
+    np.testing.assert_array_equal(oc.cpu().numpy().view(np.uint32), rc)
+    np.testing.assert_array_equal(ol.cpu().numpy().view(np.uint32), rl)
+    np.testing.assert_array_equal(orr.cpu().numpy().view(np.uint32), rr)
+    np.testing.assert_array_equal(ow.cpu().numpy(), rw)
+
+
+def test_count_with_device_expansion(known_counts):
+    """nq_count at depth >= 7 builds a shallow frontier and deepens it on the device."""
+    nq = _nq()
+    for n, k in [(12, 7), (14, 8), (16, 7)]:
+        for mode in ("persistent", "plain"):
+            _say("count via expansion", n, k, mode)
+            total, counts = nq.count(n, depth=k, mode=mode, counts=True)
+            assert total == known_counts[n]
+            pre, _ = oracle.frontier(n, k)
+            ref, _ = oracle.count_prefixes(n, pre, threads=8)
+            np.testing.assert_array_equal(counts, ref)
