@@ -63,14 +63,16 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
 // last one publishes the instance's total to host memory (value first, then
 // the generation flag, each as a system-scope store, so a host that sees the
 // flag also sees the value).
-__device__ __noinline__ void publish_if_last(const DfsParams& P, uint32_t s) {
+__device__ __forceinline__ void publish_if_last(uint32_t* remaining, unsigned long long* totals,
+                                                const uint32_t* gen, unsigned long long* host_val,
+                                                unsigned long long* host_flag, uint32_t s) {
     __threadfence();                                      // totals add before the count
-    const uint32_t before = atomicSub(&P.remaining[s], 1u);
+    const uint32_t before = atomicSub(&remaining[s], 1u);
     if (before == 1u) {
         __threadfence();
-        const unsigned long long t = atomicAdd(&P.totals[s], 0ull);
-        __hip_atomic_store(&P.host_val[s], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&P.host_flag[s], (unsigned long long)P.inst_gen[s], __ATOMIC_RELEASE,
+        const unsigned long long t = atomicAdd(&totals[s], 0ull);
+        __hip_atomic_store(&host_val[s], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&host_flag[s], (unsigned long long)gen[s], __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
@@ -260,7 +262,8 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 else
                     wtotal += w * sum64;
             }
-            if (P.remaining && inst_ok) publish_if_last(P, s);
+            if (P.remaining && inst_ok)
+                publish_if_last(P.remaining, P.totals, P.inst_gen, P.host_val, P.host_flag, s);
             has_task = false;
         }
         if (PERSISTENT && !exhausted) {
