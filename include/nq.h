@@ -255,7 +255,7 @@ int nq_batch_destroy(nq_batch* batch);
  * A scheduler thread owned by the server admits requests in arrival order while
  * request slots (4096), work-ring space and the LDS stack of the epoch kernel
  * allow, and launches bounded persistent "epochs" over the newly admitted
- * subproblems on two alternating streams, so new work overlaps the tail of
+ * subproblems on four rotating streams, so new work overlaps the tail of
  * older work.  A request's result is published to pinned host memory by the
  * GPU lane that retires its last subproblem.
  *

@@ -7,9 +7,8 @@
 // device-resident ring (host frontier + H2D for counts, device-to-device copies
 // out of the resident frontier for slices), and launches a bounded "epoch": one
 // persistent DFS launch over exactly the entries admitted since the previous
-// epoch.  Epochs alternate between two streams, so the next epoch is queued
-// while the previous one still runs and its waves fill the CUs as the older
-// epoch drains.  Every retired subproblem decrements its request's remaining
+// epoch.  Epochs rotate over four streams, so new epochs are queued while
+// older ones still run and their waves fill the CUs as the older epochs drain.  Every retired subproblem decrements its request's remaining
 // counter on the device; the lane that retires the last one publishes the
 // request's total to pinned host memory (value, then a generation flag), where
 // the scheduler sees it without waiting for the epoch to end.
@@ -67,6 +66,7 @@ struct Epoch {
 };
 
 constexpr uint32_t kHeads = 64;
+constexpr uint32_t kStreams = 4;             // epochs in flight at once (divides kHeads)
 constexpr size_t kRingEntryBytes = 4 * 4 + 1;   // cols, ld, rd, inst + weight
 
 }  // namespace
@@ -89,10 +89,10 @@ struct nq_server {
     uint32_t *s_n = nullptr, *s_rem = nullptr, *s_gen = nullptr;
     unsigned long long* s_tot = nullptr;
     unsigned long long* heads = nullptr;
-    nqi::SlotInit* d_init = nullptr;       // max_slots records per epoch parity
+    nqi::SlotInit* d_init = nullptr;       // max_slots records per epoch stream
     unsigned long long *h_val = nullptr, *h_flag = nullptr;   // pinned, host view
     unsigned long long *d_val = nullptr, *d_flag = nullptr;   // device view
-    hipStream_t streams[2] = {nullptr, nullptr};
+    hipStream_t streams[kStreams] = {};
     std::map<std::pair<uint32_t, uint32_t>, Resident> resident;
 
     // scheduling state (guarded by mu)
@@ -284,11 +284,11 @@ int admit_and_launch(nq_server* s) {
     }
     if (taken.empty()) return NQ_OK;
     const uint64_t n_entries = s->ring_tail - epoch_start;
-    hipStream_t st = s->streams[s->epoch_no & 1u];
+    hipStream_t st = s->streams[s->epoch_no % kStreams];
     hipError_t e = hipSuccess;
     // 1. slot records, 2. instance ids of every entry, 3. count frontiers,
     // 4. slices (device to device).  Host-staged copies go in ring order.
-    const size_t init_off = (s->epoch_no & 1u) * s->max_slots;
+    const size_t init_off = (s->epoch_no % kStreams) * s->max_slots;
     nqi::SlotInit* d_init = s->d_init + init_off;
     if ((e = hipMemcpyAsync(d_init, ep.inits.data(), ep.inits.size() * sizeof(SlotInit),
                             hipMemcpyHostToDevice, st)) != hipSuccess) {
@@ -440,7 +440,7 @@ int serve_create(const nq_opts* opts, uint64_t hbm_budget, nq_server** out) {
     const size_t o_ld = R * 4, o_rd = R * 8, o_inst = R * 12, o_w = R * 16;
     const size_t o_sn = (o_w + R + 255) / 256 * 256, o_rem = o_sn + S * 4, o_gen = o_rem + S * 4;
     const size_t o_tot = (o_gen + S * 4 + 255) / 256 * 256, o_heads = o_tot + S * 8;
-    const size_t o_init = o_heads + kHeads * 8, bytes = o_init + 2 * S * sizeof(SlotInit);
+    const size_t o_init = o_heads + kHeads * 8, bytes = o_init + kStreams * S * sizeof(SlotInit);
     if ((e = hipMalloc(&s->dev, bytes)) != hipSuccess) {
         set_hip_error(e);
         return fail(e == hipErrorOutOfMemory ? NQ_ENOMEM : NQ_EDEVICE);
