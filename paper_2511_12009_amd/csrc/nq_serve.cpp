@@ -8,10 +8,11 @@
 // out of the resident frontier for slices), and launches a bounded "epoch": one
 // persistent DFS launch over exactly the entries admitted since the previous
 // epoch.  Epochs rotate over four streams, so new epochs are queued while
-// older ones still run and their waves fill the CUs as the older epochs drain.  Every retired subproblem decrements its request's remaining
-// counter on the device; the lane that retires the last one publishes the
-// request's total to pinned host memory (value, then a generation flag), where
-// the scheduler sees it without waiting for the epoch to end.
+// older ones still run and their waves fill the CUs as the older epochs
+// drain.  Every retired subproblem decrements its request's remaining counter
+// on the device; the lane that retires the last one publishes the request's
+// total to pinned host memory (value, then a generation flag), where the
+// scheduler sees it without waiting for the epoch to end.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
