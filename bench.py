@@ -296,7 +296,7 @@ def main():
     src = "oracle (tests/golden)" if nodes else None
     kern_ms = float(np.mean(ev_ms))
     out = {
-        "metric": "DFS nodes/s (N=20 count, 1 MI355X, batched persistent launch, bit-exact)",
+        "metric": "DFS nodes/s + N=20 count wall time on 1 MI355X, batched vs plain, bit-exact",
         "value": (nodes / (ms_step / 1e3)) if nodes else None,
         "unit": "DFS nodes/s",
         "n_gpus": 1,
@@ -308,8 +308,9 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"N-Queens N={N} full count, pre-placement depth {k}, "
-                               f"{F} subproblems, persistent launch",
+        "config": {"workload": f"N-Queens N={N} full count, pre-placement depth {k}"
+                               f"{' (autotuned over 5..8)' if tuned else ''}, {F} subproblems "
+                               "resident in HBM, one persistent launch",
                    "n": N, "depth": k, "subproblems": F, "solutions": EXPECT,
                    "nodes": nodes, "nodes_source": src},
         "plain": {"ms_per_step": plain_ms,
