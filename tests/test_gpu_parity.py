@@ -245,3 +245,12 @@ def test_count_with_device_expansion(known_counts):
             pre, _ = oracle.frontier(n, k)
             ref, _ = oracle.count_prefixes(n, pre, threads=8)
             np.testing.assert_array_equal(counts, ref)
+
+
+@pytest.mark.parametrize("n,k", [(19, 6), (20, 7), (20, 8), (21, 7)])
+def test_large_counts_at_tuned_depths(n, k, known_counts):
+    """Full counts at the depths the autotuner chooses from (published totals);
+    depth >= 7 goes through the device expansion."""
+    nq = _nq()
+    _say("large count", n, k)
+    assert nq.count(n, depth=k, mode="persistent") == known_counts[n]
