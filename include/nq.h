@@ -103,7 +103,10 @@ int nq_frontier_runs(uint32_t n, uint32_t depth, uint64_t* offsets, uint32_t cap
  * deeper row, into d_ocols, d_old, d_ord (d_oweight nullable; children inherit
  * their parent's weight, 1 when d_weight is NULL).  Order: all children of entry
  * 0 (lowest column first), then entry 1, ...; expanding nq_frontier(n, k) gives
- * nq_frontier(n, k + rows) exactly.  With d_ocols, d_old or d_ord NULL only
+ * nq_frontier(n, k + rows) exactly when k >= 2 or n is even.  (For odd n at
+ * k = 1 the centre entry has weight 1 and an unrestricted row 1; its children
+ * keep weight 1, which gives the same weighted count as the deeper frontier,
+ * whose centre entries restrict row 1 and carry weight 2.)  With d_ocols, d_old or d_ord NULL only
  * *out_len (the number of children) is computed; capacity < *out_len is
  * NQ_ERANGE.  The call allocates scratch device memory and waits on `stream`
  * (hipStream_t or NULL) for the size and, when writing, for the result.

@@ -4,8 +4,10 @@
 // placement of `rows` more queens below each of them, i.e. the frontier at
 // depth k + rows, in canonical order: the children of entry i follow those of
 // entry i - 1, and each entry's children are in lowest-column-first order, so
-// expanding the depth-k frontier gives exactly nq_frontier(n, k + rows).
-// Children inherit their parent's weight.
+// expanding the depth-k frontier gives exactly nq_frontier(n, k + rows) for
+// k >= 2 or even n.  Children inherit their parent's weight (for odd n from
+// depth 1 the weight-1 centre entry keeps its unrestricted row 1, which gives
+// the same weighted count as the deeper frontier's restricted, weight-2 form).
 //
 // Three passes: count the children of every entry (one thread per entry), an
 // exclusive scan of the counts (rocPRIM via hipCUB) giving each entry's output

@@ -218,9 +218,11 @@ def test_node_counts_per_subproblem(n, k):
         assert _digest(counts.cpu().numpy().view(np.uint64)) == g[5]
 
 
-@pytest.mark.parametrize("n,k,rows", [(12, 2, 1), (13, 3, 2), (16, 4, 3), (11, 1, 3), (20, 5, 2)])
+@pytest.mark.parametrize("n,k,rows", [(12, 2, 1), (13, 3, 2), (16, 4, 3), (11, 2, 3), (12, 1, 3),
+                                      (20, 5, 2)])
 def test_device_expansion_matches_oracle_frontier(n, k, rows):
-    """nq_expand of the depth-k frontier is the oracle's depth k+rows frontier."""
+    """nq_expand of the depth-k frontier is the oracle's depth k+rows frontier
+    (k >= 2, or even n: see the next test for odd n from depth 1)."""
     nq = _nq()
     cols, ld, rd, w = nq.frontier(n, k)
     t = [_dev(x) for x in (cols, ld, rd)]
@@ -254,3 +256,18 @@ def test_large_counts_at_tuned_depths(n, k, known_counts):
     nq = _nq()
     _say("large count", n, k)
     assert nq.count(n, depth=k, mode="persistent") == known_counts[n]
+
+
+def test_expansion_of_odd_board_from_depth_one(known_counts):
+    """For odd n the depth-1 centre entry has weight 1 and an unrestricted row 1,
+    so its expansion differs from the deeper frontier (which restricts row 1 and
+    doubles the weight) but the weighted count is the same."""
+    nq = _nq()
+    n = 11
+    cols, ld, rd, w = nq.frontier(n, 1)
+    t = [_dev(x) for x in (cols, ld, rd)]
+    oc, ol, orr, ow = nq.expand(n, 3, *t, weight=torch.from_numpy(w).cuda())
+    assert oc.numel() != oracle.frontier_size(n, 4)
+    counts, total = nq.count_subproblems(n, oc, ol, orr, weight=ow, depth=4)
+    torch.cuda.synchronize()
+    assert int(total.item()) == known_counts[n]
