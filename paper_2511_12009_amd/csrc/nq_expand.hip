@@ -93,7 +93,8 @@ __global__ void nq_expand_write_kernel(const uint32_t* __restrict__ cols,
 size_t expand_scratch_bytes(uint64_t len) {
     size_t scan_bytes = 0;
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (const uint64_t*)nullptr,
-                                           (uint64_t*)nullptr, (int)std::max<uint64_t>(len, 1));
+                                           (uint64_t*)nullptr,
+                                           (int)std::min<uint64_t>(len + 1, 0x7fffffff));
     return (len + 1) * 8 * 2 + scan_bytes + 256;
 }
 
@@ -102,7 +103,7 @@ int expand_device(uint32_t n, uint32_t rows, const uint32_t* cols, const uint32_
                   uint32_t* old, uint32_t* ord, uint8_t* ow, uint64_t cap, uint64_t* out_len,
                   void* scratch, void* stream) {
     if (n < 1 || n > NQ_MAX_N || rows < 1 || rows > kMaxExpandRows || !out_len) return NQ_EINVAL;
-    if (len > (uint64_t)0x7fffffff) return NQ_EINVAL;         // scan index range
+    if (len >= (uint64_t)0x7fffffff) return NQ_EINVAL;        // scan index range
     hipStream_t s = (hipStream_t)stream;
     if (len == 0) { *out_len = 0; return NQ_OK; }
     char* sc = static_cast<char*>(scratch);
@@ -113,6 +114,7 @@ int expand_device(uint32_t n, uint32_t rows, const uint32_t* cols, const uint32_
     hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, counts, offsets,
                                                     (int)(len + 1), s);
     if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
+    if (scan_bytes + (len + 1) * 16 + 256 > expand_scratch_bytes(len)) return NQ_EINVAL;
     const uint32_t block = 256;
     const uint32_t grid = (uint32_t)((len + block - 1) / block);
     // counts[len] = 0 so that offsets[len] is the total.
