@@ -36,7 +36,7 @@
 namespace nqi {
 
 // Default inner-loop form of the DFS kernels (see nq_dfs_kernel).
-constexpr int kDefaultLoop = 0;
+constexpr int kDefaultLoop = 1;
 
 namespace {
 
