@@ -164,6 +164,16 @@ __device__ __forceinline__ void isa_pop_prefetched(u32x4& st, u32x4& nxt, int32_
         : "memory");
 }
 
+// p = lowest set bit of v; v loses it (in place, so the loop-carried register
+// of v is also the one the pop writes).
+__device__ __forceinline__ void isa_take_lowest(uint32_t& v, uint32_t& p) {
+    uint32_t neg;
+    asm("v_sub_u32 %[n], 0, %[v]\n\t"
+        "v_and_b32 %[p], %[v], %[n]\n\t"
+        "v_xor_b32 %[v], %[v], %[p]"
+        : [v] "+v"(v), [p] "=&v"(p), [n] "=&v"(neg));
+}
+
 // Select: d = m ? a : d per lane (v_cndmask with an SGPR lane mask).
 __device__ __forceinline__ uint32_t isa_sel(uint64_t m, uint32_t a, uint32_t d) {
     asm("v_cndmask_b32 %0, %0, %1, %2" : "+v"(d) : "v"(a), "s"(m));
@@ -325,8 +335,9 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         // The trip count is wave-uniform; readfirstlane keeps it in an SGPR.
         uint32_t trips = __builtin_amdgcn_readfirstlane(P.refill_every);
         do {
-            const uint32_t p = st.w & (0u - st.w);
-            const uint32_t rest = st.w ^ p;
+            // p = lowest untried column; the untried set keeps its register.
+            uint32_t p, rest = st.w;
+            isa_take_lowest(rest, p);
             const uint32_t nc = LEAFCTR ? st.x + p + step_k : (st.x | p);
             const uint32_t nl = (st.y + p) << 1;
             const uint32_t nr = (st.z + p) >> 1;
