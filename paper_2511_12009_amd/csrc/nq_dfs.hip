@@ -355,7 +355,9 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
             st.y = isa_sel(descm, nl, st.y);
             st.z = isa_sel(descm, nr, st.z);
             st.w = isa_sel(descm, a, st.w);
-            const uint64_t popm = __builtin_amdgcn_ballot_w64(st.w == 0u);
+            // After the select, avail == 0 exactly when the lane did not
+            // descend (a descent has a != 0) and had no untried column left.
+            const uint64_t popm = ~(descm | restm);
             if (LOOP == 2) {
                 isa_pop_prefetched(st, nxt, top, floor, popm);
                 isa_prefetch(nxt, top);
