@@ -121,6 +121,7 @@ static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
     P.cols = d_cols; P.ld = d_ld; P.rd = d_rd; P.weight = d_weight;
     P.counts = d_counts; P.totals = d_total; P.head = head; P.nodes = d_nodes;
     P.len = len; P.n = n; P.frames = frames; P.refill_every = refill_default(opts);
+    P.idle_min = default_idle_min();
     P.reverse = (opts && (opts->flags & NQ_FLAG_FORWARD_ORDER)) ? 0u : 1u;
     EventTimer t;
     if (kernel_ms && (rc = t.start(s)) != NQ_OK) return rc;

@@ -333,39 +333,51 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         u32x4 nxt;
         if (LOOP == 2) isa_prefetch(nxt, top);
         // The trip count is wave-uniform; readfirstlane keeps it in an SGPR.
-        uint32_t trips = __builtin_amdgcn_readfirstlane(P.refill_every);
-        do {
-            // p = lowest untried column; the untried set keeps its register.
-            uint32_t p, rest = st.w;
-            isa_take_lowest(rest, p);
-            const uint32_t nc = LEAFCTR ? st.x + p + step_k : (st.x | p);
-            const uint32_t nl = (st.y + p) << 1;
-            const uint32_t nr = (st.z + p) >> 1;
-            const uint32_t a = last & ~(nc | nl | nr);
-            if (STATS) steps32 += (p != 0u);
-            const uint64_t leafm = __builtin_amdgcn_ballot_w64(
-                LEAFCTR ? (int32_t)nc < 0 : __popc(nc) == nm1);
-            const uint64_t anym = __builtin_amdgcn_ballot_w64(a != 0u);
-            const uint64_t restm = __builtin_amdgcn_ballot_w64(rest != 0u);
-            const uint64_t descm = anym & ~leafm;
-            isa_count(sum32, anym & leafm);
-            st.w = rest;
-            isa_push(st, top, descm & restm);
-            st.x = isa_sel(descm, nc, st.x);
-            st.y = isa_sel(descm, nl, st.y);
-            st.z = isa_sel(descm, nr, st.z);
-            st.w = isa_sel(descm, a, st.w);
-            // After the select, avail == 0 exactly when the lane did not
-            // descend (a descent has a != 0) and had no untried column left.
-            const uint64_t popm = ~(descm | restm);
-            if (LOOP == 2) {
-                isa_pop_prefetched(st, nxt, top, floor, popm);
-                isa_prefetch(nxt, top);
-            } else {
-                isa_pop(st, top, floor, popm);
-            }
-            trips = __builtin_amdgcn_readfirstlane(trips - 1u);
-        } while (trips != 0u);
+        // Steps run in chunks of 32; between chunks a persistent wave returns
+        // to the scheduler early once `idle_min` of its lanes have finished
+        // (a finished lane has avail == 0 after its step), so finished lanes
+        // wait for at most one chunk instead of `refill_every` steps.
+        uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 31u) / 32u);
+        for (;;) {
+            uint32_t trips = 32u;
+            do {
+                // p = lowest untried column; the untried set keeps its register.
+                uint32_t p, rest = st.w;
+                isa_take_lowest(rest, p);
+                const uint32_t nc = LEAFCTR ? st.x + p + step_k : (st.x | p);
+                const uint32_t nl = (st.y + p) << 1;
+                const uint32_t nr = (st.z + p) >> 1;
+                const uint32_t a = last & ~(nc | nl | nr);
+                if (STATS) steps32 += (p != 0u);
+                const uint64_t leafm = __builtin_amdgcn_ballot_w64(
+                    LEAFCTR ? (int32_t)nc < 0 : __popc(nc) == nm1);
+                const uint64_t anym = __builtin_amdgcn_ballot_w64(a != 0u);
+                const uint64_t restm = __builtin_amdgcn_ballot_w64(rest != 0u);
+                const uint64_t descm = anym & ~leafm;
+                isa_count(sum32, anym & leafm);
+                st.w = rest;
+                isa_push(st, top, descm & restm);
+                st.x = isa_sel(descm, nc, st.x);
+                st.y = isa_sel(descm, nl, st.y);
+                st.z = isa_sel(descm, nr, st.z);
+                st.w = isa_sel(descm, a, st.w);
+                // After the select, avail == 0 exactly when the lane did not
+                // descend (a descent has a != 0) and had no untried column left.
+                const uint64_t popm = ~(descm | restm);
+                if (LOOP == 2) {
+                    isa_pop_prefetched(st, nxt, top, floor, popm);
+                    isa_prefetch(nxt, top);
+                } else {
+                    isa_pop(st, top, floor, popm);
+                }
+                trips = __builtin_amdgcn_readfirstlane(trips - 1u);
+            } while (trips != 0u);
+            chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
+            if (chunks == 0u) break;
+            if (PERSISTENT && P.idle_min && !exhausted &&
+                (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(st.w == 0u)) >= P.idle_min)
+                break;
+        }
         if (LOOP == 2) asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(nxt)::"memory");
         }
         c = st.x; l = st.y; r = st.z; v = st.w;
@@ -422,6 +434,18 @@ static int loop_form() {
         return kDefaultLoop;
     }();
     return form;
+}
+
+uint32_t default_idle_min() {
+    static const uint32_t v = [] {
+        const char* e = std::getenv("NQ_IDLE_MIN");
+        if (e && *e) {
+            const long x = std::strtol(e, nullptr, 10);
+            if (x >= 0 && x <= 64) return (uint32_t)x;
+        }
+        return 4u;
+    }();
+    return v;
 }
 
 static const void* select_kernel(uint32_t mode, bool stats, bool leafctr) {

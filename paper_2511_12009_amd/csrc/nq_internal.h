@@ -55,7 +55,8 @@ struct DfsParams {
     uint64_t wrap;
     uint32_t ninst;                 // instances (slots) when inst != nullptr: ids >= ninst
                                     // are never used to index (the entry is rejected)
-    uint32_t pad2;
+    uint32_t idle_min;              // persistent: visit the scheduler early once this many
+                                    // lanes of a wave are idle (0 = every refill_every steps)
     uint32_t* remaining;
     const uint32_t* inst_gen;
     unsigned long long* host_val;
@@ -131,6 +132,11 @@ int expand_device(uint32_t n, uint32_t rows, const uint32_t* cols, const uint32_
 
 // Tuning results remembered for this process (nq_autotune), by device and n.
 int tune_lookup(uint32_t n, nq_tuned* out);
+
+// Lanes of a persistent wave that must be idle before it visits the scheduler
+// between chunks of steps (NQ_IDLE_MIN in the environment overrides, for
+// measurements).
+uint32_t default_idle_min();
 
 // Records a failing hipError_t for nq_last_hip_error().
 void set_hip_error(int err);
