@@ -180,6 +180,57 @@ __device__ __forceinline__ uint32_t isa_sel(uint64_t m, uint32_t a, uint32_t d) 
     return d;
 }
 
+// The frame as two 64-bit halves, (cols | ld << 32, rd | avail << 32): the
+// same 16 bytes as u32x4, so that the descend select moves it with two
+// v_mov_b64 under an exec mask instead of four v_cndmask.
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) u64x2 lds_frame64;
+
+__device__ __forceinline__ lds_frame64* frame64_at(int32_t addr) {
+    return (lds_frame64*)(uintptr_t)(uint32_t)addr;
+}
+
+__device__ __forceinline__ void isa_push64(u64x2 st, int32_t& top, uint64_t m) {
+    uint64_t sv;
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[m]\n\t"
+        "ds_write_b64 %[top], %[s0] offset:1024\n\t"
+        "ds_write_b64 %[top], %[s1] offset:1032\n\t"
+        "v_add_u32 %[top], 0x400, %[top]\n\t"
+        "s_mov_b64 exec, %[sv]"
+        : [top] "+v"(top), [sv] "=&s"(sv)
+        : [m] "s"(m), [s0] "v"(st.x), [s1] "v"(st.y)
+        : "memory");
+}
+
+__device__ __forceinline__ void isa_pop64(u64x2& st, int32_t& top, int32_t floor, uint64_t m) {
+    uint64_t sv;
+    int32_t t;
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[m]\n\t"
+        "ds_read_b64 %[s0], %[top]\n\t"
+        "ds_read_b64 %[s1], %[top] offset:8\n\t"
+        "v_add_u32 %[t], 0xfffffc00, %[top]\n\t"
+        "v_max_i32 %[top], %[t], %[fl]\n\t"
+        "s_mov_b64 exec, %[sv]\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [s0] "+v"(st.x), [s1] "+v"(st.y), [top] "+v"(top), [sv] "=&s"(sv), [t] "=&v"(t)
+        : [m] "s"(m), [fl] "v"(floor)
+        : "memory");
+}
+
+// st = ch for the lanes in `m`.
+__device__ __forceinline__ void isa_move64(uint64_t m, u64x2 ch, u64x2& st) {
+    uint64_t sv;
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[m]\n\t"
+        "v_mov_b64 %[s0], %[c0]\n\t"
+        "v_mov_b64 %[s1], %[c1]\n\t"
+        "s_mov_b64 exec, %[sv]"
+        : [s0] "+v"(st.x), [s1] "+v"(st.y), [sv] "=&s"(sv)
+        : [c0] "v"(ch.x), [c1] "v"(ch.y), [m] "s"(m));
+}
+
 // sum += 1 for the lanes in `m` (carry-in add).
 __device__ __forceinline__ void isa_count(uint32_t& sum, uint64_t m) {
     uint64_t junk;
@@ -188,7 +239,9 @@ __device__ __forceinline__ void isa_count(uint32_t& sum, uint64_t m) {
 
 // LOOP selects the inner-loop form: 0 = plain C++ (the compiler places the
 // exec masks), 1 = hand-placed exec masks with a direct pop, 2 = as 1 but the
-// frame a pop needs is read one step ahead, so the pop does not wait on LDS.
+// frame a pop needs is read one step ahead, so the pop does not wait on LDS,
+// 3 = as 1 with the frame in 64-bit halves and the descend select done by two
+// exec-masked 64-bit moves.
 template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP>
 __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     extern __shared__ uint4 lds_stack[];
@@ -327,6 +380,49 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 top = max(top - 1024, floor);
             }
         }
+        } else if (LOOP == 3) {
+        // As LOOP 1, with the frame in two 64-bit halves and the descend
+        // select done by two exec-masked v_mov_b64.
+        u64x2 st2;
+        st2.x = ((uint64_t)l << 32) | c;
+        st2.y = ((uint64_t)v << 32) | r;
+        uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 31u) / 32u);
+        for (;;) {
+            uint32_t trips = 32u;
+            do {
+                const uint32_t c0 = (uint32_t)st2.x, l0 = (uint32_t)(st2.x >> 32);
+                const uint32_t r0 = (uint32_t)st2.y;
+                uint32_t p, rest = (uint32_t)(st2.y >> 32);
+                isa_take_lowest(rest, p);
+                const uint32_t nc = LEAFCTR ? c0 + p + step_k : (c0 | p);
+                const uint32_t nl = (l0 + p) << 1;
+                const uint32_t nr = (r0 + p) >> 1;
+                const uint32_t a = last & ~(nc | nl | nr);
+                if (STATS) steps32 += (p != 0u);
+                const uint64_t leafm = __builtin_amdgcn_ballot_w64(
+                    LEAFCTR ? (int32_t)nc < 0 : __popc(nc) == nm1);
+                const uint64_t anym = __builtin_amdgcn_ballot_w64(a != 0u);
+                const uint64_t restm = __builtin_amdgcn_ballot_w64(rest != 0u);
+                const uint64_t descm = anym & ~leafm;
+                isa_count(sum32, anym & leafm);
+                st2.y = ((uint64_t)rest << 32) | r0;
+                isa_push64(st2, top, descm & restm);
+                u64x2 ch;
+                ch.x = ((uint64_t)nl << 32) | nc;
+                ch.y = ((uint64_t)a << 32) | nr;
+                isa_move64(descm, ch, st2);
+                isa_pop64(st2, top, floor, ~(descm | restm));
+                trips = __builtin_amdgcn_readfirstlane(trips - 1u);
+            } while (trips != 0u);
+            chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
+            if (chunks == 0u) break;
+            if (PERSISTENT && P.idle_min && !exhausted &&
+                (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((uint32_t)(st2.y >> 32) == 0u)) >=
+                    P.idle_min)
+                break;
+        }
+        st = u32x4{(uint32_t)st2.x, (uint32_t)(st2.x >> 32), (uint32_t)st2.y,
+                   (uint32_t)(st2.y >> 32)};
         } else {
         // Same step with the lane masks kept in SGPR pairs: the push, the
         // selects, the pop and the leaf count use them directly.
@@ -425,12 +521,12 @@ static const void* select_kernel_loop(uint32_t mode, bool stats, bool leafctr) {
     return leafctr ? kernel_ptr<false, false, true, LOOP>() : kernel_ptr<false, false, false, LOOP>();
 }
 
-// Inner-loop form: NQ_DFS_LOOP=0/1/2 in the environment overrides the default
+// Inner-loop form: NQ_DFS_LOOP=0..3 in the environment overrides the default
 // (for measurements).
 static int loop_form() {
     static const int form = [] {
         const char* e = std::getenv("NQ_DFS_LOOP");
-        if (e && (e[0] == '0' || e[0] == '1' || e[0] == '2') && e[1] == 0) return e[0] - '0';
+        if (e && e[0] >= '0' && e[0] <= '3' && e[1] == 0) return e[0] - '0';
         return kDefaultLoop;
     }();
     return form;
@@ -452,6 +548,7 @@ static const void* select_kernel(uint32_t mode, bool stats, bool leafctr) {
     switch (loop_form()) {
         case 1: return select_kernel_loop<1>(mode, stats, leafctr);
         case 2: return select_kernel_loop<2>(mode, stats, leafctr);
+        case 3: return select_kernel_loop<3>(mode, stats, leafctr);
         default: return select_kernel_loop<0>(mode, stats, leafctr);
     }
 }
