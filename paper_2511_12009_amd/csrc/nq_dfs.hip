@@ -237,11 +237,89 @@ __device__ __forceinline__ void isa_count(uint32_t& sum, uint64_t m) {
     asm("v_addc_co_u32 %0, %1, %0, 0, %2" : "+v"(sum), "=s"(junk) : "s"(m));
 }
 
+// Negated untried set w = -avail: p = lowest untried column, w becomes
+// -(avail - p) in place, zm = lanes whose untried set is now empty (the carry
+// out of w + p).  The mask leaves the block in an SGPR pair and is only read by
+// SALU code.
+__device__ __forceinline__ void isa_take_neg(uint32_t& w, uint32_t& p, uint64_t& zm) {
+    uint32_t t;
+    asm("v_sub_u32 %[t], 0, %[w]\n\t"
+        "v_and_b32 %[p], %[w], %[t]\n\t"
+        "v_add_co_u32 %[w], %[z], %[w], %[p]"
+        : [w] "+v"(w), [p] "=&v"(p), [t] "=&v"(t), [z] "=&s"(zm));
+}
+
+// Returns -a; am = lanes with a != 0 (the borrow of 0 - a), read by SALU
+// code only.
+__device__ __forceinline__ uint32_t isa_neg_any(uint32_t a, uint64_t& am) {
+    uint32_t n;
+    asm("v_sub_co_u32 %0, %1, 0, %2" : "=v"(n), "=s"(am) : "v"(a));
+    return n;
+}
+
+// One step's stack and frame update for the negated-avail loops (LOOP 4, 5),
+// in a single exec-masked block.  The three lane masks are disjoint subsets of
+// exec: lanes in `pm` store the frame at [top + 1024] and advance top, lanes
+// in `dm` take the child frame `ch`, lanes in `qm` reload the frame at [top]
+// and step top back.  No clamp: a lane that has popped its sentinel is parked
+// and its masks stay empty until it takes a new entry.
+__device__ __forceinline__ void isa_step64(u64x2& st, u64x2 ch, int32_t& top, uint64_t pm,
+                                           uint64_t dm, uint64_t qm) {
+    uint64_t sv;
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[pm]\n\t"
+        "ds_write_b64 %[top], %[s0] offset:1024\n\t"
+        "ds_write_b64 %[top], %[s1] offset:1032\n\t"
+        "v_add_u32 %[top], 0x400, %[top]\n\t"
+        "s_and_b64 exec, %[sv], %[dm]\n\t"
+        "v_mov_b64 %[s0], %[c0]\n\t"
+        "v_mov_b64 %[s1], %[c1]\n\t"
+        "s_and_b64 exec, %[sv], %[qm]\n\t"
+        "ds_read_b64 %[s0], %[top]\n\t"
+        "ds_read_b64 %[s1], %[top] offset:8\n\t"
+        "v_add_u32 %[top], 0xfffffc00, %[top]\n\t"
+        "s_mov_b64 exec, %[sv]\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [s0] "+v"(st.x), [s1] "+v"(st.y), [top] "+v"(top), [sv] "=&s"(sv)
+        : [c0] "v"(ch.x), [c1] "v"(ch.y), [pm] "s"(pm), [dm] "s"(dm), [qm] "s"(qm)
+        : "memory");
+}
+
+// As isa_step64 with the frame as four dwords: one ds_write_b128 /
+// ds_read_b128 each way and four v_cndmask for the child.
+__device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, uint64_t pm,
+                                            uint64_t dm, uint64_t qm) {
+    uint64_t sv;
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[pm]\n\t"
+        "ds_write_b128 %[top], %[st] offset:1024\n\t"
+        "v_add_u32 %[top], 0x400, %[top]\n\t"
+        "s_mov_b64 exec, %[sv]"
+        : [top] "+v"(top), [sv] "=&s"(sv)
+        : [pm] "s"(pm), [st] "v"(st)
+        : "memory");
+    st.x = isa_sel(dm, ch.x, st.x);
+    st.y = isa_sel(dm, ch.y, st.y);
+    st.z = isa_sel(dm, ch.z, st.z);
+    st.w = isa_sel(dm, ch.w, st.w);
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[qm]\n\t"
+        "ds_read_b128 %[st], %[top]\n\t"
+        "v_add_u32 %[top], 0xfffffc00, %[top]\n\t"
+        "s_mov_b64 exec, %[sv]\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [st] "+v"(st), [top] "+v"(top), [sv] "=&s"(sv)
+        : [qm] "s"(qm)
+        : "memory");
+}
+
 // LOOP selects the inner-loop form: 0 = plain C++ (the compiler places the
 // exec masks), 1 = hand-placed exec masks with a direct pop, 2 = as 1 but the
 // frame a pop needs is read one step ahead, so the pop does not wait on LDS,
 // 3 = as 1 with the frame in 64-bit halves and the descend select done by two
-// exec-masked 64-bit moves.
+// exec-masked 64-bit moves, 4 = the frame keeps its untried set negated so
+// that the lane masks come from carries (halves and 64-bit moves as in 3),
+// 5 = as 4 with the frame as four dwords and v_cndmask selects.
 template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP>
 __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     extern __shared__ uint4 lds_stack[];
@@ -423,6 +501,68 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         }
         st = u32x4{(uint32_t)st2.x, (uint32_t)(st2.x >> 32), (uint32_t)st2.y,
                    (uint32_t)(st2.y >> 32)};
+        } else if (LOOP == 4 || LOOP == 5) {
+        // The frame keeps the untried set negated, w = -avail (mod 2^32), so
+        // that the step's lane masks come out of carries instead of compares:
+        //   p = w & -w is the lowest untried column, and w + p = -(avail - p)
+        //   carries out exactly when that column was the last one;
+        //   the child's w = 0 - a borrows exactly when a != 0.
+        // A parked lane has w = 0: p = 0, no carry, no free square, so it
+        // neither pushes, descends nor pops (its stack pointer needs no clamp).
+        uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 31u) / 32u);
+        u64x2 st2;
+        u32x4 st4;
+        if (LOOP == 4) {
+            st2.x = ((uint64_t)l << 32) | c;
+            st2.y = ((uint64_t)(0u - v) << 32) | r;
+        } else {
+            st4 = u32x4{c, l, r, 0u - v};
+        }
+        for (;;) {
+            uint32_t trips = 32u;
+            do {
+                const uint32_t c0 = LOOP == 4 ? (uint32_t)st2.x : st4.x;
+                const uint32_t l0 = LOOP == 4 ? (uint32_t)(st2.x >> 32) : st4.y;
+                const uint32_t r0 = LOOP == 4 ? (uint32_t)st2.y : st4.z;
+                const uint32_t w0 = LOOP == 4 ? (uint32_t)(st2.y >> 32) : st4.w;
+                uint32_t w1 = w0, p;
+                uint64_t zm;
+                isa_take_neg(w1, p, zm);
+                const uint32_t nc = LEAFCTR ? c0 + p + step_k : (c0 | p);
+                const uint32_t nl = (l0 + p) << 1;
+                const uint32_t nr = (r0 + p) >> 1;
+                uint64_t anym;
+                const uint32_t na = isa_neg_any(last & ~(nc | nl | nr), anym);
+                if (STATS) steps32 += (p != 0u);
+                const uint64_t leafm = __builtin_amdgcn_ballot_w64(
+                    LEAFCTR ? (int32_t)nc < 0 : __popc(nc) == nm1);
+                const uint64_t descm = anym & ~leafm;
+                isa_count(sum32, anym & leafm);
+                if (LOOP == 4) {
+                    st2.y = ((uint64_t)w1 << 32) | r0;
+                    u64x2 ch;
+                    ch.x = ((uint64_t)nl << 32) | nc;
+                    ch.y = ((uint64_t)na << 32) | nr;
+                    isa_step64(st2, ch, top, descm & ~zm, descm, zm & ~descm);
+                } else {
+                    st4.w = w1;
+                    isa_step128(st4, u32x4{nc, nl, nr, na}, top, descm & ~zm, descm,
+                                zm & ~descm);
+                }
+                trips = __builtin_amdgcn_readfirstlane(trips - 1u);
+            } while (trips != 0u);
+            chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
+            if (chunks == 0u) break;
+            const uint32_t wn = LOOP == 4 ? (uint32_t)(st2.y >> 32) : st4.w;
+            if (PERSISTENT && P.idle_min && !exhausted &&
+                (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(wn == 0u)) >= P.idle_min)
+                break;
+        }
+        if (LOOP == 4)
+            st = u32x4{(uint32_t)st2.x, (uint32_t)(st2.x >> 32), (uint32_t)st2.y,
+                       0u - (uint32_t)(st2.y >> 32)};
+        else
+            st = u32x4{st4.x, st4.y, st4.z, 0u - st4.w};
         } else {
         // Same step with the lane masks kept in SGPR pairs: the push, the
         // selects, the pop and the leaf count use them directly.
@@ -521,12 +661,12 @@ static const void* select_kernel_loop(uint32_t mode, bool stats, bool leafctr) {
     return leafctr ? kernel_ptr<false, false, true, LOOP>() : kernel_ptr<false, false, false, LOOP>();
 }
 
-// Inner-loop form: NQ_DFS_LOOP=0..3 in the environment overrides the default
+// Inner-loop form: NQ_DFS_LOOP=0..5 in the environment overrides the default
 // (for measurements).
 static int loop_form() {
     static const int form = [] {
         const char* e = std::getenv("NQ_DFS_LOOP");
-        if (e && e[0] >= '0' && e[0] <= '3' && e[1] == 0) return e[0] - '0';
+        if (e && e[0] >= '0' && e[0] <= '5' && e[1] == 0) return e[0] - '0';
         return kDefaultLoop;
     }();
     return form;
@@ -549,6 +689,8 @@ static const void* select_kernel(uint32_t mode, bool stats, bool leafctr) {
         case 1: return select_kernel_loop<1>(mode, stats, leafctr);
         case 2: return select_kernel_loop<2>(mode, stats, leafctr);
         case 3: return select_kernel_loop<3>(mode, stats, leafctr);
+        case 4: return select_kernel_loop<4>(mode, stats, leafctr);
+        case 5: return select_kernel_loop<5>(mode, stats, leafctr);
         default: return select_kernel_loop<0>(mode, stats, leafctr);
     }
 }
