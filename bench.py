@@ -55,6 +55,30 @@ def golden_nodes(n, k):
     return None
 
 
+def profiled_traffic(n, k):
+    """HBM bytes per launch of the default persistent DFS kernel at (n, k) from
+    the committed counter summary (profiles/), or None when there is none, when
+    the DFS kernel source has changed since the counters were taken (the summary
+    records its sha256), or when an environment override selects another
+    kernel form or scheduler setting."""
+    if any(os.environ.get(v) for v in ("NQ_DFS_LOOP", "NQ_IDLE_MIN", "NQ_CLAIM")):
+        return None
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2511_12009_amd", "csrc", "nq_dfs.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("counters:"):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:] if "=" in x)
+                if (kv.get("source_sha256") == digest and int(kv.get("n", -1)) == n and int(kv.get("depth", -1)) == k):
+                    return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+    return None
+
+
 def known_counts():
     """Published counts (tests/golden/known_counts.txt)."""
     out = {}
@@ -323,7 +347,8 @@ def main():
     if nodes:
         achieved = nodes * OPS_PER_NODE / (kern_ms / 1e3)
         out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK / 1e12,
-                           "unit": "Tint32op/s", "frac": achieved / INT_PEAK, "traffic": None,
+                           "unit": "Tint32op/s", "frac": achieved / INT_PEAK,
+                           "traffic": profiled_traffic(N, k),
                            "ops_per_node": OPS_PER_NODE, "kernel_ms": kern_ms}
     out["launch"] = {"waves_per_cu": args.waves_per_cu, "refill_every": args.refill,
                      "wg_size": args.wg, "autotune": tuned}

@@ -122,6 +122,7 @@ static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
     P.counts = d_counts; P.totals = d_total; P.head = head; P.nodes = d_nodes;
     P.len = len; P.n = n; P.frames = frames; P.refill_every = refill_default(opts);
     P.idle_min = default_idle_min();
+    P.claim = default_claim();
     P.reverse = (opts && (opts->flags & NQ_FLAG_FORWARD_ORDER)) ? 0u : 1u;
     EventTimer t;
     if (kernel_ms && (rc = t.start(s)) != NQ_OK) return rc;
@@ -258,9 +259,10 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
         }
         if (opts && opts->counts_out && opts->counts_capacity < F) return NQ_ERANGE;
         DevBuf buf;
-        // Layout: cols | ld | rd | counts | total | weight.
+        // Layout: cols | ld | rd | counts (only when asked for) | total | weight.
+        const bool want_counts = opts && opts->counts_out;
         const size_t off_ld = F * 4, off_rd = 2 * F * 4, off_cnt = (3 * F * 4 + 7) & ~size_t(7);
-        const size_t off_tot = off_cnt + F * 8, off_w = off_tot + 8;
+        const size_t off_tot = off_cnt + (want_counts ? F * 8 : 0), off_w = off_tot + 8;
         if ((rc = buf.alloc(off_w + F)) != NQ_OK) return rc;
         char* b = buf.as<char>();
         if (rows) {
@@ -284,7 +286,6 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
         auto* d_total = reinterpret_cast<unsigned long long*>(b + off_tot);
         if ((rc = launch_zero_u64(d_total, 1, s)) != NQ_OK) return rc;
         const uint32_t mode = opt_mode(opts);
-        const bool want_counts = opts && opts->counts_out;
         double ms = 0.0, ms_part = 0.0;
         if (mode == NQ_MODE_PLAIN) {
             // One launch per row-0 column (the form the paper's host driver uses

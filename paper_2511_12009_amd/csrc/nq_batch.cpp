@@ -154,6 +154,7 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
         P.frames = frames;
         P.refill_every = (opts && opts->refill_every) ? opts->refill_every : 512u;
         P.idle_min = default_idle_min();
+        P.claim = default_claim();
         P.reverse = (opts && (opts->flags & NQ_FLAG_FORWARD_ORDER)) ? 0u : 1u;
         DeviceInfo dev;
         if ((rc = device_info(&dev)) != NQ_OK) return fail(rc);

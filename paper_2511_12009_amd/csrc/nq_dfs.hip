@@ -106,7 +106,9 @@ __device__ __forceinline__ lds_frame* frame_at(int32_t addr) {
 
 // Exec-masked helpers for the hand-scheduled loop (LOOP >= 1).  Each block
 // switches exec to the given lane mask, does its LDS access and stack-pointer
-// update, and restores exec before the block ends.
+// update, and restores exec before the block ends.  The SALU instructions in a
+// block overwrite SCC, so every such block lists it as clobbered (otherwise
+// the compiler may keep a loop-exit compare in SCC across the block).
 
 // Push: frame -> [top + 1024], top += 1024 for the lanes in `m`.
 __device__ __forceinline__ void isa_push(u32x4 st, int32_t& top, uint64_t m) {
@@ -118,7 +120,7 @@ __device__ __forceinline__ void isa_push(u32x4 st, int32_t& top, uint64_t m) {
         "s_mov_b64 exec, %[sv]"
         : [top] "+v"(top), [sv] "=&s"(sv)
         : [m] "s"(m), [st] "v"(st)
-        : "memory");
+        : "memory", "scc");
 }
 
 // Pop: frame <- [top], top = max(top - 1024, floor) for the lanes in `m`; the
@@ -135,7 +137,7 @@ __device__ __forceinline__ void isa_pop(u32x4& st, int32_t& top, int32_t floor, 
         "s_waitcnt lgkmcnt(0)"
         : [st] "+v"(st), [top] "+v"(top), [sv] "=&s"(sv), [t] "=&v"(t)
         : [m] "s"(m), [fl] "v"(floor)
-        : "memory");
+        : "memory", "scc");
 }
 
 // Prefetch the frame a pop would restore: nxt <- [top] for every lane.
@@ -200,7 +202,7 @@ __device__ __forceinline__ void isa_push64(u64x2 st, int32_t& top, uint64_t m) {
         "s_mov_b64 exec, %[sv]"
         : [top] "+v"(top), [sv] "=&s"(sv)
         : [m] "s"(m), [s0] "v"(st.x), [s1] "v"(st.y)
-        : "memory");
+        : "memory", "scc");
 }
 
 __device__ __forceinline__ void isa_pop64(u64x2& st, int32_t& top, int32_t floor, uint64_t m) {
@@ -216,7 +218,7 @@ __device__ __forceinline__ void isa_pop64(u64x2& st, int32_t& top, int32_t floor
         "s_waitcnt lgkmcnt(0)"
         : [s0] "+v"(st.x), [s1] "+v"(st.y), [top] "+v"(top), [sv] "=&s"(sv), [t] "=&v"(t)
         : [m] "s"(m), [fl] "v"(floor)
-        : "memory");
+        : "memory", "scc");
 }
 
 // st = ch for the lanes in `m`.
@@ -228,7 +230,8 @@ __device__ __forceinline__ void isa_move64(uint64_t m, u64x2 ch, u64x2& st) {
         "v_mov_b64 %[s1], %[c1]\n\t"
         "s_mov_b64 exec, %[sv]"
         : [s0] "+v"(st.x), [s1] "+v"(st.y), [sv] "=&s"(sv)
-        : [c0] "v"(ch.x), [c1] "v"(ch.y), [m] "s"(m));
+        : [c0] "v"(ch.x), [c1] "v"(ch.y), [m] "s"(m)
+        : "scc");
 }
 
 // sum += 1 for the lanes in `m` (carry-in add).
@@ -282,7 +285,7 @@ __device__ __forceinline__ void isa_step64(u64x2& st, u64x2 ch, int32_t& top, ui
         "s_waitcnt lgkmcnt(0)"
         : [s0] "+v"(st.x), [s1] "+v"(st.y), [top] "+v"(top), [sv] "=&s"(sv)
         : [c0] "v"(ch.x), [c1] "v"(ch.y), [pm] "s"(pm), [dm] "s"(dm), [qm] "s"(qm)
-        : "memory");
+        : "memory", "scc");
 }
 
 // As isa_step64 with the frame as four dwords: one ds_write_b128 /
@@ -297,7 +300,7 @@ __device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, u
         "s_mov_b64 exec, %[sv]"
         : [top] "+v"(top), [sv] "=&s"(sv)
         : [pm] "s"(pm), [st] "v"(st)
-        : "memory");
+        : "memory", "scc");
     st.x = isa_sel(dm, ch.x, st.x);
     st.y = isa_sel(dm, ch.y, st.y);
     st.z = isa_sel(dm, ch.z, st.z);
@@ -310,7 +313,7 @@ __device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, u
         "s_waitcnt lgkmcnt(0)"
         : [st] "+v"(st), [top] "+v"(top), [sv] "=&s"(sv)
         : [qm] "s"(qm)
-        : "memory");
+        : "memory", "scc");
 }
 
 // LOOP selects the inner-loop form: 0 = plain C++ (the compiler places the
@@ -337,6 +340,8 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     uint64_t wtotal = 0;                  // weighted total, single-instance launches
     bool has_task = false;                // holds an entry not yet retired
     bool exhausted = !PERSISTENT;         // no entries left to claim (wave-uniform)
+    bool claimed_all = false;             // head has passed the end (wave-uniform)
+    uint64_t qlo = 0, qhi = 0;            // claimed entries not yet taken (wave-uniform)
 
     // Takes entry `i`: loads its triple, writes the sentinel and settles the
     // cases that need no search (a full board, the last row, no free square).
@@ -408,18 +413,36 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
             has_task = false;
         }
         if (PERSISTENT && !exhausted) {
+            // Idle lanes take, in rank order, the wave's unused claimed
+            // entries [qlo, qhi) first, then a fresh block of at least
+            // P.claim entries claimed with one atomic add.
             const uint64_t idle = __ballot(!has_task);
             if (idle != 0) {
                 const uint32_t want = (uint32_t)__popcll(idle);
-                const int leader = __ffsll((unsigned long long)idle) - 1;
-                uint64_t first = 0;
-                if ((int)lane == leader) first = atomicAdd(P.head, (unsigned long long)want);
-                first = shfl_u64(first, leader);
-                if (!has_task) {
-                    const uint64_t i = first + lane_rank(idle);
-                    if (i < P.len) take(i);
+                const uint64_t have = qhi - qlo;
+                uint64_t nlo = 0, nhi = 0;
+                if (have < want && !claimed_all) {
+                    const uint64_t grab = max((uint64_t)(want - have), (uint64_t)P.claim);
+                    const int leader = __ffsll((unsigned long long)idle) - 1;
+                    uint64_t first = 0;
+                    if ((int)lane == leader) first = atomicAdd(P.head, (unsigned long long)grab);
+                    first = shfl_u64(first, leader);
+                    nlo = min(first, P.len);
+                    nhi = min(first + grab, P.len);
+                    if (first + grab >= P.len) claimed_all = true;
                 }
-                if (first + want >= P.len) exhausted = true;
+                if (!has_task) {
+                    const uint64_t rk = lane_rank(idle);
+                    if (rk < have) take(qlo + rk);
+                    else if (nlo + (rk - have) < nhi) take(nlo + (rk - have));
+                }
+                if (want <= have) {
+                    qlo += want;
+                } else {
+                    qlo = min(nlo + (want - have), nhi);
+                    qhi = nhi;
+                }
+                if (claimed_all && qlo >= qhi) exhausted = true;
             }
         }
         if (!__any(v != 0u)) {
@@ -670,6 +693,18 @@ static int loop_form() {
         return kDefaultLoop;
     }();
     return form;
+}
+
+uint32_t default_claim() {
+    static const uint32_t v = [] {
+        const char* e = std::getenv("NQ_CLAIM");
+        if (e && *e) {
+            const long x = std::strtol(e, nullptr, 10);
+            if (x >= 0 && x <= 4096) return (uint32_t)x;
+        }
+        return 0u;
+    }();
+    return v;
 }
 
 uint32_t default_idle_min() {

@@ -57,6 +57,9 @@ struct DfsParams {
                                     // are never used to index (the entry is rejected)
     uint32_t idle_min;              // persistent: visit the scheduler early once this many
                                     // lanes of a wave are idle (0 = every refill_every steps)
+    uint32_t claim;                 // persistent: entries a wave claims per atomic on head
+                                    // (at least what its idle lanes need); the surplus is
+                                    // handed out at the wave's later visits
     uint32_t* remaining;
     const uint32_t* inst_gen;
     unsigned long long* host_val;
@@ -137,6 +140,7 @@ int tune_lookup(uint32_t n, nq_tuned* out);
 // between chunks of steps (NQ_IDLE_MIN in the environment overrides, for
 // measurements).
 uint32_t default_idle_min();
+uint32_t default_claim();
 
 // Records a failing hipError_t for nq_last_hip_error().
 void set_hip_error(int err);

@@ -350,6 +350,7 @@ int admit_and_launch(nq_server* s) {
     P.frames = s->max_frames;
     P.refill_every = s->launch.refill_every ? s->launch.refill_every : 512u;
     P.idle_min = default_idle_min();
+    P.claim = default_claim();
     P.reverse = 0;                                      // arrival order
     P.base = epoch_start % s->ring_cap;
     P.wrap = s->ring_cap;

@@ -97,6 +97,7 @@ int trial(uint32_t n, uint32_t depth, const ResidentFrontier& fr, uint32_t waves
     P.totals = fr.total; P.head = fr.total + 1;
     P.len = fr.len; P.n = n; P.frames = frames; P.refill_every = refill; P.reverse = 1;
     P.idle_min = default_idle_min();
+    P.claim = default_claim();
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e;
     if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
