@@ -10,8 +10,9 @@ value = DFS nodes per second = nodes(20, k) / step time, where nodes(20, k) is
 the oracle's node count (queens placed in rows k..18 below every pre-placed
 prefix), read from tests/golden/oracle_runs.txt.
 
-The pre-placement depth and launch shape come from nq_autotune (depths 5..8)
-unless --depth is given.  Printed: one JSON line with the metric, the "plain"
+The pre-placement depth and launch shape come from nq_autotune (depths 6..10)
+unless --depth is given.  Frontiers deeper than 8 rows are built on the host at
+depth k-2 and expanded on the device (nq_expand) before the timed region.  Printed: one JSON line with the metric, the "plain"
 form (one launch per row-0 column over the same frontier), the end-to-end
 nq_count wall time, the int-ALU roofline of the DFS kernel, the ragged
 256-instance batch (one graph replay), the serving loop at a few request
@@ -157,6 +158,21 @@ def bench_serving(nq, known, rates, seconds):
     return res
 
 
+def device_frontier(nq, torch, dev, k):
+    """The N=20 depth-k frontier as device tensors (cols, ld, rd int32, weight
+    uint8): built on the host, and for k > 8 at depth k-2 and expanded by two
+    rows on the device."""
+    hk = k if k <= 8 else k - 2
+    cols, ld, rd, w = nq.frontier(N, hk)
+    t = [torch.from_numpy(x.view(np.int32)).to(dev) for x in (cols, ld, rd)]
+    tw = torch.from_numpy(w).to(dev)
+    if hk == k:
+        return t[0], t[1], t[2], tw
+    out = nq.expand(N, k - hk, t[0], t[1], t[2], tw)
+    torch.cuda.synchronize()
+    return out
+
+
 def profile_run(nq, torch, k, args):
     """A short program for rocprofv3 counter passes: a plain copy of known size,
     then one DFS launch of the benchmark workload."""
@@ -167,24 +183,25 @@ def profile_run(nq, torch, k, args):
     dst.copy_(src)                                   # 256 MiB read + 256 MiB written
     torch.cuda.synchronize()
     del src, dst
-    cols, ld, rd, w = nq.frontier(N, k)
-    t = [torch.from_numpy(x.view(np.int32)).to(dev) for x in (cols, ld, rd)]
-    tw = torch.from_numpy(w).to(dev)
-    counts = torch.empty(len(cols), dtype=torch.int64, device=dev)
+    c, l, r, tw = device_frontier(nq, torch, dev, k)
+    t = [c, l, r]
+    counts = torch.empty(c.numel(), dtype=torch.int64, device=dev)
     total = torch.zeros(1, dtype=torch.int64, device=dev)
     _, _, ms = nq.count_subproblems(N, *t, weight=tw, counts=counts, total=total, depth=k,
                                     timing=True, waves_per_cu=args.waves_per_cu,
                                     refill_every=args.refill)
     if int(total.item()) != EXPECT:
         raise SystemExit(f"bench.py: profile total {int(total.item())} != {EXPECT}")
-    print(f"[bench] profile: copy 256 MiB, DFS N={N} k={k} F={len(cols)} kernel {ms:.1f} ms",
+    print(f"[bench] profile: copy 256 MiB, DFS N={N} k={k} F={c.numel()} kernel {ms:.1f} ms",
           file=sys.stderr, flush=True)
 
 
 def cpu_baseline(k, budget_s):
-    """The oracle on a seeded sample of the N=20 frontier, all host cores."""
+    """The oracle on a seeded sample of the N=20 frontier (depth min(k, 8), so
+    that the prefix list stays small), all host cores."""
     import oracle
     cores = min(os.cpu_count() or 1, 16)
+    k = min(k, 8)
     pre, _ = oracle.frontier(N, k)
     rng = np.random.default_rng(20251112)
     order = rng.permutation(len(pre))
@@ -210,7 +227,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--depth", type=int, default=0, help="0 = autotune over 5..8")
+    ap.add_argument("--depth", type=int, default=0, help="0 = autotune over 6..10")
     ap.add_argument("--tune-ms", type=float, default=40000.0)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--serve-rates", default="25,100", help="COUNT requests/s, comma list")
@@ -241,8 +258,8 @@ def main():
 
     tuned = None
     if args.depth == 0:
-        print("[bench] autotune N=20 over depths 5..8", file=sys.stderr, flush=True)
-        tuned = nq.autotune(N, 5, 8, budget_ms=args.tune_ms)
+        print("[bench] autotune N=20 over depths 6..10", file=sys.stderr, flush=True)
+        tuned = nq.autotune(N, 6, 10, budget_ms=args.tune_ms)
         print(f"[bench] tuned {tuned}", file=sys.stderr, flush=True)
         if tuned["count"] != EXPECT:
             raise SystemExit(f"bench.py: autotune count {tuned['count']} != {EXPECT}")
@@ -253,13 +270,9 @@ def main():
             args.refill = tuned["refill_every"]
     else:
         k = args.depth
-    cols, ld, rd, w = nq.frontier(N, k)
-    F = len(cols)
     dev = torch.device("cuda:0")
-    t_cols = torch.from_numpy(cols.view(np.int32)).to(dev)
-    t_ld = torch.from_numpy(ld.view(np.int32)).to(dev)
-    t_rd = torch.from_numpy(rd.view(np.int32)).to(dev)
-    t_w = torch.from_numpy(w).to(dev)
+    t_cols, t_ld, t_rd, t_w = device_frontier(nq, torch, dev, k)
+    F = t_cols.numel()
     counts = torch.empty(F, dtype=torch.int64, device=dev)
     total = torch.zeros(1, dtype=torch.int64, device=dev)
     host_total = torch.zeros(1, dtype=torch.int64).pin_memory()

@@ -151,6 +151,9 @@ typedef struct nq_opts {
     uint64_t* d_nodes;       /* nq_count_subproblems only, optional device uint64[len]:
                                 DFS nodes of each subproblem (queens placed in rows
                                 placed..n-2); selects the node-counting kernel        */
+    uint32_t claim;          /* persistent mode: entries a wave takes from the shared
+                                work head per atomic add (0 = default); what its idle
+                                lanes do not need yet feeds its later refills         */
 } nq_opts;
 
 /*
@@ -163,6 +166,9 @@ typedef struct nq_opts {
  * weighted total in *out_total.  Synchronous: returns after the result is on the
  * host.  If opts->counts_out is set, it receives the per-subproblem counts in
  * frontier order (NQ_ERANGE if counts_capacity < F).  n in [1, 28].
+ * opts->depth == 0 selects the depth nq_autotune found for n in this process,
+ * else the shallowest depth whose frontier has at least 2^29 entries (at most
+ * n - 4, and under 2^32 entries).
  */
 int nq_count(uint32_t n, const nq_opts* opts, uint64_t* out_total);
 

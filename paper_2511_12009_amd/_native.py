@@ -36,6 +36,7 @@ class NqOpts(ct.Structure):
         ("counts_capacity", ct.c_uint64),
         ("kernel_ms_out", ct.POINTER(ct.c_double)),
         ("d_nodes", ct.c_void_p),
+        ("claim", ct.c_uint32),
     ]
 
 
@@ -141,8 +142,9 @@ FLAG_FORWARD_ORDER = 1
 
 
 def _opts(depth=0, mode="persistent", wg_size=0, waves_per_cu=0, refill_every=0, stream=None,
-          flags=0):
+          flags=0, claim=0):
     o = NqOpts()
+    o.claim = claim
     o.flags = flags
     o.depth = depth
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -214,12 +216,12 @@ def expand(n: int, rows: int, cols, ld, rd, weight=None, stream=None):
 
 def count(n: int, depth: int = 0, mode="persistent", wg_size: int = 0, waves_per_cu: int = 0,
           refill_every: int = 0, counts: bool = False, timing: bool = False, stream=None,
-          forward: bool = False):
+          forward: bool = False, claim: int = 0):
     """Q(n).  With counts=True also the per-subproblem counts (numpy uint64, frontier
     order); with timing=True also the DFS kernel time in ms.  Synchronous."""
     o = _opts(depth, mode, wg_size, waves_per_cu, refill_every,
               stream if stream is None else _stream_handle(stream),
-              FLAG_FORWARD_ORDER if forward else 0)
+              FLAG_FORWARD_ORDER if forward else 0, claim)
     buf = None
     if counts:
         if depth == 0:
@@ -243,7 +245,7 @@ def count(n: int, depth: int = 0, mode="persistent", wg_size: int = 0, waves_per
 def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None,
                       depth: int = 0, mode="persistent", wg_size: int = 0,
                       waves_per_cu: int = 0, refill_every: int = 0, stream=None,
-                      timing: bool = False, nodes=None, forward: bool = False):
+                      timing: bool = False, nodes=None, forward: bool = False, claim: int = 0):
     """Counts every subtree of device-resident triples (torch int32 CUDA tensors).
 
     ``counts`` (int64[F]) and ``total`` (int64[1], accumulated) are torch tensors
@@ -265,7 +267,7 @@ def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None
     if total is None:
         total = torch.zeros(1, dtype=torch.int64, device=cols.device)
     o = _opts(depth, mode, wg_size, waves_per_cu, refill_every, _stream_handle(stream),
-              FLAG_FORWARD_ORDER if forward else 0)
+              FLAG_FORWARD_ORDER if forward else 0, claim)
     if nodes is not None:
         if nodes.dtype != torch.int64 or nodes.numel() != length or not nodes.is_cuda:
             raise ValueError("nodes must be an int64 CUDA tensor of the same length")
@@ -282,13 +284,13 @@ def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None
 
 
 def count_batch(ns, depths=None, mode="persistent", wg_size: int = 0, waves_per_cu: int = 0,
-                refill_every: int = 0, stream=None):
+                refill_every: int = 0, stream=None, claim: int = 0):
     """[Q(n) for n in ns], all instances in one persistent launch."""
     ns_a = np.ascontiguousarray(np.asarray(ns, dtype=np.uint32))
     d_a = None if depths is None else np.ascontiguousarray(np.asarray(depths, dtype=np.uint32))
     out = np.zeros(max(len(ns_a), 1), np.uint64)
     o = _opts(0, mode, wg_size, waves_per_cu, refill_every,
-              stream if stream is None else _stream_handle(stream))
+              stream if stream is None else _stream_handle(stream), 0, claim)
     p32 = lambda a: None if a is None else a.ctypes.data_as(ct.POINTER(ct.c_uint32))  # noqa: E731
     _check(lib().nq_count_batch(len(ns_a), p32(ns_a), p32(d_a), ct.byref(o),
                                 out.ctypes.data_as(ct.POINTER(ct.c_uint64))), "nq_count_batch")
@@ -299,11 +301,11 @@ class Batch:
     """A replayable batch plan (nq_batch_create / nq_batch_run / nq_batch_destroy)."""
 
     def __init__(self, ns, depths=None, depth: int = 0, wg_size: int = 0, waves_per_cu: int = 0,
-                 refill_every: int = 0, forward: bool = False):
+                 refill_every: int = 0, forward: bool = False, claim: int = 0):
         self.ns = np.ascontiguousarray(np.asarray(ns, dtype=np.uint32))
         self._d = None if depths is None else np.ascontiguousarray(np.asarray(depths, np.uint32))
         o = _opts(depth, "persistent", wg_size, waves_per_cu, refill_every, None,
-                  FLAG_FORWARD_ORDER if forward else 0)
+                  FLAG_FORWARD_ORDER if forward else 0, claim)
         h = ct.c_void_p()
         p32 = lambda a: None if a is None else a.ctypes.data_as(ct.POINTER(ct.c_uint32))  # noqa
         _check(lib().nq_batch_create(len(self.ns), p32(self.ns), p32(self._d), ct.byref(o),

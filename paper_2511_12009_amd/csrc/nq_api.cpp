@@ -75,18 +75,32 @@ uint32_t opt_mode(const nq_opts* o) {
 }
 
 // Default pre-placement depth: the shallowest depth whose frontier has at least
-// `target` entries, capped so that every subtree keeps a few rows of search.
+// 2^29 entries (a few thousand DFS nodes per entry at N = 20, small enough for
+// the persistent scheduler to balance), capped so that every subtree keeps
+// two rows of search and the frontier stays under 2^32 entries.  Sizes are
+// exact up to depth 8 (host enumeration) and extrapolated by the last growth
+// ratio beyond it, where nq_count builds the frontier by device expansion.
 uint32_t auto_depth(uint32_t n) {
-    const uint64_t target = 1u << 20;
-    uint32_t cap = n > 4 ? n - 4 : 1;
-    cap = std::min<uint32_t>(cap, 8);
-    for (uint32_t k = 1; k < cap; ++k) {
-        uint64_t f = 0;
+    const uint64_t target = 1ull << 29, limit = 1ull << 32;
+    const uint32_t cap = n > 4 ? n - 4 : 1;
+    uint64_t prev = 0, f = 0;
+    uint32_t k = 1;
+    for (; k <= std::min<uint32_t>(cap, 8); ++k) {
+        prev = f;
         if (frontier_fill(n, k, nullptr, nullptr, nullptr, nullptr, 0, &f, nullptr) != NQ_OK)
             return 1;
         if (f >= target) return k;
     }
-    return std::max<uint32_t>(1, std::min(cap, n));
+    --k;                                    // deepest enumerated depth
+    if (k < cap && prev > 0 && f > prev) {
+        const double ratio = (double)f / (double)prev;
+        double est = (double)f;
+        while (k < cap && est < (double)target && est * ratio < (double)limit) {
+            est *= ratio;
+            ++k;
+        }
+    }
+    return std::max<uint32_t>(1, k);
 }
 
 uint32_t refill_default(const nq_opts* o) {
@@ -122,7 +136,7 @@ static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
     P.counts = d_counts; P.totals = d_total; P.head = head; P.nodes = d_nodes;
     P.len = len; P.n = n; P.frames = frames; P.refill_every = refill_default(opts);
     P.idle_min = default_idle_min();
-    P.claim = default_claim();
+    P.claim = (opts && opts->claim) ? opts->claim : default_claim(len, cfg);
     P.reverse = (opts && (opts->flags & NQ_FLAG_FORWARD_ORDER)) ? 0u : 1u;
     EventTimer t;
     if (kernel_ms && (rc = t.start(s)) != NQ_OK) return rc;
@@ -133,6 +147,86 @@ static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
         if (e != hipSuccess && rc == NQ_OK) { set_hip_error((int)e); rc = NQ_EDEVICE; }
     }
     return rc;
+}
+
+DeviceFrontier::~DeviceFrontier() {
+    if (dev) (void)hipFree(dev);
+}
+
+int build_device_frontier(uint32_t n, uint32_t depth, void* stream, DeviceFrontier* out) {
+    if (!out || out->dev) return NQ_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t host_depth = depth >= 7 ? depth - std::min<uint32_t>(2, depth - 5) : depth;
+    const uint32_t rows = depth - host_depth;
+    uint64_t Fh = 0;
+    std::vector<uint64_t> first_row;
+    int rc = frontier_fill(n, host_depth, nullptr, nullptr, nullptr, nullptr, 0, &Fh, nullptr);
+    if (rc != NQ_OK) return rc;
+    std::vector<uint32_t> hc(Fh), hl(Fh), hr(Fh);
+    std::vector<uint8_t> hw(Fh);
+    rc = frontier_fill(n, host_depth, hc.data(), hl.data(), hr.data(), hw.data(), Fh, &Fh,
+                       &first_row);
+    if (rc != NQ_OK) return rc;
+    DevBuf shallow, scratch;
+    uint64_t F = Fh;
+    char* sb = nullptr;
+    if (rows) {
+        // shallow frontier + expansion scratch, then the size of the deep one
+        if ((rc = shallow.alloc(Fh * 13 + 64)) != NQ_OK) return rc;
+        sb = shallow.as<char>();
+        if (Fh) {
+            NQ_HIP(hipMemcpyAsync(sb, hc.data(), Fh * 4, hipMemcpyHostToDevice, s));
+            NQ_HIP(hipMemcpyAsync(sb + Fh * 4, hl.data(), Fh * 4, hipMemcpyHostToDevice, s));
+            NQ_HIP(hipMemcpyAsync(sb + Fh * 8, hr.data(), Fh * 4, hipMemcpyHostToDevice, s));
+            NQ_HIP(hipMemcpyAsync(sb + Fh * 12, hw.data(), Fh, hipMemcpyHostToDevice, s));
+        }
+        if ((rc = scratch.alloc(expand_scratch_bytes(Fh))) != NQ_OK) return rc;
+        rc = expand_device(n, rows, reinterpret_cast<uint32_t*>(sb),
+                           reinterpret_cast<uint32_t*>(sb + Fh * 4),
+                           reinterpret_cast<uint32_t*>(sb + Fh * 8),
+                           reinterpret_cast<uint8_t*>(sb + Fh * 12), Fh, nullptr, nullptr,
+                           nullptr, nullptr, 0, &F, scratch.p, s);
+        if (rc != NQ_OK) return rc;
+        // row-0 runs of the deep frontier: the expansion offsets of the
+        // shallow runs' starts (offsets[Fh] = F)
+        const uint64_t* offs = scratch.as<uint64_t>() + (Fh + 1);
+        for (auto& o : first_row) {
+            uint64_t v = 0;
+            NQ_HIP(hipMemcpy(&v, offs + o, 8, hipMemcpyDeviceToHost));
+            o = v;
+        }
+    }
+    const size_t o_ld = F * 4, o_rd = 2 * F * 4, o_w = 3 * F * 4;
+    DevBuf arr;
+    if ((rc = arr.alloc(o_w + F + 16)) != NQ_OK) return rc;
+    char* b = arr.as<char>();
+    if (rows) {
+        uint64_t got = 0;
+        rc = expand_device(n, rows, reinterpret_cast<uint32_t*>(sb),
+                           reinterpret_cast<uint32_t*>(sb + Fh * 4),
+                           reinterpret_cast<uint32_t*>(sb + Fh * 8),
+                           reinterpret_cast<uint8_t*>(sb + Fh * 12), Fh,
+                           reinterpret_cast<uint32_t*>(b), reinterpret_cast<uint32_t*>(b + o_ld),
+                           reinterpret_cast<uint32_t*>(b + o_rd),
+                           reinterpret_cast<uint8_t*>(b + o_w), F, &got, scratch.p, s);
+        if (rc != NQ_OK) return rc;
+    } else if (F) {
+        NQ_HIP(hipMemcpyAsync(b, hc.data(), F * 4, hipMemcpyHostToDevice, s));
+        NQ_HIP(hipMemcpyAsync(b + o_ld, hl.data(), F * 4, hipMemcpyHostToDevice, s));
+        NQ_HIP(hipMemcpyAsync(b + o_rd, hr.data(), F * 4, hipMemcpyHostToDevice, s));
+        NQ_HIP(hipMemcpyAsync(b + o_w, hw.data(), F, hipMemcpyHostToDevice, s));
+    }
+    // the host vectors and the scratch die here
+    NQ_HIP(hipStreamSynchronize(s));
+    out->dev = arr.p;
+    arr.p = nullptr;
+    out->len = F;
+    out->cols = reinterpret_cast<uint32_t*>(b);
+    out->ld = reinterpret_cast<uint32_t*>(b + o_ld);
+    out->rd = reinterpret_cast<uint32_t*>(b + o_rd);
+    out->w = reinterpret_cast<uint8_t*>(b + o_w);
+    out->first_row = std::move(first_row);
+    return NQ_OK;
 }
 
 }  // namespace nqi
@@ -215,75 +309,21 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
     const uint32_t depth = local.depth ? local.depth : auto_depth(n);
     if (depth > n) return NQ_EINVAL;
     try {
-        // Frontier: built on the host at a shallow depth and, for deep
-        // pre-placement, expanded on the device (nq_expand) by up to 2 rows.
-        const uint32_t host_depth = depth >= 7 ? depth - std::min<uint32_t>(2, depth - 5) : depth;
-        const uint32_t rows = depth - host_depth;
-        uint64_t Fh = 0;
-        std::vector<uint64_t> first_row;
-        int rc = frontier_fill(n, host_depth, nullptr, nullptr, nullptr, nullptr, 0, &Fh, nullptr);
-        if (rc != NQ_OK) return rc;
-        std::vector<uint32_t> hc(Fh), hl(Fh), hr(Fh);
-        std::vector<uint8_t> hw(Fh);
-        rc = frontier_fill(n, host_depth, hc.data(), hl.data(), hr.data(), hw.data(), Fh, &Fh,
-                           &first_row);
-        if (rc != NQ_OK) return rc;
         hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
-        DevBuf shallow, scratch;
-        uint64_t F = Fh;
-        if (rows) {
-            // shallow frontier + expansion scratch, then the size of the deep one
-            if ((rc = shallow.alloc(Fh * 13 + 64)) != NQ_OK) return rc;
-            char* sb = shallow.as<char>();
-            if (Fh) {
-                NQ_HIP(hipMemcpyAsync(sb, hc.data(), Fh * 4, hipMemcpyHostToDevice, s));
-                NQ_HIP(hipMemcpyAsync(sb + Fh * 4, hl.data(), Fh * 4, hipMemcpyHostToDevice, s));
-                NQ_HIP(hipMemcpyAsync(sb + Fh * 8, hr.data(), Fh * 4, hipMemcpyHostToDevice, s));
-                NQ_HIP(hipMemcpyAsync(sb + Fh * 12, hw.data(), Fh, hipMemcpyHostToDevice, s));
-            }
-            if ((rc = scratch.alloc(expand_scratch_bytes(Fh))) != NQ_OK) return rc;
-            rc = expand_device(n, rows, reinterpret_cast<uint32_t*>(sb),
-                               reinterpret_cast<uint32_t*>(sb + Fh * 4),
-                               reinterpret_cast<uint32_t*>(sb + Fh * 8),
-                               reinterpret_cast<uint8_t*>(sb + Fh * 12), Fh, nullptr, nullptr,
-                               nullptr, nullptr, 0, &F, scratch.p, s);
-            if (rc != NQ_OK) return rc;
-            // row-0 runs of the deep frontier: the expansion offsets of the
-            // shallow runs' starts (offsets[Fh] = F)
-            const uint64_t* offs = scratch.as<uint64_t>() + (Fh + 1);
-            for (auto& o : first_row) {
-                uint64_t v = 0;
-                NQ_HIP(hipMemcpy(&v, offs + o, 8, hipMemcpyDeviceToHost));
-                o = v;
-            }
-        }
+        DeviceFrontier fr;
+        int rc = build_device_frontier(n, depth, s, &fr);
+        if (rc != NQ_OK) return rc;
+        const uint64_t F = fr.len;
+        const std::vector<uint64_t>& first_row = fr.first_row;
         if (opts && opts->counts_out && opts->counts_capacity < F) return NQ_ERANGE;
-        DevBuf buf;
-        // Layout: cols | ld | rd | counts (only when asked for) | total | weight.
+        // counts (only when asked for) | total
         const bool want_counts = opts && opts->counts_out;
-        const size_t off_ld = F * 4, off_rd = 2 * F * 4, off_cnt = (3 * F * 4 + 7) & ~size_t(7);
-        const size_t off_tot = off_cnt + (want_counts ? F * 8 : 0), off_w = off_tot + 8;
-        if ((rc = buf.alloc(off_w + F)) != NQ_OK) return rc;
+        DevBuf buf;
+        const size_t off_tot = want_counts ? F * 8 : 0;
+        if ((rc = buf.alloc(off_tot + 8)) != NQ_OK) return rc;
         char* b = buf.as<char>();
-        if (rows) {
-            char* sb = shallow.as<char>();
-            uint64_t got = 0;
-            rc = expand_device(n, rows, reinterpret_cast<uint32_t*>(sb),
-                               reinterpret_cast<uint32_t*>(sb + Fh * 4),
-                               reinterpret_cast<uint32_t*>(sb + Fh * 8),
-                               reinterpret_cast<uint8_t*>(sb + Fh * 12), Fh,
-                               reinterpret_cast<uint32_t*>(b),
-                               reinterpret_cast<uint32_t*>(b + off_ld),
-                               reinterpret_cast<uint32_t*>(b + off_rd),
-                               reinterpret_cast<uint8_t*>(b + off_w), F, &got, scratch.p, s);
-            if (rc != NQ_OK) return rc;
-        } else if (F) {
-            NQ_HIP(hipMemcpyAsync(b, hc.data(), F * 4, hipMemcpyHostToDevice, s));
-            NQ_HIP(hipMemcpyAsync(b + off_ld, hl.data(), F * 4, hipMemcpyHostToDevice, s));
-            NQ_HIP(hipMemcpyAsync(b + off_rd, hr.data(), F * 4, hipMemcpyHostToDevice, s));
-            NQ_HIP(hipMemcpyAsync(b + off_w, hw.data(), F, hipMemcpyHostToDevice, s));
-        }
         auto* d_total = reinterpret_cast<unsigned long long*>(b + off_tot);
+        uint64_t* d_counts = want_counts ? reinterpret_cast<uint64_t*>(b) : nullptr;
         if ((rc = launch_zero_u64(d_total, 1, s)) != NQ_OK) return rc;
         const uint32_t mode = opt_mode(opts);
         double ms = 0.0, ms_part = 0.0;
@@ -292,30 +332,21 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
             // per GPU slice), each over its contiguous run of the frontier.
             for (size_t j = 0; j + 1 < first_row.size(); ++j) {
                 const uint64_t lo = first_row[j], hi = first_row[j + 1];
-                rc = run_device(n, reinterpret_cast<uint32_t*>(b) + lo,
-                                reinterpret_cast<uint32_t*>(b + off_ld) + lo,
-                                reinterpret_cast<uint32_t*>(b + off_rd) + lo,
-                                reinterpret_cast<uint8_t*>(b + off_w) + lo, hi - lo,
-                                want_counts ? reinterpret_cast<uint64_t*>(b + off_cnt) + lo
-                                            : nullptr,
-                                d_total, depth, opts, opts && opts->kernel_ms_out ? &ms_part
-                                                                                  : nullptr);
+                rc = run_device(n, fr.cols + lo, fr.ld + lo, fr.rd + lo, fr.w + lo, hi - lo,
+                                d_counts ? d_counts + lo : nullptr, d_total, depth, opts,
+                                opts && opts->kernel_ms_out ? &ms_part : nullptr);
                 if (rc != NQ_OK) return rc;
                 ms += ms_part;
             }
         } else {
-            rc = run_device(n, reinterpret_cast<uint32_t*>(b),
-                            reinterpret_cast<uint32_t*>(b + off_ld),
-                            reinterpret_cast<uint32_t*>(b + off_rd),
-                            reinterpret_cast<uint8_t*>(b + off_w), F,
-                            want_counts ? reinterpret_cast<uint64_t*>(b + off_cnt) : nullptr,
-                            d_total, depth, opts, opts && opts->kernel_ms_out ? &ms : nullptr);
+            rc = run_device(n, fr.cols, fr.ld, fr.rd, fr.w, F, d_counts, d_total, depth, opts,
+                            opts && opts->kernel_ms_out ? &ms : nullptr);
             if (rc != NQ_OK) return rc;
         }
         uint64_t total = 0;
         NQ_HIP(hipMemcpyAsync(&total, d_total, 8, hipMemcpyDeviceToHost, s));
         if (want_counts && F)
-            NQ_HIP(hipMemcpyAsync(opts->counts_out, b + off_cnt, F * 8, hipMemcpyDeviceToHost, s));
+            NQ_HIP(hipMemcpyAsync(opts->counts_out, d_counts, F * 8, hipMemcpyDeviceToHost, s));
         NQ_HIP(hipStreamSynchronize(s));
         if (want_counts)
             for (uint64_t i = 0; i < F; ++i)

@@ -154,7 +154,6 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
         P.frames = frames;
         P.refill_every = (opts && opts->refill_every) ? opts->refill_every : 512u;
         P.idle_min = default_idle_min();
-        P.claim = default_claim();
         P.reverse = (opts && (opts->flags & NQ_FLAG_FORWARD_ORDER)) ? 0u : 1u;
         DeviceInfo dev;
         if ((rc = device_info(&dev)) != NQ_OK) return fail(rc);
@@ -162,6 +161,7 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
                               opts ? opts->waves_per_cu : 0, frames, total, false, leafctr,
                               &b->cfg)) != NQ_OK)
             return fail(rc);
+        P.claim = (opts && opts->claim) ? opts->claim : default_claim(total, b->cfg);
         // Capture: zero totals, zero head + DFS, totals to pinned host memory.
         if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)) !=
             hipSuccess) {

@@ -695,16 +695,21 @@ static int loop_form() {
     return form;
 }
 
-uint32_t default_claim() {
-    static const uint32_t v = [] {
+uint32_t default_claim(uint64_t len, const LaunchCfg& cfg) {
+    static const long env = [] {
         const char* e = std::getenv("NQ_CLAIM");
         if (e && *e) {
             const long x = std::strtol(e, nullptr, 10);
-            if (x >= 0 && x <= 4096) return (uint32_t)x;
+            if (x >= 0 && x <= 4096) return x;
         }
-        return 0u;
+        return -1l;
     }();
-    return v;
+    if (env >= 0) return (uint32_t)env;
+    // A block of up to 256 entries per atomic, but no more than 1/16 of a
+    // wave's share of the frontier, so small launches still spread over every
+    // resident wave (0 = each refill claims exactly its idle lanes).
+    const uint64_t waves = (uint64_t)cfg.grid * (cfg.wg_size / 64u);
+    return (uint32_t)std::min<uint64_t>(256, waves ? len / (waves * 16) : 0);
 }
 
 uint32_t default_idle_min() {

@@ -140,10 +140,33 @@ int tune_lookup(uint32_t n, nq_tuned* out);
 // between chunks of steps (NQ_IDLE_MIN in the environment overrides, for
 // measurements).
 uint32_t default_idle_min();
-uint32_t default_claim();
+// Entries per work-head claim for a persistent launch over `len` entries
+// (NQ_CLAIM in the environment overrides, for measurements).
+uint32_t default_claim(uint64_t len, const LaunchCfg& cfg);
 
 // Records a failing hipError_t for nq_last_hip_error().
 void set_hip_error(int err);
+
+// The frontier of (n, depth) resident in device memory, in one allocation
+// cols | ld | rd | weight (frontier order), plus the start of every row-0 run
+// (then len).  Built on the host (frontier_fill) at a shallow depth and, for
+// depth >= 7, deepened on the device by up to two rows (expand_device), so
+// that frontiers of 10^9 entries never pass through host memory.
+struct DeviceFrontier {
+    void* dev = nullptr;
+    uint64_t len = 0;
+    uint32_t* cols = nullptr;
+    uint32_t* ld = nullptr;
+    uint32_t* rd = nullptr;
+    uint8_t* w = nullptr;
+    std::vector<uint64_t> first_row;
+    DeviceFrontier() = default;
+    DeviceFrontier(const DeviceFrontier&) = delete;
+    DeviceFrontier& operator=(const DeviceFrontier&) = delete;
+    ~DeviceFrontier();
+};
+// Builds it on `stream` and waits for it.  NQ_ENOMEM when it does not fit.
+int build_device_frontier(uint32_t n, uint32_t depth, void* stream, DeviceFrontier* out);
 
 // Frames per lane needed by a subproblem with `placed` queens on an n board.
 inline uint32_t frames_needed(uint32_t n, uint32_t placed) {

@@ -350,7 +350,6 @@ int admit_and_launch(nq_server* s) {
     P.frames = s->max_frames;
     P.refill_every = s->launch.refill_every ? s->launch.refill_every : 512u;
     P.idle_min = default_idle_min();
-    P.claim = default_claim();
     P.reverse = 0;                                      // arrival order
     P.base = epoch_start % s->ring_cap;
     P.wrap = s->ring_cap;
@@ -362,6 +361,7 @@ int admit_and_launch(nq_server* s) {
     const uint64_t waves = (n_entries + 63) / 64;
     const uint64_t per_wg = cfg.wg_size / 64u;
     cfg.grid = (uint32_t)std::min<uint64_t>(cfg.grid, (waves + per_wg - 1) / per_wg);
+    P.claim = default_claim(n_entries, cfg);
     if ((rc = launch_dfs(cfg, P, st)) != NQ_OK) return rc;
     if ((e = hipEventCreateWithFlags(&ep.done, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventRecord(ep.done, st)) != hipSuccess) {

@@ -33,57 +33,31 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::map<TuneKey, nq_tuned> g_tune_cache;
 
-// A frontier resident on the device for the duration of the tuning.
-struct ResidentFrontier {
-    void* dev = nullptr;
-    uint64_t len = 0;
-    uint32_t* cols = nullptr;
-    uint32_t* ld = nullptr;
-    uint32_t* rd = nullptr;
-    uint8_t* w = nullptr;
+// The frontier of one trial depth, resident on the device for the tuning,
+// with the trial's 8-byte total.
+struct TrialFrontier {
+    DeviceFrontier fr;
     unsigned long long* total = nullptr;
-    ~ResidentFrontier() {
-        if (dev) (void)hipFree(dev);
+    ~TrialFrontier() {
+        if (total) (void)hipFree(total);
     }
-    int load(uint32_t n, uint32_t depth) {
-        uint64_t F = 0;
-        int rc = frontier_fill(n, depth, nullptr, nullptr, nullptr, nullptr, 0, &F, nullptr);
+    int load(uint32_t n, uint32_t depth, hipStream_t s) {
+        int rc = build_device_frontier(n, depth, s, &fr);
         if (rc != NQ_OK) return rc;
-        std::vector<uint32_t> hc(F), hl(F), hr(F);
-        std::vector<uint8_t> hw(F);
-        rc = frontier_fill(n, depth, hc.data(), hl.data(), hr.data(), hw.data(), F, &F, nullptr);
-        if (rc != NQ_OK) return rc;
-        const size_t o_ld = F * 4, o_rd = 2 * F * 4, o_w = 3 * F * 4;
-        const size_t o_t = (o_w + F + 15) / 16 * 16;
-        hipError_t e = hipMalloc(&dev, o_t + 16);
+        hipError_t e = hipMalloc((void**)&total, 16);
         if (e != hipSuccess) {
             set_hip_error(e);
-            dev = nullptr;
+            total = nullptr;
             return e == hipErrorOutOfMemory ? NQ_ENOMEM : NQ_EDEVICE;
         }
-        char* b = static_cast<char*>(dev);
-        if (F && ((e = hipMemcpy(b, hc.data(), F * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-                  (e = hipMemcpy(b + o_ld, hl.data(), F * 4, hipMemcpyHostToDevice)) !=
-                      hipSuccess ||
-                  (e = hipMemcpy(b + o_rd, hr.data(), F * 4, hipMemcpyHostToDevice)) !=
-                      hipSuccess ||
-                  (e = hipMemcpy(b + o_w, hw.data(), F, hipMemcpyHostToDevice)) != hipSuccess)) {
-            set_hip_error(e);
-            return NQ_EDEVICE;
-        }
-        len = F;
-        cols = reinterpret_cast<uint32_t*>(b);
-        ld = reinterpret_cast<uint32_t*>(b + o_ld);
-        rd = reinterpret_cast<uint32_t*>(b + o_rd);
-        w = reinterpret_cast<uint8_t*>(b + o_w);
-        total = reinterpret_cast<unsigned long long*>(b + o_t);
         return NQ_OK;
     }
 };
 
 // One timed persistent count; *ms is the device time of zero + DFS.
-int trial(uint32_t n, uint32_t depth, const ResidentFrontier& fr, uint32_t waves_per_cu,
+int trial(uint32_t n, uint32_t depth, const TrialFrontier& tf, uint32_t waves_per_cu,
           uint32_t refill, hipStream_t s, double* ms, uint64_t* total_out) {
+    const DeviceFrontier& fr = tf.fr;
     DeviceInfo dev;
     int rc = device_info(&dev);
     if (rc != NQ_OK) return rc;
@@ -94,10 +68,10 @@ int trial(uint32_t n, uint32_t depth, const ResidentFrontier& fr, uint32_t waves
     if (rc != NQ_OK) return rc;
     DfsParams P{};
     P.cols = fr.cols; P.ld = fr.ld; P.rd = fr.rd; P.weight = fr.w;
-    P.totals = fr.total; P.head = fr.total + 1;
+    P.totals = tf.total; P.head = tf.total + 1;
     P.len = fr.len; P.n = n; P.frames = frames; P.refill_every = refill; P.reverse = 1;
     P.idle_min = default_idle_min();
-    P.claim = default_claim();
+    P.claim = default_claim(fr.len, cfg);
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e;
     if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
@@ -108,7 +82,7 @@ int trial(uint32_t n, uint32_t depth, const ResidentFrontier& fr, uint32_t waves
     rc = NQ_OK;
     e = hipEventRecord(a, s);
     if (e == hipSuccess) {
-        rc = launch_zero_u64(fr.total, 1, s);
+        rc = launch_zero_u64(tf.total, 1, s);
         if (rc == NQ_OK) rc = launch_dfs(cfg, P, s);
         e = hipEventRecord(b, s);
     }
@@ -116,7 +90,7 @@ int trial(uint32_t n, uint32_t depth, const ResidentFrontier& fr, uint32_t waves
     float f = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
     unsigned long long t = 0;
-    if (e == hipSuccess) e = hipMemcpy(&t, fr.total, 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&t, tf.total, 8, hipMemcpyDeviceToHost);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
@@ -141,7 +115,7 @@ int tune_lookup(uint32_t n, nq_tuned* out) {
 int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms, nq_tuned* out) {
     if (n < 4 || n > NQ_MAX_N || !out) return NQ_EINVAL;
     if (depth_lo == 0) depth_lo = std::max<uint32_t>(1, std::min<uint32_t>(n - 2, n > 12 ? n - 14 : 1));
-    if (depth_hi == 0) depth_hi = std::min<uint32_t>(n - 2, depth_lo + 3);
+    if (depth_hi == 0) depth_hi = std::min<uint32_t>(n - 2, depth_lo + 4);
     if (depth_lo > depth_hi || depth_hi > n) return NQ_EINVAL;
     if (budget_ms <= 0) budget_ms = 60000.0;
     hipStream_t s = nullptr;
@@ -158,7 +132,7 @@ int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
     uint64_t expect = 0;
     bool have_expect = false;
     int trials = 0;
-    auto consider = [&](uint32_t depth, const ResidentFrontier& fr, uint32_t wpc, uint32_t rf,
+    auto consider = [&](uint32_t depth, const TrialFrontier& fr, uint32_t wpc, uint32_t rf,
                         bool* better) -> int {
         double ms = 0;
         uint64_t total = 0;
@@ -180,16 +154,16 @@ int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
         // 1. depth, default launch shape.  Each depth is timed twice, the first
         //    run also warming the code object.
         for (uint32_t d = depth_lo; d <= depth_hi && spent < budget_ms; ++d) {
-            ResidentFrontier fr;
-            int rc = fr.load(n, d);
+            TrialFrontier fr;
+            int rc = fr.load(n, d, s);
             if (rc != NQ_OK) return rc;
             bool b = false;
             for (int rep = 0; rep < 2 && spent < budget_ms; ++rep)
                 if ((rc = consider(d, fr, 0, 512, &b)) != NQ_OK) return rc;
         }
         // 2. waves per CU and the visit interval at the best depth.
-        ResidentFrontier fr;
-        int rc = fr.load(n, best.depth);
+        TrialFrontier fr;
+        int rc = fr.load(n, best.depth, s);
         if (rc != NQ_OK) return rc;
         const uint32_t d = best.depth;
         for (uint32_t wpc : {8u, 16u, 24u}) {

@@ -50,7 +50,7 @@ def run(n, k, threads):
 
 
 def write_nodes():
-    """Node counts at depths 4..8 for every even N with an oracle run."""
+    """Node counts at depths j-2..j+4 for every even N with an oracle run at depth j."""
     runs = []
     with open(OUT) as f:
         runs = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
@@ -60,7 +60,7 @@ def write_nodes():
         lines.append((n, j, nodes, "run"))
         if n % 2:
             continue
-        for k in range(max(1, j - 2), min(n, j + 3)):
+        for k in range(max(1, j - 2), min(n, j + 5)):
             if k == j or any(x[0] == n and x[1] == k for x in runs):
                 continue
             if k < j:

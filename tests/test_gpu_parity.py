@@ -54,6 +54,14 @@ def test_small_boards_every_depth(mode, known_counts):
             assert nq.count(n, depth=k, mode=mode) == known_counts[n], (n, k, mode)
 
 
+def test_automatic_depth(known_counts):
+    """depth 0: the library picks the pre-placement (deep ones by device expansion)."""
+    nq = _nq()
+    for n in range(1, 17):
+        _say("auto depth", n)
+        assert nq.count(n) == known_counts[n], n
+
+
 @pytest.mark.parametrize("mode", ["plain", "persistent"])
 def test_n14_depth3_per_subproblem(mode):
     nq = _nq()
@@ -79,6 +87,22 @@ def test_n17_depth5_persistent_per_subproblem():
     idx = np.random.default_rng(17).choice(len(pre), 200, replace=False)
     ref, _ = oracle.count_prefixes(n, pre[idx], threads=8)
     np.testing.assert_array_equal(counts[idx], ref)
+
+
+@pytest.mark.parametrize("claim", [1, 5, 63, 64, 100, 1000, 1 << 20])
+def test_block_claims_per_subproblem(claim):
+    """Persistent refills from per-wave claimed blocks of any size (smaller and
+    larger than a wave, and than the frontier), both claim orders."""
+    nq = _nq()
+    pre, _ = oracle.frontier(14, 3)
+    ref, _ = oracle.count_prefixes(14, pre, threads=8)
+    for forward in (False, True):
+        _say("n14 k3 claim", claim, "forward" if forward else "reverse")
+        total, counts = nq.count(14, depth=3, counts=True, claim=claim, forward=forward)
+        assert total == 365596
+        np.testing.assert_array_equal(counts, ref)
+    _say("n17 k5 claim", claim)
+    assert nq.count(17, depth=5, claim=claim) == 95815104
 
 
 def test_count_subproblems_random_prefixes():
