@@ -116,7 +116,7 @@ def bench_serving(nq, known, rates, seconds):
     import seeded_inputs
     F21 = nq.frontier_size(21, 6)
     res = []
-    with nq.Server(hbm_budget=2 << 30) as srv:
+    with nq.Server(hbm_budget=16 << 30) as srv:
         srv.wait(srv.submit_slice(21, 6, 0, 1))          # builds the resident frontier
         for rate in rates:
             n_req = max(1, int(rate * seconds))

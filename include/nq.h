@@ -256,11 +256,15 @@ int nq_batch_destroy(nq_batch* batch);
  * pre-placed subproblem of Section 1, searched by the DFS of Algorithm 2 /
  * Algorithm 3.  Requests:
  *   NQ_REQ_COUNT  Q(n); depth = pre-placement depth (0 = the server picks the
- *                 shallowest depth with >= 4096 subproblems).
+ *                 shallowest depth with >= 2^18 subproblems, at most n - 4).
  *   NQ_REQ_SLICE  sum(weight * count) over entries [start, start + len) of the
- *                 (n, depth) frontier in nq_frontier order; the frontier is
- *                 built once and kept in device memory, slices are copied out
- *                 of it on the device.
+ *                 (n, depth) frontier in nq_frontier order.
+ * Every (n, depth) frontier is built once and kept in device memory; requests
+ * are copied out of it on the device.  For slices of a frontier of >= 2^16
+ * entries (depth >= 2) the kept frontier is expanded by two rows (one when
+ * n < depth + 10), as far as the budget allows: a slice's subtrees are then
+ * searched as their children, a contiguous range of the expanded frontier with
+ * the same weights, so the result is unchanged and the work spreads wider.
  * A scheduler thread owned by the server admits requests in arrival order while
  * request slots (4096), work-ring space and the LDS stack of the epoch kernel
  * allow, and launches bounded persistent "epochs" over the newly admitted
@@ -271,7 +275,7 @@ int nq_batch_destroy(nq_batch* batch);
  * nq_serve_create: opts may set depth (= the LDS stack frames per lane of the
  * epoch kernel, default 14: a request whose subproblems need more stack than
  * that is refused with NQ_EINVAL at submit), wg_size, waves_per_cu and
- * refill_every; hbm_budget_bytes (0 = 1 GiB) is split between the work ring
+ * refill_every; hbm_budget_bytes (0 = 8 GiB) is split between the work ring
  * (17 B per subproblem) and the resident slice frontiers.
  * nq_serve_submit: non-blocking; NQ_EINVAL for a malformed request, NQ_EFULL
  * when 65536 requests are already waiting.  A request larger than the ring, or
@@ -297,7 +301,8 @@ typedef struct nq_result {
     int32_t status;          /* NQ_OK or why the request failed                    */
     uint32_t reserved;
     uint64_t count;          /* Q(n), or the slice's weighted sum                  */
-    uint64_t entries;        /* subproblems searched for this request              */
+    uint64_t entries;        /* subproblems searched for this request (after the
+                                expansion of slices described above)              */
     uint64_t t_submit_ns, t_admit_ns, t_done_ns;
 } nq_result;
 typedef struct nq_server nq_server;

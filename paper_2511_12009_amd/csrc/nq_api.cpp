@@ -154,10 +154,14 @@ DeviceFrontier::~DeviceFrontier() {
 }
 
 int build_device_frontier(uint32_t n, uint32_t depth, void* stream, DeviceFrontier* out) {
-    if (!out || out->dev) return NQ_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
     const uint32_t host_depth = depth >= 7 ? depth - std::min<uint32_t>(2, depth - 5) : depth;
-    const uint32_t rows = depth - host_depth;
+    return build_device_frontier_at(n, host_depth, depth - host_depth, stream, out, nullptr);
+}
+
+int build_device_frontier_at(uint32_t n, uint32_t host_depth, uint32_t rows, void* stream,
+                             DeviceFrontier* out, std::vector<uint64_t>* offsets) {
+    if (!out || out->dev || rows > 3 || host_depth + rows > n) return NQ_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
     uint64_t Fh = 0;
     std::vector<uint64_t> first_row;
     int rc = frontier_fill(n, host_depth, nullptr, nullptr, nullptr, nullptr, 0, &Fh, nullptr);
@@ -190,11 +194,19 @@ int build_device_frontier(uint32_t n, uint32_t depth, void* stream, DeviceFronti
         // row-0 runs of the deep frontier: the expansion offsets of the
         // shallow runs' starts (offsets[Fh] = F)
         const uint64_t* offs = scratch.as<uint64_t>() + (Fh + 1);
-        for (auto& o : first_row) {
-            uint64_t v = 0;
-            NQ_HIP(hipMemcpy(&v, offs + o, 8, hipMemcpyDeviceToHost));
-            o = v;
+        if (offsets) {
+            offsets->resize(Fh + 1);
+            NQ_HIP(hipMemcpy(offsets->data(), offs, (Fh + 1) * 8, hipMemcpyDeviceToHost));
+            for (auto& o : first_row) o = (*offsets)[o];
+        } else {
+            for (auto& o : first_row) {
+                uint64_t v = 0;
+                NQ_HIP(hipMemcpy(&v, offs + o, 8, hipMemcpyDeviceToHost));
+                o = v;
+            }
         }
+    } else if (offsets) {
+        offsets->clear();
     }
     const size_t o_ld = F * 4, o_rd = 2 * F * 4, o_w = 3 * F * 4;
     DevBuf arr;

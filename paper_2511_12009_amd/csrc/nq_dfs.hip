@@ -666,6 +666,11 @@ __global__ void nq_zero_u64_kernel(unsigned long long* dst, uint64_t count) {
     if (i < count) dst[i] = 0ull;
 }
 
+__global__ void nq_fill_u32_kernel(uint32_t* dst, uint32_t value, uint64_t count) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = value;
+}
+
 template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP>
 static const void* kernel_ptr() {
     return reinterpret_cast<const void*>(&nq_dfs_kernel<PERSISTENT, STATS, LEAFCTR, LOOP>);
@@ -809,6 +814,18 @@ int launch_zero_u64(unsigned long long* dst, uint64_t count, void* stream) {
     const uint64_t grid = (count + block - 1) / block;
     hipLaunchKernelGGL(nq_zero_u64_kernel, dim3((uint32_t)grid), dim3(block), 0,
                        (hipStream_t)stream, dst, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
+    return NQ_OK;
+}
+
+int launch_fill_u32(uint32_t* dst, uint32_t value, uint64_t count, void* stream) {
+    if (count == 0) return NQ_OK;
+    const uint32_t block = 256;
+    const uint64_t grid = (count + block - 1) / block;
+    if (grid > 0x7fffffffull) return NQ_EINVAL;
+    hipLaunchKernelGGL(nq_fill_u32_kernel, dim3((uint32_t)grid), dim3(block), 0,
+                       (hipStream_t)stream, dst, value, count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
     return NQ_OK;

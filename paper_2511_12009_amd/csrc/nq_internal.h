@@ -122,6 +122,8 @@ int launch_slot_init(const SlotInit* recs, uint32_t count, uint32_t* inst_n, uin
 
 // Enqueues dst[0..count) = 0 with a kernel (no memset node in captured graphs).
 int launch_zero_u64(unsigned long long* dst, uint64_t count, void* stream);
+// Enqueues dst[0..count) = value with a kernel.
+int launch_fill_u32(uint32_t* dst, uint32_t value, uint64_t count, void* stream);
 
 // Device frontier expansion (nq_expand.hip): scratch size for `len` parents,
 // and the expansion itself; *out_len gets the child count (the call waits on
@@ -163,10 +165,23 @@ struct DeviceFrontier {
     DeviceFrontier() = default;
     DeviceFrontier(const DeviceFrontier&) = delete;
     DeviceFrontier& operator=(const DeviceFrontier&) = delete;
+    DeviceFrontier(DeviceFrontier&& o) noexcept
+        : dev(o.dev), len(o.len), cols(o.cols), ld(o.ld), rd(o.rd), w(o.w),
+          first_row(std::move(o.first_row)) {
+        o.dev = nullptr;
+    }
+    DeviceFrontier& operator=(DeviceFrontier&&) = delete;
     ~DeviceFrontier();
 };
 // Builds it on `stream` and waits for it.  NQ_ENOMEM when it does not fit.
 int build_device_frontier(uint32_t n, uint32_t depth, void* stream, DeviceFrontier* out);
+// The same from an explicit split: the host frontier of depth host_depth,
+// expanded by `rows` (0..3) on the device.  With `offsets` non-null and rows > 0
+// it also receives, for every host-depth entry i, the index of its first child
+// (offsets[F_host] = len), so that entries [a, b) of the host-depth frontier
+// correspond to [offsets[a], offsets[b]) of the built one.
+int build_device_frontier_at(uint32_t n, uint32_t host_depth, uint32_t rows, void* stream,
+                             DeviceFrontier* out, std::vector<uint64_t>* offsets);
 
 // Frames per lane needed by a subproblem with `placed` queens on an n board.
 inline uint32_t frames_needed(uint32_t n, uint32_t placed) {

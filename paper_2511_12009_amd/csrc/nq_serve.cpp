@@ -1,13 +1,16 @@
 // Serving loop: continuous batching of count requests on one GPU.
 //
 // Requests (a full count Q(n), or the weighted sum over a contiguous slice of
-// a device-resident frontier) arrive at any time.  A scheduler thread admits
-// them in arrival order while request slots, work-ring space and the stack
-// frames of the epoch kernel allow, writes their subproblems into a
-// device-resident ring (host frontier + H2D for counts, device-to-device copies
-// out of the resident frontier for slices), and launches a bounded "epoch": one
-// persistent DFS launch over exactly the entries admitted since the previous
-// epoch.  Epochs rotate over four streams, so new epochs are queued while
+// a frontier) arrive at any time.  Every request is served out of a frontier
+// kept in device memory: built once per (n, depth) and, for slices of a
+// shallow frontier, pre-expanded by up to two rows on the device, so that a
+// slice of a few thousand subtrees becomes a few hundred thousand smaller ones
+// (children are contiguous and in order, so a slice maps to one contiguous
+// range of the expanded frontier) and spreads over the whole GPU.  A scheduler
+// thread admits requests in arrival order while request slots, work-ring space
+// and the stack frames of the epoch kernel allow, copies their subproblems
+// device-to-device into a ring, and launches a bounded "epoch": one persistent
+// DFS launch over exactly the entries admitted since the previous epoch.  Epochs rotate over four streams, so new epochs are queued while
 // older ones still run and their waves fill the CUs as the older epochs
 // drain.  Every retired subproblem decrements its request's remaining counter
 // on the device; the lane that retires the last one publishes the request's
@@ -25,6 +28,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -48,27 +52,33 @@ struct Req {
     uint64_t t_submit = 0, t_admit = 0, t_done = 0;
     uint32_t slot = 0, gen = 0;
     uint64_t ring_start = 0, ring_len = 0;
-    uint32_t depth = 0;          // COUNT: chosen pre-placement depth
+    uint32_t depth = 0;          // pre-placement depth (COUNT: chosen at submit)
     uint64_t entries = 0;        // subproblems of this request
 };
 
-struct Resident {                // a frontier kept on the device for slices
-    void* dev = nullptr;
-    uint64_t len = 0;
-    uint32_t *cols = nullptr, *ld = nullptr, *rd = nullptr;
-    uint8_t* w = nullptr;
+// A frontier kept on the device: the (n, depth) frontier expanded by `rows`;
+// entry i of the (n, depth) frontier owns entries [off[i], off[i + 1]) of `fr`
+// (off empty when rows == 0: entry i is entry i).
+struct Resident {
+    nqi::DeviceFrontier fr;
+    uint32_t rows = 0;
+    uint64_t len = 0;                    // entries of the (n, depth) frontier
+    uint64_t bytes = 0;
+    std::vector<uint64_t> off;
+    uint64_t first(uint64_t i) const { return rows ? off[i] : i; }
 };
 
 struct Epoch {
     hipEvent_t done = nullptr;
     std::vector<nqi::SlotInit> inits;      // host staging kept alive until `done`
-    std::vector<uint32_t> hc, hl, hr, hi;
-    std::vector<uint8_t> hw;
 };
 
 constexpr uint32_t kHeads = 64;
 constexpr uint32_t kStreams = 4;             // epochs in flight at once (divides kHeads)
 constexpr size_t kRingEntryBytes = 4 * 4 + 1;   // cols, ld, rd, inst + weight
+constexpr uint64_t kCountEntries = 1u << 18;    // COUNT: shallowest depth with this many
+constexpr uint64_t kSliceSplit = 1u << 16;      // SLICE residents: expand when a slice of
+                                                // the whole frontier would have fewer
 
 }  // namespace
 
@@ -94,7 +104,8 @@ struct nq_server {
     unsigned long long *h_val = nullptr, *h_flag = nullptr;   // pinned, host view
     unsigned long long *d_val = nullptr, *d_flag = nullptr;   // device view
     hipStream_t streams[kStreams] = {};
-    std::map<std::pair<uint32_t, uint32_t>, Resident> resident;
+    hipStream_t aux = nullptr;              // resident frontier builds
+    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, Resident> resident;   // (n, depth, kind)
 
     // scheduling state (guarded by mu)
     std::mutex mu;
@@ -122,23 +133,30 @@ namespace nqi {
 
 namespace {
 
-// Smallest depth whose frontier has at least `target` entries, within the
-// server's stack budget (frames) and at most n - 2.
+// Smallest depth whose frontier has at least kCountEntries entries, within the
+// server's stack budget (frames) and at most n - 4 (n - 2 for small boards).
 uint32_t count_depth(uint32_t n, uint32_t max_frames) {
     if (n <= 3) return n;                       // tiny boards: full pre-placement
-    const uint32_t hi = n - 2;
+    const uint32_t hi = n > 6 ? n - 4 : n - 2;
     const uint32_t lo = (n >= max_frames + 2) ? std::max<uint32_t>(1, n - 2 - max_frames) : 1u;
     for (uint32_t k = lo; k <= hi; ++k) {
         uint64_t f = 0;
         if (frontier_fill(n, k, nullptr, nullptr, nullptr, nullptr, 0, &f, nullptr) != NQ_OK)
             break;
-        if (f >= 4096) return k;
+        if (f >= kCountEntries) return k;
     }
-    return hi;
+    return std::max(lo, hi);
 }
 
-int ensure_resident(nq_server* s, uint32_t n, uint32_t depth, Resident** out) {
-    auto key = std::make_pair(n, depth);
+// The resident frontier serving (n, depth) requests of one kind, built on
+// first use (on the server's own stream, so running epochs are not waited
+// for).  COUNT residents are the plain frontier (its depth already gives
+// kCountEntries subtrees).  SLICE residents of a frontier of at least
+// kSliceSplit entries, where a slice is a small part of a large search, are
+// expanded by two rows (one when fewer rows would be left below), as far as the
+// resident budget allows.
+int ensure_resident(nq_server* s, uint32_t n, uint32_t depth, uint32_t kind, Resident** out) {
+    auto key = std::make_tuple(n, depth, kind);
     auto it = s->resident.find(key);
     if (it != s->resident.end()) {
         *out = &it->second;
@@ -147,31 +165,27 @@ int ensure_resident(nq_server* s, uint32_t n, uint32_t depth, Resident** out) {
     uint64_t F = 0;
     int rc = frontier_fill(n, depth, nullptr, nullptr, nullptr, nullptr, 0, &F, nullptr);
     if (rc != NQ_OK) return rc;
-    const uint64_t bytes = F * 13 + 64;
-    if (s->resident_bytes + bytes > s->budget / 2) return NQ_ENOMEM;
-    std::vector<uint32_t> hc(F), hl(F), hr(F);
-    std::vector<uint8_t> hw(F);
-    rc = frontier_fill(n, depth, hc.data(), hl.data(), hr.data(), hw.data(), F, &F, nullptr);
-    if (rc != NQ_OK) return rc;
-    Resident r;
-    r.len = F;
-    hipError_t e = hipMalloc(&r.dev, bytes);
-    if (e != hipSuccess) { set_hip_error(e); return NQ_ENOMEM; }
-    char* b = static_cast<char*>(r.dev);
-    r.cols = reinterpret_cast<uint32_t*>(b);
-    r.ld = reinterpret_cast<uint32_t*>(b + F * 4);
-    r.rd = reinterpret_cast<uint32_t*>(b + F * 8);
-    r.w = reinterpret_cast<uint8_t*>(b + F * 12);
-    if (F && ((e = hipMemcpy(r.cols, hc.data(), F * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-              (e = hipMemcpy(r.ld, hl.data(), F * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-              (e = hipMemcpy(r.rd, hr.data(), F * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-              (e = hipMemcpy(r.w, hw.data(), F, hipMemcpyHostToDevice)) != hipSuccess)) {
-        set_hip_error(e);
-        (void)hipFree(r.dev);
-        return NQ_EDEVICE;
+    uint32_t rows = 0;
+    if (kind == NQ_REQ_SLICE && depth >= 2 && F >= kSliceSplit)
+        rows = (n >= depth + 10) ? 2u : (n >= depth + 7) ? 1u : 0u;
+    const uint64_t avail = s->budget / 2 > s->resident_bytes ? s->budget / 2 - s->resident_bytes : 0;
+    for (; rows > 0; --rows) {                   // the deepest expansion that fits
+        uint64_t Fd = 0;
+        if ((rc = frontier_fill(n, depth + rows, nullptr, nullptr, nullptr, nullptr, 0, &Fd,
+                                nullptr)) != NQ_OK)
+            return rc;
+        if (Fd * 13 + (F + 1) * 8 <= avail) break;
     }
-    s->resident_bytes += bytes;
-    auto ins = s->resident.emplace(key, r);
+    Resident r;
+    r.rows = rows;
+    r.len = F;
+    if (F * 13 > avail && rows == 0) return NQ_ENOMEM;
+    rc = build_device_frontier_at(n, depth, rows, s->aux, &r.fr, rows ? &r.off : nullptr);
+    if (rc != NQ_OK) return rc;
+    r.bytes = r.fr.len * 13 + r.off.size() * 8;
+    if (r.bytes > avail) return NQ_ENOMEM;
+    s->resident_bytes += r.bytes;
+    auto ins = s->resident.emplace(key, std::move(r));
     *out = &ins.first->second;
     return NQ_OK;
 }
@@ -223,38 +237,35 @@ int admit_and_launch(nq_server* s) {
     Epoch ep;
     const uint64_t epoch_start = s->ring_tail;
     std::vector<uint64_t> taken;
-    struct SliceCopy { Resident* res; uint64_t src, pos, len; };
-    std::vector<SliceCopy> slices;
+    struct Copy { const Resident* res; uint64_t src, pos, len; uint32_t slot; };
+    std::vector<Copy> copies;
     while (!s->pending.empty() && !s->free_slots.empty()) {
         Req& r = s->reqs.at(s->pending.front());
-        uint64_t F = 0;
+        auto finish = [&](int status) {
+            r.status = status;
+            r.state = ReqState::Done;
+            r.t_admit = r.t_done = now_ns();
+            s->pending.pop_front();
+        };
         Resident* res = nullptr;
-        std::vector<uint32_t> c, l, rr;
-        std::vector<uint8_t> w;
-        if (r.rq.kind == NQ_REQ_COUNT) {
-            int rc = frontier_fill(r.rq.n, r.depth, nullptr, nullptr, nullptr, nullptr, 0, &F,
-                                   nullptr);
-            if (rc != NQ_OK) { r.status = rc; r.state = ReqState::Done; r.t_done = now_ns(); s->pending.pop_front(); continue; }
-        } else {
-            int rc = ensure_resident(s, r.rq.n, r.rq.depth, &res);
-            if (rc != NQ_OK || r.rq.start + r.rq.len > res->len) {
-                r.status = rc != NQ_OK ? rc : NQ_EINVAL;
-                r.state = ReqState::Done;
-                r.t_done = now_ns();
-                s->pending.pop_front();
+        int rc = ensure_resident(s, r.rq.n, r.depth, r.rq.kind, &res);
+        if (rc != NQ_OK) { finish(rc); continue; }
+        uint64_t lo = 0, hi = res->len;                   // entries of the (n, depth) frontier
+        if (r.rq.kind == NQ_REQ_SLICE) {
+            if (r.rq.start > res->len || r.rq.len > res->len - r.rq.start) {
+                finish(NQ_EINVAL);
                 continue;
             }
-            F = r.rq.len;
+            lo = r.rq.start;
+            hi = r.rq.start + r.rq.len;
         }
-        if (F > s->ring_cap) {                       // can never fit
-            r.status = NQ_ENOMEM; r.state = ReqState::Done; r.t_done = now_ns();
-            s->pending.pop_front();
-            continue;
-        }
+        const uint64_t src = res->first(lo);
+        const uint64_t F = res->first(hi) - src;          // subproblems in the ring
+        if (F > s->ring_cap) { finish(NQ_ENOMEM); continue; }     // can never fit
         if (s->ring_tail + F - s->ring_head > s->ring_cap) break;   // wait for space
-        if (F == 0) {                                  // nothing to search
-            r.count = 0; r.state = ReqState::Done; r.t_admit = r.t_done = now_ns();
-            s->pending.pop_front();
+        if (F == 0) {                                     // nothing to search
+            r.count = 0;
+            finish(NQ_OK);
             continue;
         }
         const uint32_t slot = s->free_slots.back();
@@ -266,17 +277,7 @@ int admit_and_launch(nq_server* s) {
         r.entries = F;
         s->ring_tail += F;
         ep.inits.push_back({slot, r.rq.n, (uint32_t)F, r.gen});
-        if (r.rq.kind == NQ_REQ_COUNT) {
-            const size_t o = ep.hc.size();
-            ep.hc.resize(o + F); ep.hl.resize(o + F); ep.hr.resize(o + F); ep.hw.resize(o + F);
-            uint64_t got = 0;
-            frontier_fill(r.rq.n, r.depth, ep.hc.data() + o, ep.hl.data() + o, ep.hr.data() + o,
-                          ep.hw.data() + o, F, &got, nullptr);
-            ep.hi.insert(ep.hi.end(), F, slot);
-        } else {
-            slices.push_back({res, r.rq.start, r.ring_start, F});
-            ep.hi.insert(ep.hi.end(), F, slot);
-        }
+        copies.push_back({res, src, r.ring_start, F, slot});
         r.state = ReqState::Admitted;
         r.t_admit = now_ns();
         taken.push_back(s->pending.front());
@@ -287,8 +288,8 @@ int admit_and_launch(nq_server* s) {
     const uint64_t n_entries = s->ring_tail - epoch_start;
     hipStream_t st = s->streams[s->epoch_no % kStreams];
     hipError_t e = hipSuccess;
-    // 1. slot records, 2. instance ids of every entry, 3. count frontiers,
-    // 4. slices (device to device).  Host-staged copies go in ring order.
+    // 1. slot records, 2. every request's entries (device to device out of its
+    // resident frontier) and instance ids, in ring order.
     const size_t init_off = (s->epoch_no % kStreams) * s->max_slots;
     nqi::SlotInit* d_init = s->d_init + init_off;
     if ((e = hipMemcpyAsync(d_init, ep.inits.data(), ep.inits.size() * sizeof(SlotInit),
@@ -299,46 +300,23 @@ int admit_and_launch(nq_server* s) {
     int rc = launch_slot_init(d_init, (uint32_t)ep.inits.size(), s->s_n, s->s_rem, s->s_tot,
                               s->s_gen, st);
     if (rc != NQ_OK) return rc;
-    ring_segments(s, epoch_start, n_entries, [&](uint64_t phys, uint64_t off, uint64_t len) {
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->r_inst + phys, ep.hi.data() + off, len * 4,
-                               hipMemcpyHostToDevice, st);
-    });
-    // count entries are staged in ring order, skipping the slices' ranges
-    uint64_t staged = 0;
-    uint64_t pos = epoch_start;
-    for (uint64_t tk : taken) {
-        const Req& r = s->reqs.at(tk);
-        if (r.rq.kind == NQ_REQ_COUNT) {
-            ring_segments(s, pos, r.ring_len, [&](uint64_t phys, uint64_t off, uint64_t len) {
-                if (e != hipSuccess) return;
-                const uint64_t so = staged + off;
-                if ((e = hipMemcpyAsync(s->r_cols + phys, ep.hc.data() + so, len * 4,
-                                        hipMemcpyHostToDevice, st)) != hipSuccess) return;
-                if ((e = hipMemcpyAsync(s->r_ld + phys, ep.hl.data() + so, len * 4,
-                                        hipMemcpyHostToDevice, st)) != hipSuccess) return;
-                if ((e = hipMemcpyAsync(s->r_rd + phys, ep.hr.data() + so, len * 4,
-                                        hipMemcpyHostToDevice, st)) != hipSuccess) return;
-                e = hipMemcpyAsync(s->r_w + phys, ep.hw.data() + so, len,
-                                   hipMemcpyHostToDevice, st);
-            });
-            staged += r.ring_len;
-        }
-        pos += r.ring_len;
-    }
-    for (const SliceCopy& sc : slices) {
-        ring_segments(s, sc.pos, sc.len, [&](uint64_t phys, uint64_t off, uint64_t len) {
-            if (e != hipSuccess) return;
-            const uint64_t src = sc.src + off;
-            if ((e = hipMemcpyAsync(s->r_cols + phys, sc.res->cols + src, len * 4,
+    for (const Copy& cp : copies) {
+        const DeviceFrontier& fr = cp.res->fr;
+        ring_segments(s, cp.pos, cp.len, [&](uint64_t phys, uint64_t off, uint64_t len) {
+            if (e != hipSuccess || rc != NQ_OK) return;
+            const uint64_t from = cp.src + off;
+            if ((e = hipMemcpyAsync(s->r_cols + phys, fr.cols + from, len * 4,
                                     hipMemcpyDeviceToDevice, st)) != hipSuccess) return;
-            if ((e = hipMemcpyAsync(s->r_ld + phys, sc.res->ld + src, len * 4,
+            if ((e = hipMemcpyAsync(s->r_ld + phys, fr.ld + from, len * 4,
                                     hipMemcpyDeviceToDevice, st)) != hipSuccess) return;
-            if ((e = hipMemcpyAsync(s->r_rd + phys, sc.res->rd + src, len * 4,
+            if ((e = hipMemcpyAsync(s->r_rd + phys, fr.rd + from, len * 4,
                                     hipMemcpyDeviceToDevice, st)) != hipSuccess) return;
-            e = hipMemcpyAsync(s->r_w + phys, sc.res->w + src, len, hipMemcpyDeviceToDevice, st);
+            if ((e = hipMemcpyAsync(s->r_w + phys, fr.w + from, len, hipMemcpyDeviceToDevice,
+                                    st)) != hipSuccess) return;
+            rc = launch_fill_u32(s->r_inst + phys, cp.slot, len, st);
         });
     }
+    if (rc != NQ_OK) return rc;
     if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
     // 5. the epoch: one persistent launch over [epoch_start, ring_tail).
     DfsParams P{};
@@ -397,15 +375,16 @@ void worker_main(nq_server* s) {
 void destroy_all(nq_server* s) {
     for (hipStream_t st : s->streams)
         if (st) (void)hipStreamSynchronize(st);
+    if (s->aux) (void)hipStreamSynchronize(s->aux);
     for (auto& ep : s->epochs)
         if (ep.done) (void)hipEventDestroy(ep.done);
-    for (auto& kv : s->resident)
-        if (kv.second.dev) (void)hipFree(kv.second.dev);
     if (s->dev) (void)hipFree(s->dev);
     if (s->h_val) (void)hipHostFree(s->h_val);
     if (s->h_flag) (void)hipHostFree(s->h_flag);
     for (hipStream_t st : s->streams)
         if (st) (void)hipStreamDestroy(st);
+    s->resident.clear();
+    if (s->aux) (void)hipStreamDestroy(s->aux);
     delete s;
 }
 
@@ -417,7 +396,7 @@ int serve_create(const nq_opts* opts, uint64_t hbm_budget, nq_server** out) {
     nq_server* s = new (std::nothrow) nq_server();
     if (!s) return NQ_ENOMEM;
     if (opts) s->launch = *opts;
-    s->budget = hbm_budget ? hbm_budget : (1ull << 30);
+    s->budget = hbm_budget ? hbm_budget : (8ull << 30);
     // Frames: requests whose subproblems need more are refused at submit.
     s->max_frames = (opts && opts->depth) ? opts->depth : 14u;
     // Half of the budget is the work ring, the other half resident frontiers.
@@ -478,6 +457,10 @@ int serve_create(const nq_opts* opts, uint64_t hbm_budget, nq_server** out) {
             set_hip_error(e);
             return fail(NQ_EDEVICE);
         }
+    if ((e = hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking)) != hipSuccess) {
+        set_hip_error(e);
+        return fail(NQ_EDEVICE);
+    }
     try {
         s->worker = std::thread(worker_main, s);
     } catch (...) {
