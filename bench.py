@@ -346,7 +346,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": f"N-Queens N={N} full count, pre-placement depth {k}"
-                               f"{' (autotuned over 5..8)' if tuned else ''}, {F} subproblems "
+                               f"{' (autotuned over 6..10)' if tuned else ''}, {F} subproblems "
                                "resident in HBM, one persistent launch",
                    "n": N, "depth": k, "subproblems": F, "solutions": EXPECT,
                    "nodes": nodes, "nodes_source": src},
