@@ -48,8 +48,11 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 
+// Default depth of one instance: 5, or n - 12 for large boards, so that no
+// instance needs more than 10 stack frames (11 KB of LDS per wave: 14 resident
+// waves per CU) and the largest instances are cut into millions of subtrees.
 uint32_t batch_default_depth(uint32_t n, uint32_t requested) {
-    uint32_t k = requested ? requested : 5u;
+    uint32_t k = requested ? requested : std::max<uint32_t>(5u, n > 12 ? n - 12 : 0u);
     const uint32_t cap = n > 2 ? n - 2 : 1u;
     return std::max<uint32_t>(1u, std::min(k, cap));
 }

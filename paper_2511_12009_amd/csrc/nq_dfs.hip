@@ -322,7 +322,8 @@ __device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, u
 // 3 = as 1 with the frame in 64-bit halves and the descend select done by two
 // exec-masked 64-bit moves, 4 = the frame keeps its untried set negated so
 // that the lane masks come from carries (halves and 64-bit moves as in 3),
-// 5 = as 4 with the frame as four dwords and v_cndmask selects.
+// 5 = as 4 with the frame as four dwords and v_cndmask selects, 6 = as 1 with
+// two steps per loop trip.
 template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP>
 __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     extern __shared__ uint4 lds_stack[];
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 31u) / 32u);
         for (;;) {
             uint32_t trips = 32u;
-            do {
+            auto step = [&]() {
                 // p = lowest untried column; the untried set keeps its register.
                 uint32_t p, rest = st.w;
                 isa_take_lowest(rest, p);
@@ -629,7 +630,11 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 } else {
                     isa_pop(st, top, floor, popm);
                 }
-                trips = __builtin_amdgcn_readfirstlane(trips - 1u);
+            };
+            do {
+                step();
+                if (LOOP == 6) step();            // two steps per loop trip
+                trips = __builtin_amdgcn_readfirstlane(trips - (LOOP == 6 ? 2u : 1u));
             } while (trips != 0u);
             chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
             if (chunks == 0u) break;
@@ -689,12 +694,12 @@ static const void* select_kernel_loop(uint32_t mode, bool stats, bool leafctr) {
     return leafctr ? kernel_ptr<false, false, true, LOOP>() : kernel_ptr<false, false, false, LOOP>();
 }
 
-// Inner-loop form: NQ_DFS_LOOP=0..5 in the environment overrides the default
+// Inner-loop form: NQ_DFS_LOOP=0..6 in the environment overrides the default
 // (for measurements).
 static int loop_form() {
     static const int form = [] {
         const char* e = std::getenv("NQ_DFS_LOOP");
-        if (e && e[0] >= '0' && e[0] <= '5' && e[1] == 0) return e[0] - '0';
+        if (e && e[0] >= '0' && e[0] <= '6' && e[1] == 0) return e[0] - '0';
         return kDefaultLoop;
     }();
     return form;
@@ -736,6 +741,7 @@ static const void* select_kernel(uint32_t mode, bool stats, bool leafctr) {
         case 3: return select_kernel_loop<3>(mode, stats, leafctr);
         case 4: return select_kernel_loop<4>(mode, stats, leafctr);
         case 5: return select_kernel_loop<5>(mode, stats, leafctr);
+        case 6: return select_kernel_loop<6>(mode, stats, leafctr);
         default: return select_kernel_loop<0>(mode, stats, leafctr);
     }
 }
