@@ -12,21 +12,24 @@
 //
 // LDS layout (the bank-conflict-free stack of Section 3.1, re-derived for a
 // 64-lane wave and 16-byte frames): wave w of a workgroup owns
-// frames * 64 * 16 bytes; frame f of lane l is the uint4 at index
-// (w * frames + f) * 64 + l.  A wave-wide ds_write_b128 / ds_read_b128 touches
-// one 16-byte slot per lane, and the slot's bank offset depends on l only
-// (f * 64 * 16 bytes is a multiple of every bank-row size), so lanes at
-// different depths never collide.
+// (frames + 1) * 64 * 16 bytes; slot f of lane l is the 16-byte frame at index
+// (w * (frames + 1) + f) * 64 + l, slot 0 holding the lane's sentinel.  A
+// wave-wide ds_write_b128 / ds_read_b128 touches one 16-byte slot per lane,
+// and the slot's bank offset depends on l only (64 * 16 bytes is a multiple of
+// every bank-row size), so lanes at different depths never collide.
 //
 // Scheduling.  Plain mode: lane i of the grid takes entry i and idles once its
-// subtree is done.  Persistent mode: a resident grid; every `refill_every` DFS
-// steps each wave ballots its idle lanes, claims that many entries with one
-// atomic add on a global head, and hands them out by rank (mbcnt), so the
-// idle lanes read consecutive entries with coalesced loads.  By default the
-// entries are claimed from the end of the frontier down: subtrees below the
-// later row-0 columns are the larger ones (the per-GPU times of Section 4.5
-// grow with the position in the frontier), and starting them first shortens
-// the tail of the launch.
+// subtree is done.  Persistent mode: a resident grid; a wave visits the
+// scheduler every `refill_every` DFS steps, or earlier once `idle_min` of its
+// lanes are idle.  A visit retires finished lanes, then hands its idle lanes
+// entries by rank (mbcnt): first from the wave's own block of claimed entries,
+// then from a fresh block of at least `claim` entries taken with one atomic add
+// on a global head.  The idle lanes therefore read consecutive entries with
+// coalesced loads, and the head sees one atomic per block rather than one per
+// visit.  By default entries are claimed from the end of the frontier down:
+// subtrees below the later row-0 columns are the larger ones (the per-GPU times
+// of Section 4.5 grow with the position in the frontier), and starting them
+// first shortens the tail of the launch.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -104,7 +107,7 @@ __device__ __forceinline__ lds_frame* frame_at(int32_t addr) {
     return (lds_frame*)(uintptr_t)(uint32_t)addr;
 }
 
-// Exec-masked helpers for the hand-scheduled loop (LOOP >= 1).  Each block
+// Exec-masked helpers for the hand-scheduled loops (forms 1 and 2).  Each block
 // switches exec to the given lane mask, does its LDS access and stack-pointer
 // update, and restores exec before the block ends.  The SALU instructions in a
 // block overwrite SCC, so every such block lists it as clobbered (otherwise
@@ -140,32 +143,6 @@ __device__ __forceinline__ void isa_pop(u32x4& st, int32_t& top, int32_t floor, 
         : "memory", "scc");
 }
 
-// Prefetch the frame a pop would restore: nxt <- [top] for every lane.
-__device__ __forceinline__ void isa_prefetch(u32x4& nxt, int32_t top) {
-    asm volatile("ds_read_b128 %[nx], %[top]" : [nx] "=v"(nxt) : [top] "v"(top) : "memory");
-}
-
-// Pop from the prefetched frame: wait for it, then st <- nxt and
-// top = max(top - 1024, floor) for the lanes in `m`.
-__device__ __forceinline__ void isa_pop_prefetched(u32x4& st, u32x4& nxt, int32_t& top,
-                                                   int32_t floor, uint64_t m) {
-    int32_t t;
-    asm volatile(
-        "s_waitcnt lgkmcnt(0)\n\t"
-        "v_cndmask_b32 %[s0], %[s0], %[n0], %[m]\n\t"
-        "v_cndmask_b32 %[s1], %[s1], %[n1], %[m]\n\t"
-        "v_cndmask_b32 %[s2], %[s2], %[n2], %[m]\n\t"
-        "v_cndmask_b32 %[s3], %[s3], %[n3], %[m]\n\t"
-        "v_add_u32 %[t], 0xfffffc00, %[top]\n\t"
-        "v_max_i32 %[t], %[t], %[fl]\n\t"
-        "v_cndmask_b32 %[top], %[top], %[t], %[m]"
-        : [s0] "+v"(st.x), [s1] "+v"(st.y), [s2] "+v"(st.z), [s3] "+v"(st.w), [top] "+v"(top),
-          [t] "=&v"(t)
-        : [n0] "v"(nxt.x), [n1] "v"(nxt.y), [n2] "v"(nxt.z), [n3] "v"(nxt.w), [m] "s"(m),
-          [fl] "v"(floor)
-        : "memory");
-}
-
 // p = lowest set bit of v; v loses it (in place, so the loop-carried register
 // of v is also the one the pop writes).
 __device__ __forceinline__ void isa_take_lowest(uint32_t& v, uint32_t& p) {
@@ -180,58 +157,6 @@ __device__ __forceinline__ void isa_take_lowest(uint32_t& v, uint32_t& p) {
 __device__ __forceinline__ uint32_t isa_sel(uint64_t m, uint32_t a, uint32_t d) {
     asm("v_cndmask_b32 %0, %0, %1, %2" : "+v"(d) : "v"(a), "s"(m));
     return d;
-}
-
-// The frame as two 64-bit halves, (cols | ld << 32, rd | avail << 32): the
-// same 16 bytes as u32x4, so that the descend select moves it with two
-// v_mov_b64 under an exec mask instead of four v_cndmask.
-typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(3))) u64x2 lds_frame64;
-
-__device__ __forceinline__ lds_frame64* frame64_at(int32_t addr) {
-    return (lds_frame64*)(uintptr_t)(uint32_t)addr;
-}
-
-__device__ __forceinline__ void isa_push64(u64x2 st, int32_t& top, uint64_t m) {
-    uint64_t sv;
-    asm volatile(
-        "s_and_saveexec_b64 %[sv], %[m]\n\t"
-        "ds_write_b64 %[top], %[s0] offset:1024\n\t"
-        "ds_write_b64 %[top], %[s1] offset:1032\n\t"
-        "v_add_u32 %[top], 0x400, %[top]\n\t"
-        "s_mov_b64 exec, %[sv]"
-        : [top] "+v"(top), [sv] "=&s"(sv)
-        : [m] "s"(m), [s0] "v"(st.x), [s1] "v"(st.y)
-        : "memory", "scc");
-}
-
-__device__ __forceinline__ void isa_pop64(u64x2& st, int32_t& top, int32_t floor, uint64_t m) {
-    uint64_t sv;
-    int32_t t;
-    asm volatile(
-        "s_and_saveexec_b64 %[sv], %[m]\n\t"
-        "ds_read_b64 %[s0], %[top]\n\t"
-        "ds_read_b64 %[s1], %[top] offset:8\n\t"
-        "v_add_u32 %[t], 0xfffffc00, %[top]\n\t"
-        "v_max_i32 %[top], %[t], %[fl]\n\t"
-        "s_mov_b64 exec, %[sv]\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : [s0] "+v"(st.x), [s1] "+v"(st.y), [top] "+v"(top), [sv] "=&s"(sv), [t] "=&v"(t)
-        : [m] "s"(m), [fl] "v"(floor)
-        : "memory", "scc");
-}
-
-// st = ch for the lanes in `m`.
-__device__ __forceinline__ void isa_move64(uint64_t m, u64x2 ch, u64x2& st) {
-    uint64_t sv;
-    asm volatile(
-        "s_and_saveexec_b64 %[sv], %[m]\n\t"
-        "v_mov_b64 %[s0], %[c0]\n\t"
-        "v_mov_b64 %[s1], %[c1]\n\t"
-        "s_mov_b64 exec, %[sv]"
-        : [s0] "+v"(st.x), [s1] "+v"(st.y), [sv] "=&s"(sv)
-        : [c0] "v"(ch.x), [c1] "v"(ch.y), [m] "s"(m)
-        : "scc");
 }
 
 // sum += 1 for the lanes in `m` (carry-in add).
@@ -260,36 +185,11 @@ __device__ __forceinline__ uint32_t isa_neg_any(uint32_t a, uint64_t& am) {
     return n;
 }
 
-// One step's stack and frame update for the negated-avail loops (LOOP 4, 5),
-// in a single exec-masked block.  The three lane masks are disjoint subsets of
-// exec: lanes in `pm` store the frame at [top + 1024] and advance top, lanes
-// in `dm` take the child frame `ch`, lanes in `qm` reload the frame at [top]
-// and step top back.  No clamp: a lane that has popped its sentinel is parked
-// and its masks stay empty until it takes a new entry.
-__device__ __forceinline__ void isa_step64(u64x2& st, u64x2 ch, int32_t& top, uint64_t pm,
-                                           uint64_t dm, uint64_t qm) {
-    uint64_t sv;
-    asm volatile(
-        "s_and_saveexec_b64 %[sv], %[pm]\n\t"
-        "ds_write_b64 %[top], %[s0] offset:1024\n\t"
-        "ds_write_b64 %[top], %[s1] offset:1032\n\t"
-        "v_add_u32 %[top], 0x400, %[top]\n\t"
-        "s_and_b64 exec, %[sv], %[dm]\n\t"
-        "v_mov_b64 %[s0], %[c0]\n\t"
-        "v_mov_b64 %[s1], %[c1]\n\t"
-        "s_and_b64 exec, %[sv], %[qm]\n\t"
-        "ds_read_b64 %[s0], %[top]\n\t"
-        "ds_read_b64 %[s1], %[top] offset:8\n\t"
-        "v_add_u32 %[top], 0xfffffc00, %[top]\n\t"
-        "s_mov_b64 exec, %[sv]\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : [s0] "+v"(st.x), [s1] "+v"(st.y), [top] "+v"(top), [sv] "=&s"(sv)
-        : [c0] "v"(ch.x), [c1] "v"(ch.y), [pm] "s"(pm), [dm] "s"(dm), [qm] "s"(qm)
-        : "memory", "scc");
-}
-
-// As isa_step64 with the frame as four dwords: one ds_write_b128 /
-// ds_read_b128 each way and four v_cndmask for the child.
+// One step's stack and frame update for form 2: lanes in `pm` store the frame
+// at [top + 1024] and advance top, lanes in `dm` take the child frame `ch`
+// (four v_cndmask), lanes in `qm` reload the frame at [top] and step top back.
+// The three masks are disjoint.  No clamp: a lane that has popped its sentinel
+// is parked and its masks stay empty until it takes a new entry.
 __device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, uint64_t pm,
                                             uint64_t dm, uint64_t qm) {
     uint64_t sv;
@@ -317,13 +217,8 @@ __device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, u
 }
 
 // LOOP selects the inner-loop form: 0 = plain C++ (the compiler places the
-// exec masks), 1 = hand-placed exec masks with a direct pop, 2 = as 1 but the
-// frame a pop needs is read one step ahead, so the pop does not wait on LDS,
-// 3 = as 1 with the frame in 64-bit halves and the descend select done by two
-// exec-masked 64-bit moves, 4 = the frame keeps its untried set negated so
-// that the lane masks come from carries (halves and 64-bit moves as in 3),
-// 5 = as 4 with the frame as four dwords and v_cndmask selects, 6 = as 1 with
-// two steps per loop trip.
+// exec masks), 1 = hand-placed exec masks (the default), 2 = as 1 with the
+// untried set kept negated so that two lane masks come from carries.
 template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP>
 __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     extern __shared__ uint4 lds_stack[];
@@ -455,6 +350,11 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         // The frame is kept as one 4-vector so that push and pop move it with
         // a single ds_write_b128 / ds_read_b128 and no register shuffling.
         u32x4 st = {c, l, r, v};
+        // Steps run in chunks of 32 (forms 1 and 2); between chunks a
+        // persistent wave returns to the scheduler early once `idle_min` of
+        // its lanes have finished (avail == 0 after a step), so a finished
+        // lane waits for at most one chunk instead of `refill_every` steps.
+        // The trip counts are wave-uniform; readfirstlane keeps them in SGPRs.
         if (LOOP == 0) {
         for (uint32_t it = 0; it < P.refill_every; ++it) {
             const uint32_t p = st.w & (0u - st.w);    // lowest untried column
@@ -482,125 +382,13 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 top = max(top - 1024, floor);
             }
         }
-        } else if (LOOP == 3) {
-        // As LOOP 1, with the frame in two 64-bit halves and the descend
-        // select done by two exec-masked v_mov_b64.
-        u64x2 st2;
-        st2.x = ((uint64_t)l << 32) | c;
-        st2.y = ((uint64_t)v << 32) | r;
+        } else if (LOOP == 1) {
+        // The lane masks live in SGPR pairs; the push, the selects, the pop
+        // and the leaf count use them directly.
         uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 31u) / 32u);
         for (;;) {
             uint32_t trips = 32u;
             do {
-                const uint32_t c0 = (uint32_t)st2.x, l0 = (uint32_t)(st2.x >> 32);
-                const uint32_t r0 = (uint32_t)st2.y;
-                uint32_t p, rest = (uint32_t)(st2.y >> 32);
-                isa_take_lowest(rest, p);
-                const uint32_t nc = LEAFCTR ? c0 + p + step_k : (c0 | p);
-                const uint32_t nl = (l0 + p) << 1;
-                const uint32_t nr = (r0 + p) >> 1;
-                const uint32_t a = last & ~(nc | nl | nr);
-                if (STATS) steps32 += (p != 0u);
-                const uint64_t leafm = __builtin_amdgcn_ballot_w64(
-                    LEAFCTR ? (int32_t)nc < 0 : __popc(nc) == nm1);
-                const uint64_t anym = __builtin_amdgcn_ballot_w64(a != 0u);
-                const uint64_t restm = __builtin_amdgcn_ballot_w64(rest != 0u);
-                const uint64_t descm = anym & ~leafm;
-                isa_count(sum32, anym & leafm);
-                st2.y = ((uint64_t)rest << 32) | r0;
-                isa_push64(st2, top, descm & restm);
-                u64x2 ch;
-                ch.x = ((uint64_t)nl << 32) | nc;
-                ch.y = ((uint64_t)a << 32) | nr;
-                isa_move64(descm, ch, st2);
-                isa_pop64(st2, top, floor, ~(descm | restm));
-                trips = __builtin_amdgcn_readfirstlane(trips - 1u);
-            } while (trips != 0u);
-            chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
-            if (chunks == 0u) break;
-            if (PERSISTENT && P.idle_min && !exhausted &&
-                (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((uint32_t)(st2.y >> 32) == 0u)) >=
-                    P.idle_min)
-                break;
-        }
-        st = u32x4{(uint32_t)st2.x, (uint32_t)(st2.x >> 32), (uint32_t)st2.y,
-                   (uint32_t)(st2.y >> 32)};
-        } else if (LOOP == 4 || LOOP == 5) {
-        // The frame keeps the untried set negated, w = -avail (mod 2^32), so
-        // that the step's lane masks come out of carries instead of compares:
-        //   p = w & -w is the lowest untried column, and w + p = -(avail - p)
-        //   carries out exactly when that column was the last one;
-        //   the child's w = 0 - a borrows exactly when a != 0.
-        // A parked lane has w = 0: p = 0, no carry, no free square, so it
-        // neither pushes, descends nor pops (its stack pointer needs no clamp).
-        uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 31u) / 32u);
-        u64x2 st2;
-        u32x4 st4;
-        if (LOOP == 4) {
-            st2.x = ((uint64_t)l << 32) | c;
-            st2.y = ((uint64_t)(0u - v) << 32) | r;
-        } else {
-            st4 = u32x4{c, l, r, 0u - v};
-        }
-        for (;;) {
-            uint32_t trips = 32u;
-            do {
-                const uint32_t c0 = LOOP == 4 ? (uint32_t)st2.x : st4.x;
-                const uint32_t l0 = LOOP == 4 ? (uint32_t)(st2.x >> 32) : st4.y;
-                const uint32_t r0 = LOOP == 4 ? (uint32_t)st2.y : st4.z;
-                const uint32_t w0 = LOOP == 4 ? (uint32_t)(st2.y >> 32) : st4.w;
-                uint32_t w1 = w0, p;
-                uint64_t zm;
-                isa_take_neg(w1, p, zm);
-                const uint32_t nc = LEAFCTR ? c0 + p + step_k : (c0 | p);
-                const uint32_t nl = (l0 + p) << 1;
-                const uint32_t nr = (r0 + p) >> 1;
-                uint64_t anym;
-                const uint32_t na = isa_neg_any(last & ~(nc | nl | nr), anym);
-                if (STATS) steps32 += (p != 0u);
-                const uint64_t leafm = __builtin_amdgcn_ballot_w64(
-                    LEAFCTR ? (int32_t)nc < 0 : __popc(nc) == nm1);
-                const uint64_t descm = anym & ~leafm;
-                isa_count(sum32, anym & leafm);
-                if (LOOP == 4) {
-                    st2.y = ((uint64_t)w1 << 32) | r0;
-                    u64x2 ch;
-                    ch.x = ((uint64_t)nl << 32) | nc;
-                    ch.y = ((uint64_t)na << 32) | nr;
-                    isa_step64(st2, ch, top, descm & ~zm, descm, zm & ~descm);
-                } else {
-                    st4.w = w1;
-                    isa_step128(st4, u32x4{nc, nl, nr, na}, top, descm & ~zm, descm,
-                                zm & ~descm);
-                }
-                trips = __builtin_amdgcn_readfirstlane(trips - 1u);
-            } while (trips != 0u);
-            chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
-            if (chunks == 0u) break;
-            const uint32_t wn = LOOP == 4 ? (uint32_t)(st2.y >> 32) : st4.w;
-            if (PERSISTENT && P.idle_min && !exhausted &&
-                (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(wn == 0u)) >= P.idle_min)
-                break;
-        }
-        if (LOOP == 4)
-            st = u32x4{(uint32_t)st2.x, (uint32_t)(st2.x >> 32), (uint32_t)st2.y,
-                       0u - (uint32_t)(st2.y >> 32)};
-        else
-            st = u32x4{st4.x, st4.y, st4.z, 0u - st4.w};
-        } else {
-        // Same step with the lane masks kept in SGPR pairs: the push, the
-        // selects, the pop and the leaf count use them directly.
-        u32x4 nxt;
-        if (LOOP == 2) isa_prefetch(nxt, top);
-        // The trip count is wave-uniform; readfirstlane keeps it in an SGPR.
-        // Steps run in chunks of 32; between chunks a persistent wave returns
-        // to the scheduler early once `idle_min` of its lanes have finished
-        // (a finished lane has avail == 0 after its step), so finished lanes
-        // wait for at most one chunk instead of `refill_every` steps.
-        uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 31u) / 32u);
-        for (;;) {
-            uint32_t trips = 32u;
-            auto step = [&]() {
                 // p = lowest untried column; the untried set keeps its register.
                 uint32_t p, rest = st.w;
                 isa_take_lowest(rest, p);
@@ -623,18 +411,8 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 st.w = isa_sel(descm, a, st.w);
                 // After the select, avail == 0 exactly when the lane did not
                 // descend (a descent has a != 0) and had no untried column left.
-                const uint64_t popm = ~(descm | restm);
-                if (LOOP == 2) {
-                    isa_pop_prefetched(st, nxt, top, floor, popm);
-                    isa_prefetch(nxt, top);
-                } else {
-                    isa_pop(st, top, floor, popm);
-                }
-            };
-            do {
-                step();
-                if (LOOP == 6) step();            // two steps per loop trip
-                trips = __builtin_amdgcn_readfirstlane(trips - (LOOP == 6 ? 2u : 1u));
+                isa_pop(st, top, floor, ~(descm | restm));
+                trips = __builtin_amdgcn_readfirstlane(trips - 1u);
             } while (trips != 0u);
             chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
             if (chunks == 0u) break;
@@ -642,7 +420,44 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(st.w == 0u)) >= P.idle_min)
                 break;
         }
-        if (LOOP == 2) asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(nxt)::"memory");
+        } else {
+        // Form 2.  The frame keeps the untried set negated, w = -avail (mod
+        // 2^32), so that two lane masks come out of carries instead of
+        // compares: p = w & -w is the lowest untried column, and w + p =
+        // -(avail - p) carries out exactly when that column was the last one;
+        // the child's w = 0 - a borrows exactly when a != 0.  A parked lane has
+        // w = 0: p = 0, no carry, no free square, so it neither pushes,
+        // descends nor pops, and its stack pointer needs no clamp.
+        uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 31u) / 32u);
+        st.w = 0u - st.w;
+        for (;;) {
+            uint32_t trips = 32u;
+            do {
+                uint32_t w = st.w, p;
+                uint64_t zm;
+                isa_take_neg(w, p, zm);
+                const uint32_t nc = LEAFCTR ? st.x + p + step_k : (st.x | p);
+                const uint32_t nl = (st.y + p) << 1;
+                const uint32_t nr = (st.z + p) >> 1;
+                uint64_t anym;
+                const uint32_t na = isa_neg_any(last & ~(nc | nl | nr), anym);
+                if (STATS) steps32 += (p != 0u);
+                const uint64_t leafm = __builtin_amdgcn_ballot_w64(
+                    LEAFCTR ? (int32_t)nc < 0 : __popc(nc) == nm1);
+                const uint64_t descm = anym & ~leafm;
+                isa_count(sum32, anym & leafm);
+                st.w = w;
+                isa_step128(st, u32x4{nc, nl, nr, na}, top, descm & ~zm, descm,
+                            zm & ~descm);
+                trips = __builtin_amdgcn_readfirstlane(trips - 1u);
+            } while (trips != 0u);
+            chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
+            if (chunks == 0u) break;
+            if (PERSISTENT && P.idle_min && !exhausted &&
+                (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(st.w == 0u)) >= P.idle_min)
+                break;
+        }
+        st.w = 0u - st.w;
         }
         c = st.x; l = st.y; r = st.z; v = st.w;
     }
@@ -694,12 +509,12 @@ static const void* select_kernel_loop(uint32_t mode, bool stats, bool leafctr) {
     return leafctr ? kernel_ptr<false, false, true, LOOP>() : kernel_ptr<false, false, false, LOOP>();
 }
 
-// Inner-loop form: NQ_DFS_LOOP=0..6 in the environment overrides the default
+// Inner-loop form: NQ_DFS_LOOP=0..2 in the environment overrides the default
 // (for measurements).
 static int loop_form() {
     static const int form = [] {
         const char* e = std::getenv("NQ_DFS_LOOP");
-        if (e && e[0] >= '0' && e[0] <= '6' && e[1] == 0) return e[0] - '0';
+        if (e && e[0] >= '0' && e[0] <= '2' && e[1] == 0) return e[0] - '0';
         return kDefaultLoop;
     }();
     return form;
@@ -738,10 +553,6 @@ static const void* select_kernel(uint32_t mode, bool stats, bool leafctr) {
     switch (loop_form()) {
         case 1: return select_kernel_loop<1>(mode, stats, leafctr);
         case 2: return select_kernel_loop<2>(mode, stats, leafctr);
-        case 3: return select_kernel_loop<3>(mode, stats, leafctr);
-        case 4: return select_kernel_loop<4>(mode, stats, leafctr);
-        case 5: return select_kernel_loop<5>(mode, stats, leafctr);
-        case 6: return select_kernel_loop<6>(mode, stats, leafctr);
         default: return select_kernel_loop<0>(mode, stats, leafctr);
     }
 }
