@@ -224,9 +224,10 @@ def test_n20_bench_shape():
         np.testing.assert_array_equal(counts[idx], ref)
 
 
-@pytest.mark.parametrize("n,k", [(14, 3), (17, 5), (16, 4), (12, 2)])
+@pytest.mark.parametrize("n,k", [(14, 3), (17, 5), (16, 4), (12, 2), (20, 6)])
 def test_node_counts_per_subproblem(n, k):
-    """DFS steps of the node-counting kernel equal the oracle's nodes entry by entry."""
+    """DFS steps of the node-counting kernel equal the oracle's nodes entry by entry
+    (N=20: the node total behind the benchmark's nodes/s)."""
     nq = _nq()
     g = _golden_runs()[(n, k)]
     cols, ld, rd, w = nq.frontier(n, k)
