@@ -189,7 +189,7 @@ def profile_run(nq, torch, k, args):
     total = torch.zeros(1, dtype=torch.int64, device=dev)
     _, _, ms = nq.count_subproblems(N, *t, weight=tw, counts=counts, total=total, depth=k,
                                     timing=True, waves_per_cu=args.waves_per_cu,
-                                    refill_every=args.refill)
+                                    refill_every=args.refill, claim=args.claim)
     if int(total.item()) != EXPECT:
         raise SystemExit(f"bench.py: profile total {int(total.item())} != {EXPECT}")
     print(f"[bench] profile: copy 256 MiB, DFS N={N} k={k} F={c.numel()} kernel {ms:.1f} ms",
@@ -235,6 +235,7 @@ def main():
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
+    ap.add_argument("--claim", type=int, default=0, help="entries per work-head claim (0 = auto)")
     ap.add_argument("--forward", action="store_true", help="claim entries in frontier order")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -268,6 +269,8 @@ def main():
             args.waves_per_cu = tuned["waves_per_cu"]
         if not args.refill:
             args.refill = tuned["refill_every"]
+        if not args.claim:
+            args.claim = tuned["claim"]
     else:
         k = args.depth
     dev = torch.device("cuda:0")
@@ -278,7 +281,7 @@ def main():
     host_total = torch.zeros(1, dtype=torch.int64).pin_memory()
     stream = torch.cuda.current_stream()
     kw = dict(depth=k, wg_size=args.wg, waves_per_cu=args.waves_per_cu,
-              refill_every=args.refill, forward=args.forward)
+              refill_every=args.refill, forward=args.forward, claim=args.claim)
 
     runs = nq.frontier_runs(N, k)
 
@@ -364,6 +367,7 @@ def main():
                            "traffic": profiled_traffic(N, k),
                            "ops_per_node": OPS_PER_NODE, "kernel_ms": kern_ms}
     out["launch"] = {"waves_per_cu": args.waves_per_cu, "refill_every": args.refill,
+                     "claim": args.claim,
                      "wg_size": args.wg, "autotune": tuned}
     del t_cols, t_ld, t_rd, t_w, counts
     torch.cuda.empty_cache()

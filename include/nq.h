@@ -208,9 +208,10 @@ int nq_count_batch(uint32_t ninst, const uint32_t* ns, const uint32_t* depths,
  * nq_autotune -- measure the best pre-placement depth and launch shape for n.
  *
  * Times complete persistent counts of n on the current device: every depth in
- * [depth_lo, depth_hi] (0, 0 = a range around max(1, n - 14)) with the default
- * launch shape, then, at the best depth, a few resident-wave counts per CU and
- * scheduler-visit intervals, until budget_ms of device time is spent (0 = 60 s).
+ * [depth_lo, depth_hi] (0, 0 = max(1, n - 14) .. +4) with the default launch
+ * shape, then, at the best depth, a few resident-wave counts per CU,
+ * scheduler-visit intervals and claim block sizes, until budget_ms of device
+ * time is spent (0 = 60 s).
  * The paper tunes the same choices by hand (Section 4.1 Table 3, Section 4.2
  * Table 4).  Every trial must produce the same count (else NQ_EDEVICE).  The
  * winner is written to *out and remembered for this process and device:
@@ -223,6 +224,7 @@ typedef struct nq_tuned {
     uint32_t trials;         /* timed counts made                                */
     double ms;               /* best device time of one count                    */
     uint64_t count;          /* the count every trial agreed on                  */
+    uint32_t claim;          /* entries per work-head claim (0 = size default)   */
 } nq_tuned;
 int nq_autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
                 nq_tuned* out);

@@ -48,6 +48,7 @@ class NqTuned(ct.Structure):
         ("trials", ct.c_uint32),
         ("ms", ct.c_double),
         ("count", ct.c_uint64),
+        ("claim", ct.c_uint32),
     ]
 
 
@@ -343,11 +344,12 @@ class Batch:
 
 
 def autotune(n: int, depth_lo: int = 0, depth_hi: int = 0, budget_ms: float = 0.0) -> dict:
-    """Measured best depth / waves per CU / visit interval for n (nq_autotune)."""
+    """Measured best depth / waves per CU / visit interval / claim block for n
+    (nq_autotune)."""
     t = NqTuned()
     _check(lib().nq_autotune(n, depth_lo, depth_hi, budget_ms, ct.byref(t)), "nq_autotune")
     return {"depth": t.depth, "waves_per_cu": t.waves_per_cu, "refill_every": t.refill_every,
-            "trials": t.trials, "ms": t.ms, "count": t.count}
+            "claim": t.claim, "trials": t.trials, "ms": t.ms, "count": t.count}
 
 
 class Server:

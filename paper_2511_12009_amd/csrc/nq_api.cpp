@@ -316,6 +316,7 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
             local.depth = t.depth;
             if (!local.waves_per_cu) local.waves_per_cu = t.waves_per_cu;
             if (!local.refill_every) local.refill_every = t.refill_every;
+            if (!local.claim) local.claim = t.claim;
         }
     }
     const uint32_t depth = local.depth ? local.depth : auto_depth(n);

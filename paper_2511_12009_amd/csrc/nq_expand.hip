@@ -63,26 +63,56 @@ __global__ void nq_expand_count_kernel(const uint32_t* __restrict__ cols,
     out[i] = k;
 }
 
-__global__ void nq_expand_write_kernel(const uint32_t* __restrict__ cols,
-                                       const uint32_t* __restrict__ ld,
-                                       const uint32_t* __restrict__ rd,
-                                       const uint8_t* __restrict__ w, uint64_t len, uint32_t n,
-                                       uint32_t rows, const uint64_t* __restrict__ offsets,
-                                       uint32_t* __restrict__ ocols, uint32_t* __restrict__ old,
-                                       uint32_t* __restrict__ ord, uint8_t* __restrict__ ow) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= len) return;
-    const uint32_t last = (1u << n) - 1u;
-    uint64_t o = offsets[i];
-    const uint8_t wt = w ? w[i] : (uint8_t)1;
-    for_each_child(last, rows, cols[i] & last, ld[i] & last, rd[i] & last,
-                   [&](uint32_t c, uint32_t l, uint32_t r) {
-                       ocols[o] = c;
-                       old[o] = l;
-                       ord[o] = r;
-                       if (ow) ow[o] = wt;
-                       ++o;
-                   });
+// Write pass, one wave per 64 parents.  The wave's children form one
+// contiguous range of the output (the offsets are a prefix sum), which is
+// written in chunks of kChunk entries: every lane places the children of its
+// parent that fall into the current chunk into LDS, then the wave stores the
+// chunk with consecutive lanes on consecutive entries (coalesced), instead of
+// each lane storing its own run of children with scattered 4-byte stores.
+constexpr uint32_t kChunk = 1024;
+
+__global__ __launch_bounds__(64) void nq_expand_write_kernel(
+    const uint32_t* __restrict__ cols, const uint32_t* __restrict__ ld,
+    const uint32_t* __restrict__ rd, const uint8_t* __restrict__ w, uint64_t len, uint32_t n,
+    uint32_t rows, const uint64_t* __restrict__ offsets, uint32_t* __restrict__ ocols,
+    uint32_t* __restrict__ old, uint32_t* __restrict__ ord, uint8_t* __restrict__ ow) {
+    __shared__ uint32_t s_c[kChunk], s_l[kChunk], s_r[kChunk];
+    __shared__ uint8_t s_w[kChunk];
+    const uint64_t first = (uint64_t)blockIdx.x * 64u;
+    const uint64_t i = first + threadIdx.x;
+    const uint64_t last_parent = min(first + 64u, len);          // exclusive
+    const uint64_t r0 = offsets[first], r1 = offsets[last_parent];
+    const uint32_t mask = (1u << n) - 1u;
+    const bool mine = i < len;
+    const uint64_t o0 = mine ? offsets[i] : r1, o1 = mine ? offsets[i + 1] : r1;
+    const uint32_t c = mine ? cols[i] & mask : 0u, l = mine ? ld[i] & mask : 0u,
+                   r = mine ? rd[i] & mask : 0u;
+    const uint8_t wt = (mine && w) ? w[i] : (uint8_t)1;
+    for (uint64_t base = r0; base < r1; base += kChunk) {
+        const uint64_t end = min(base + (uint64_t)kChunk, r1);
+        if (o0 < end && o1 > base) {
+            uint64_t o = o0;
+            for_each_child(mask, rows, c, l, r, [&](uint32_t cc, uint32_t cl, uint32_t cr) {
+                if (o >= base && o < end) {
+                    const uint32_t t = (uint32_t)(o - base);
+                    s_c[t] = cc;
+                    s_l[t] = cl;
+                    s_r[t] = cr;
+                    s_w[t] = wt;
+                }
+                ++o;
+            });
+        }
+        __syncthreads();
+        const uint32_t m = (uint32_t)(end - base);
+        for (uint32_t t = threadIdx.x; t < m; t += 64u) {
+            ocols[base + t] = s_c[t];
+            old[base + t] = s_l[t];
+            ord[base + t] = s_r[t];
+            if (ow) ow[base + t] = s_w[t];
+        }
+        __syncthreads();
+    }
 }
 
 }  // namespace
@@ -134,8 +164,10 @@ int expand_device(uint32_t n, uint32_t rows, const uint32_t* cols, const uint32_
     *out_len = total;
     if (!ocols || !old || !ord) return NQ_OK;                 // size query
     if (total > cap) return NQ_ERANGE;
-    hipLaunchKernelGGL(nq_expand_write_kernel, dim3(grid), dim3(block), 0, s, cols, ld, rd, w,
-                       len, n, rows, offsets, ocols, old, ord, ow);
+    const uint64_t wgrid = (len + 63) / 64;
+    if (wgrid > 0x7fffffffull) return NQ_EINVAL;
+    hipLaunchKernelGGL(nq_expand_write_kernel, dim3((uint32_t)wgrid), dim3(64), 0, s, cols, ld,
+                       rd, w, len, n, rows, offsets, ocols, old, ord, ow);
     if ((e = hipGetLastError()) != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
     return NQ_OK;
 }

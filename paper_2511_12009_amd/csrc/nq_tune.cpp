@@ -5,7 +5,8 @@
 // The paper tunes the pre-placed rows and the block/stack configuration by
 // hand (Section 4.1, Table 3; Section 4.2, Table 4); here the same choices are
 // measured.  The search is coordinate-wise: depth first (with the default
-// launch shape), then waves per CU, then the visit interval, each trial a
+// launch shape), then waves per CU, the visit interval and the size of the
+// per-wave claimed blocks, each trial a
 // complete persistent count over the resident frontier, stopping early when the
 // time budget is spent.  Results are kept per (device, n) for the process.
 #include <hip/hip_runtime.h>
@@ -56,7 +57,7 @@ struct TrialFrontier {
 
 // One timed persistent count; *ms is the device time of zero + DFS.
 int trial(uint32_t n, uint32_t depth, const TrialFrontier& tf, uint32_t waves_per_cu,
-          uint32_t refill, hipStream_t s, double* ms, uint64_t* total_out) {
+          uint32_t refill, uint32_t claim, hipStream_t s, double* ms, uint64_t* total_out) {
     const DeviceFrontier& fr = tf.fr;
     DeviceInfo dev;
     int rc = device_info(&dev);
@@ -71,7 +72,7 @@ int trial(uint32_t n, uint32_t depth, const TrialFrontier& tf, uint32_t waves_pe
     P.totals = tf.total; P.head = tf.total + 1;
     P.len = fr.len; P.n = n; P.frames = frames; P.refill_every = refill; P.reverse = 1;
     P.idle_min = default_idle_min();
-    P.claim = default_claim(fr.len, cfg);
+    P.claim = claim ? claim : default_claim(fr.len, cfg);
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e;
     if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
@@ -133,10 +134,10 @@ int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
     bool have_expect = false;
     int trials = 0;
     auto consider = [&](uint32_t depth, const TrialFrontier& fr, uint32_t wpc, uint32_t rf,
-                        bool* better) -> int {
+                        uint32_t claim, bool* better) -> int {
         double ms = 0;
         uint64_t total = 0;
-        int rc = trial(n, depth, fr, wpc, rf, s, &ms, &total);
+        int rc = trial(n, depth, fr, wpc, rf, claim, s, &ms, &total);
         if (rc != NQ_OK) return rc;
         ++trials;
         spent += ms;
@@ -145,7 +146,8 @@ int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
         have_expect = true;
         *better = ms < best.ms;
         if (*better) {
-            best.depth = depth; best.waves_per_cu = wpc; best.refill_every = rf; best.ms = ms;
+            best.depth = depth; best.waves_per_cu = wpc; best.refill_every = rf;
+            best.claim = claim; best.ms = ms;
         }
         return NQ_OK;
     };
@@ -159,9 +161,10 @@ int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
             if (rc != NQ_OK) return rc;
             bool b = false;
             for (int rep = 0; rep < 2 && spent < budget_ms; ++rep)
-                if ((rc = consider(d, fr, 0, 512, &b)) != NQ_OK) return rc;
+                if ((rc = consider(d, fr, 0, 512, 0, &b)) != NQ_OK) return rc;
         }
-        // 2. waves per CU and the visit interval at the best depth.
+        // 2. waves per CU, the visit interval and the claim block at the best
+        //    depth (claim 0 = the size-derived default).
         TrialFrontier fr;
         int rc = fr.load(n, best.depth, s);
         if (rc != NQ_OK) return rc;
@@ -169,12 +172,18 @@ int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
         for (uint32_t wpc : {8u, 16u, 24u}) {
             if (spent >= budget_ms) break;
             bool b = false;
-            if ((rc = consider(d, fr, wpc, best.refill_every, &b)) != NQ_OK) return rc;
+            if ((rc = consider(d, fr, wpc, best.refill_every, best.claim, &b)) != NQ_OK) return rc;
         }
         for (uint32_t rf : {128u, 2048u}) {
             if (spent >= budget_ms) break;
             bool b = false;
-            if ((rc = consider(d, fr, best.waves_per_cu, rf, &b)) != NQ_OK) return rc;
+            if ((rc = consider(d, fr, best.waves_per_cu, rf, best.claim, &b)) != NQ_OK) return rc;
+        }
+        for (uint32_t cl : {32u, 1024u}) {
+            if (spent >= budget_ms) break;
+            bool b = false;
+            if ((rc = consider(d, fr, best.waves_per_cu, best.refill_every, cl, &b)) != NQ_OK)
+                return rc;
         }
     } catch (const std::bad_alloc&) {
         return NQ_ENOMEM;
