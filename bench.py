@@ -1,10 +1,10 @@
 """Benchmark: DFS nodes/s of the N=20 count on one MI355X, batched vs plain.
 
 One step = the whole device path over the resident N=20 frontier (pre-placement
-depth k, built once on the host and copied to HBM before the timed region):
-zero the total, one persistent DFS launch over every subproblem (per-entry
-counts + weighted total), and the copy of the 8-byte total back to the host,
-which is checked against Q(20) = 39,029,188,884 every step.
+depth k, built before the timed region): zero the total, one persistent DFS
+launch over every subproblem (weighted total; per-subproblem counts are not
+requested), and the copy of the 8-byte total back to the host, which is checked
+against Q(20) = 39,029,188,884 every step.
 
 value = DFS nodes per second = nodes(20, k) / step time, where nodes(20, k) is
 the oracle's node count (queens placed in rows k..18 below every pre-placed
@@ -185,9 +185,8 @@ def profile_run(nq, torch, k, args):
     del src, dst
     c, l, r, tw = device_frontier(nq, torch, dev, k)
     t = [c, l, r]
-    counts = torch.empty(c.numel(), dtype=torch.int64, device=dev)
     total = torch.zeros(1, dtype=torch.int64, device=dev)
-    _, _, ms = nq.count_subproblems(N, *t, weight=tw, counts=counts, total=total, depth=k,
+    _, _, ms = nq.count_subproblems(N, *t, weight=tw, counts=False, total=total, depth=k,
                                     timing=True, waves_per_cu=args.waves_per_cu,
                                     refill_every=args.refill, claim=args.claim)
     if int(total.item()) != EXPECT:
@@ -276,7 +275,6 @@ def main():
     dev = torch.device("cuda:0")
     t_cols, t_ld, t_rd, t_w = device_frontier(nq, torch, dev, k)
     F = t_cols.numel()
-    counts = torch.empty(F, dtype=torch.int64, device=dev)
     total = torch.zeros(1, dtype=torch.int64, device=dev)
     host_total = torch.zeros(1, dtype=torch.int64).pin_memory()
     stream = torch.cuda.current_stream()
@@ -291,10 +289,10 @@ def main():
             # one launch per row-0 column, each over its run of the frontier
             for lo, hi in zip(runs[:-1], runs[1:]):
                 nq.count_subproblems(N, t_cols[lo:hi], t_ld[lo:hi], t_rd[lo:hi],
-                                     weight=t_w[lo:hi], counts=counts[lo:hi], total=total,
+                                     weight=t_w[lo:hi], counts=False, total=total,
                                      mode=mode, stream=stream, **kw)
         else:
-            nq.count_subproblems(N, t_cols, t_ld, t_rd, weight=t_w, counts=counts, total=total,
+            nq.count_subproblems(N, t_cols, t_ld, t_rd, weight=t_w, counts=False, total=total,
                                  mode=mode, stream=stream, **kw)
         host_total.copy_(total, non_blocking=True)
 
@@ -369,7 +367,7 @@ def main():
     out["launch"] = {"waves_per_cu": args.waves_per_cu, "refill_every": args.refill,
                      "claim": args.claim,
                      "wg_size": args.wg, "autotune": tuned}
-    del t_cols, t_ld, t_rd, t_w, counts
+    del t_cols, t_ld, t_rd, t_w
     torch.cuda.empty_cache()
     known = known_counts()
     if not args.no_batch:

@@ -250,7 +250,7 @@ def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None
     """Counts every subtree of device-resident triples (torch int32 CUDA tensors).
 
     ``counts`` (int64[F]) and ``total`` (int64[1], accumulated) are torch tensors
-    allocated here when not given.  ``depth`` promises that every triple has at
+    allocated here when not given; ``counts=False`` requests no per-entry counts.  ``depth`` promises that every triple has at
     least that many queens placed (sizes the LDS stack).  Asynchronous on
     ``stream`` (default: torch's current stream) unless timing=True.
     ``nodes`` (int64[F] CUDA tensor) receives the DFS nodes of every entry.
