@@ -144,6 +144,30 @@ __device__ __forceinline__ void isa_pop(u32x4& st, int32_t& top, int32_t floor, 
         : "memory", "scc");
 }
 
+// Pop as isa_pop, and while the frame is read from LDS, count the step's
+// leaves for the whole wave: leaves += popcount(anym & leafm), in SALU
+// instructions issued before the wait (the wave waits for the read anyway).
+__device__ __forceinline__ void isa_pop_count(u32x4& st, int32_t& top, int32_t floor, uint64_t m,
+                                              uint64_t anym, uint64_t leafm, uint32_t& leaves) {
+    uint64_t sv, cm;
+    uint32_t n;
+    int32_t t;
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[m]\n\t"
+        "ds_read_b128 %[st], %[top]\n\t"
+        "v_add_u32 %[t], 0xfffffc00, %[top]\n\t"
+        "v_max_i32 %[top], %[t], %[fl]\n\t"
+        "s_mov_b64 exec, %[sv]\n\t"
+        "s_and_b64 %[cm], %[am], %[lm]\n\t"
+        "s_bcnt1_i32_b64 %[n], %[cm]\n\t"
+        "s_add_u32 %[lv], %[lv], %[n]\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [st] "+v"(st), [top] "+v"(top), [sv] "=&s"(sv), [t] "=&v"(t), [cm] "=&s"(cm),
+          [n] "=&s"(n), [lv] "+s"(leaves)
+        : [m] "s"(m), [fl] "v"(floor), [am] "s"(anym), [lm] "s"(leafm)
+        : "memory", "scc");
+}
+
 // p = lowest set bit of v; v loses it (in place, so the loop-carried register
 // of v is also the one the pop writes).
 __device__ __forceinline__ void isa_take_lowest(uint32_t& v, uint32_t& p) {
@@ -417,10 +441,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                     const uint64_t anym = __builtin_amdgcn_ballot_w64(a != 0u);
                     const uint64_t restm = __builtin_amdgcn_ballot_w64(rest != 0u);
                     const uint64_t descm = anym & ~leafm;
-                    if constexpr (WC)
-                        leaves += (uint32_t)__popcll(anym & leafm);
-                    else
-                        isa_count(sum32, anym & leafm);
+                    if constexpr (!WC) isa_count(sum32, anym & leafm);
                     st.w = rest;
                     isa_push(st, top, descm & restm);
                     st.x = isa_sel(descm, nc, st.x);
@@ -429,7 +450,10 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                     st.w = isa_sel(descm, a, st.w);
                     // After the select, avail == 0 exactly when the lane did not
                     // descend (a descent has a != 0) and had no untried column left.
-                    isa_pop(st, top, floor, ~(descm | restm));
+                    if constexpr (WC)
+                        isa_pop_count(st, top, floor, ~(descm | restm), anym, leafm, leaves);
+                    else
+                        isa_pop(st, top, floor, ~(descm | restm));
                     trips = __builtin_amdgcn_readfirstlane(trips - 1u);
                 } while (trips != 0u);
                 if constexpr (WC) wave_acc += leaves;

@@ -139,6 +139,33 @@ def test_weights_and_accumulating_total():
     assert int(total.item()) == 5 + 14200
 
 
+@pytest.mark.parametrize("mode", ["persistent", "plain"])
+def test_totals_without_per_entry_counts(mode):
+    """Totals when no per-entry result is written: uniform weights (counted per
+    wave), mixed weights and no weights (counted per lane), against the oracle."""
+    nq = _nq()
+    n, k = 14, 3
+    pre, _ = oracle.frontier(n, k)
+    ref, _ = oracle.count_prefixes(n, pre, threads=8)
+    ref = ref.astype(np.uint64)
+    c, l, r = _triples_from_prefixes(n, pre)
+    rng = np.random.default_rng(1403)
+    cases = {"uniform 3": np.full(len(pre), 3, np.uint8),
+             "uniform 0": np.zeros(len(pre), np.uint8),
+             "mixed": rng.integers(0, 256, len(pre)).astype(np.uint8),
+             "none": None}
+    for name, w in cases.items():
+        _say("totals", mode, name)
+        total = torch.zeros(1, dtype=torch.int64, device="cuda")
+        tw = None if w is None else torch.from_numpy(w).cuda()
+        nq.count_subproblems(n, c, l, r, weight=tw, counts=False, total=total, depth=k,
+                             mode=mode)
+        torch.cuda.synchronize()
+        expect = int((ref * (np.ones(len(pre), np.uint64) if w is None
+                             else w.astype(np.uint64))).sum())
+        assert int(total.item()) == expect, name
+
+
 def test_large_boards_deep_prefixes():
     """n = 24..28 with deep prefixes: the popcount leaf test and the widest masks."""
     nq = _nq()
