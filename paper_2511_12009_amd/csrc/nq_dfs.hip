@@ -387,11 +387,18 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         // The frame is kept as one 4-vector so that push and pop move it with
         // a single ds_write_b128 / ds_read_b128 and no register shuffling.
         u32x4 st = {c, l, r, v};
-        // Steps run in chunks of 32 (forms 1 and 2); between chunks a
-        // persistent wave returns to the scheduler early once `idle_min` of
-        // its lanes have finished (avail == 0 after a step), so a finished
-        // lane waits for at most one chunk instead of `refill_every` steps.
-        // The trip counts are wave-uniform; readfirstlane keeps them in SGPRs.
+        // Steps run in chunks of 32 (forms 1 and 2).  After a chunk a wave
+        // returns to the scheduler early when all its lanes have finished
+        // (avail == 0 after a step) or, in persistent mode, once `idle_min` of
+        // them have, so a finished lane waits for at most one chunk instead of
+        // `refill_every` steps.  The trip counts are wave-uniform;
+        // readfirstlane keeps them in SGPRs.
+        auto chunk_done = [&](uint32_t avail) {
+            const uint32_t idle = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(avail == 0u));
+            const uint32_t lanes = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(true));
+            return idle == lanes ||
+                   (PERSISTENT && P.idle_min && !exhausted && idle >= P.idle_min);
+        };
         if (LOOP == 0) {
         for (uint32_t it = 0; it < P.refill_every; ++it) {
             const uint32_t p = st.w & (0u - st.w);    // lowest untried column
@@ -458,10 +465,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 } while (trips != 0u);
                 if constexpr (WC) wave_acc += leaves;
                 chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
-                if (chunks == 0u) break;
-                if (PERSISTENT && P.idle_min && !exhausted &&
-                    (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(st.w == 0u)) >= P.idle_min)
-                    break;
+                if (chunks == 0u || chunk_done(st.w)) break;
             }
         };
         if (wave_w)
@@ -500,10 +504,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 trips = __builtin_amdgcn_readfirstlane(trips - 1u);
             } while (trips != 0u);
             chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
-            if (chunks == 0u) break;
-            if (PERSISTENT && P.idle_min && !exhausted &&
-                (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(st.w == 0u)) >= P.idle_min)
-                break;
+            if (chunks == 0u || chunk_done(st.w)) break;
         }
         st.w = 0u - st.w;
         }
