@@ -301,13 +301,65 @@ def test_count_with_device_expansion(known_counts):
             np.testing.assert_array_equal(counts, ref)
 
 
-@pytest.mark.parametrize("n,k", [(19, 6), (20, 7), (20, 8), (21, 7)])
+@pytest.mark.parametrize("n,k", [(19, 6), (20, 7), (20, 8), (20, 10), (21, 7)])
 def test_large_counts_at_tuned_depths(n, k, known_counts):
     """Full counts at the depths the autotuner chooses from (published totals);
     depth >= 7 goes through the device expansion."""
     nq = _nq()
     _say("large count", n, k)
     assert nq.count(n, depth=k, mode="persistent") == known_counts[n]
+
+
+def test_benchmark_configuration():
+    """The benchmark's workload, N=20 at depth 9 (812 M subproblems resident,
+    built on the device, persistent launch): the total without per-entry output
+    (wave-level leaf count) and, with per-entry output, the node total of the
+    node-counting kernel against the oracle's (the numerator of the reported
+    nodes/s); then seeded depth-9 subproblems (random legal extensions of
+    oracle depth-7 prefixes) counted per entry against the oracle."""
+    nq = _nq()
+    n, k = 20, 9
+    _say("bench config: total")
+    assert nq.count(n, depth=k) == 39029188884
+    nodes_ref = {(int(r[0]), int(r[1])): int(r[2]) for r in read_table("oracle_nodes.txt")}
+    _say("bench config: nodes")
+    cols, ld, rd, w = nq.frontier(n, 7)
+    dev = [_dev(x) for x in (cols, ld, rd)]
+    c, l, r, tw = nq.expand(n, 2, *dev, weight=torch.from_numpy(w).cuda())
+    del dev
+    torch.cuda.synchronize()
+    assert c.numel() == 811572426
+    nodes = torch.empty(c.numel(), dtype=torch.int64, device="cuda")
+    _, total = nq.count_subproblems(n, c, l, r, weight=tw, depth=k, nodes=nodes)
+    torch.cuda.synchronize()
+    assert int(total.item()) == 39029188884
+    assert int(nodes.sum().item()) == nodes_ref[(n, k)]
+    del c, l, r, tw, nodes
+    _say("bench config: sampled subproblems")
+    pre7, _ = oracle.frontier(n, 7)
+    rng = np.random.default_rng(209)
+    sample = []
+    while len(sample) < 256:
+        p = [int(x) for x in pre7[rng.integers(len(pre7))]]
+        for _row in range(2):
+            free = [col for col in range(n) if _free(p, col)]
+            if not free:
+                break
+            p.append(free[rng.integers(len(free))])
+        if len(p) == 9:
+            sample.append(p)
+    pre9 = np.asarray(sample, dtype=np.int32)
+    ref, _ = oracle.count_prefixes(n, pre9, threads=8)
+    tc, tl, tr = _triples_from_prefixes(n, pre9)
+    counts, _ = nq.count_subproblems(n, tc, tl, tr, depth=k)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(counts.cpu().numpy().view(np.uint64), ref)
+
+
+def _free(prefix, col):
+    """True when a queen in the next row at `col` attacks none of `prefix`."""
+    row = len(prefix)
+    return all(c != col and abs(c - col) != row - i for i, c in enumerate(prefix))
 
 
 def test_expansion_of_odd_board_from_depth_one(known_counts):
