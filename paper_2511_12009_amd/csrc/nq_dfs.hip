@@ -271,6 +271,8 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         wave_w = P.wrange[0];
     wave_w = __builtin_amdgcn_readfirstlane(wave_w);
     uint64_t wave_acc = 0;                // leaves counted per wave (uniform)
+    uint32_t acc_s = 0u;                  // batches: instance of the lane's pending sum
+    uint64_t acc_v = 0;                   // batches: weighted sum not yet added
     bool has_task = false;                // holds an entry not yet retired
     bool exhausted = !PERSISTENT;         // no entries left to claim (wave-uniform)
     bool claimed_all = false;             // head has passed the end (wave-uniform)
@@ -336,10 +338,22 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
             const bool inst_ok = !P.inst || s < P.ninst;
             if (P.totals && ok && sum64 != 0) {
                 const uint64_t w = P.weight ? (uint64_t)P.weight[idx] : 1u;
-                if (P.inst)
-                    atomicAdd(&P.totals[s], (unsigned long long)(w * sum64));
-                else
+                if (!P.inst) {
                     wtotal += w * sum64;
+                } else if (P.remaining) {
+                    // serving: the total must be complete before the request's
+                    // remaining count can reach zero
+                    atomicAdd(&P.totals[s], (unsigned long long)(w * sum64));
+                } else {
+                    // batches: a lane's consecutive entries mostly belong to one
+                    // instance; add to its total when the instance changes
+                    if (s != acc_s) {
+                        if (acc_v) atomicAdd(&P.totals[acc_s], (unsigned long long)acc_v);
+                        acc_s = s;
+                        acc_v = 0;
+                    }
+                    acc_v += w * sum64;
+                }
             }
             if (P.remaining && inst_ok)
                 publish_if_last(P.remaining, P.totals, P.inst_gen, P.host_val, P.host_flag, s);
@@ -511,6 +525,8 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         c = st.x; l = st.y; r = st.z; v = st.w;
     }
 
+    if (P.totals && P.inst && !P.remaining && acc_v)
+        atomicAdd(&P.totals[acc_s], (unsigned long long)acc_v);
     if (P.totals && !P.inst) {
         for (int off = 32; off > 0; off >>= 1) wtotal += shfl_xor_u64(wtotal, off);
         wtotal += (uint64_t)wave_w * wave_acc;
