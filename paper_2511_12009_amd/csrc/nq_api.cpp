@@ -129,22 +129,11 @@ static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
                      len, d_nodes != nullptr, leafctr_ok(n, min_placed), &cfg);
     if (rc != NQ_OK) return rc;
     hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
-    // Scratch: the work head (persistent) and the weight range (when no
-    // per-entry output is written, for the kernel's wave-level leaf count).
-    const bool want_range = !d_counts && !d_nodes && d_total;
     unsigned long long* head = nullptr;
-    if (mode == NQ_MODE_PERSISTENT || want_range)
-        NQ_HIP(hipMallocAsync((void**)&head, 16, s));
-    uint32_t* wrange = want_range ? reinterpret_cast<uint32_t*>(head + 1) : nullptr;
-    if (wrange && (rc = launch_weight_range(d_weight, len, wrange, s)) != NQ_OK) {
-        (void)hipFreeAsync(head, s);
-        return rc;
-    }
+    if (mode == NQ_MODE_PERSISTENT) NQ_HIP(hipMallocAsync((void**)&head, 8, s));
     DfsParams P{};
     P.cols = d_cols; P.ld = d_ld; P.rd = d_rd; P.weight = d_weight;
-    P.counts = d_counts; P.totals = d_total; P.nodes = d_nodes;
-    P.head = mode == NQ_MODE_PERSISTENT ? head : nullptr;
-    P.wrange = wrange;
+    P.counts = d_counts; P.totals = d_total; P.nodes = d_nodes; P.head = head;
     P.len = len; P.n = n; P.frames = frames; P.refill_every = refill_default(opts);
     P.idle_min = default_idle_min();
     P.claim = (opts && opts->claim) ? opts->claim : default_claim(len, cfg);

@@ -33,7 +33,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
-#include <type_traits>
 
 #include "nq_internal.h"
 
@@ -144,30 +143,6 @@ __device__ __forceinline__ void isa_pop(u32x4& st, int32_t& top, int32_t floor, 
         : "memory", "scc");
 }
 
-// Pop as isa_pop, and while the frame is read from LDS, count the step's
-// leaves for the whole wave: leaves += popcount(anym & leafm), in SALU
-// instructions issued before the wait (the wave waits for the read anyway).
-__device__ __forceinline__ void isa_pop_count(u32x4& st, int32_t& top, int32_t floor, uint64_t m,
-                                              uint64_t anym, uint64_t leafm, uint32_t& leaves) {
-    uint64_t sv, cm;
-    uint32_t n;
-    int32_t t;
-    asm volatile(
-        "s_and_saveexec_b64 %[sv], %[m]\n\t"
-        "ds_read_b128 %[st], %[top]\n\t"
-        "v_add_u32 %[t], 0xfffffc00, %[top]\n\t"
-        "v_max_i32 %[top], %[t], %[fl]\n\t"
-        "s_mov_b64 exec, %[sv]\n\t"
-        "s_and_b64 %[cm], %[am], %[lm]\n\t"
-        "s_bcnt1_i32_b64 %[n], %[cm]\n\t"
-        "s_add_u32 %[lv], %[lv], %[n]\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : [st] "+v"(st), [top] "+v"(top), [sv] "=&s"(sv), [t] "=&v"(t), [cm] "=&s"(cm),
-          [n] "=&s"(n), [lv] "+s"(leaves)
-        : [m] "s"(m), [fl] "v"(floor), [am] "s"(anym), [lm] "s"(leafm)
-        : "memory", "scc");
-}
-
 // p = lowest set bit of v; v loses it (in place, so the loop-carried register
 // of v is also the one the pop writes).
 __device__ __forceinline__ void isa_take_lowest(uint32_t& v, uint32_t& p) {
@@ -259,18 +234,6 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     uint32_t sum32 = 0, steps32 = 0;
     uint64_t sum64 = 0, steps64 = 0;
     uint64_t wtotal = 0;                  // weighted total, single-instance launches
-    // Wave-level leaf count (form 1): when the launch writes no per-entry
-    // result and every entry has the same weight W, the leaves found by DFS
-    // steps are counted per wave in SALU (a popcount of the step's leaf mask),
-    // so the step needs no per-lane add, and W times the count is added to the
-    // total at the end.  Entries settled without a search still use the
-    // per-lane sums.
-    uint32_t wave_w = 0;                  // 0 = per-lane counting
-    if (LOOP == 1 && !STATS && P.wrange && P.totals && !P.inst && !P.counts && !P.remaining &&
-        P.wrange[0] == P.wrange[1])
-        wave_w = P.wrange[0];
-    wave_w = __builtin_amdgcn_readfirstlane(wave_w);
-    uint64_t wave_acc = 0;                // leaves counted per wave (uniform)
     uint32_t acc_s = 0u;                  // batches: instance of the lane's pending sum
     uint64_t acc_v = 0;                   // batches: weighted sum not yet added
     bool has_task = false;                // holds an entry not yet retired
@@ -443,49 +406,38 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         } else if (LOOP == 1) {
         // The lane masks live in SGPR pairs; the push, the selects, the pop
         // and the leaf count use them directly.
-        auto run = [&](auto wave_count) {
-            constexpr bool WC = decltype(wave_count)::value;
-            uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 31u) / 32u);
-            for (;;) {
-                uint32_t trips = 32u, leaves = 0u;
-                do {
-                    // p = lowest untried column; the untried set keeps its register.
-                    uint32_t p, rest = st.w;
-                    isa_take_lowest(rest, p);
-                    const uint32_t nc = LEAFCTR ? st.x + p + step_k : (st.x | p);
-                    const uint32_t nl = (st.y + p) << 1;
-                    const uint32_t nr = (st.z + p) >> 1;
-                    const uint32_t a = last & ~(nc | nl | nr);
-                    if (STATS) steps32 += (p != 0u);
-                    const uint64_t leafm = __builtin_amdgcn_ballot_w64(
-                        LEAFCTR ? (int32_t)nc < 0 : __popc(nc) == nm1);
-                    const uint64_t anym = __builtin_amdgcn_ballot_w64(a != 0u);
-                    const uint64_t restm = __builtin_amdgcn_ballot_w64(rest != 0u);
-                    const uint64_t descm = anym & ~leafm;
-                    if constexpr (!WC) isa_count(sum32, anym & leafm);
-                    st.w = rest;
-                    isa_push(st, top, descm & restm);
-                    st.x = isa_sel(descm, nc, st.x);
-                    st.y = isa_sel(descm, nl, st.y);
-                    st.z = isa_sel(descm, nr, st.z);
-                    st.w = isa_sel(descm, a, st.w);
-                    // After the select, avail == 0 exactly when the lane did not
-                    // descend (a descent has a != 0) and had no untried column left.
-                    if constexpr (WC)
-                        isa_pop_count(st, top, floor, ~(descm | restm), anym, leafm, leaves);
-                    else
-                        isa_pop(st, top, floor, ~(descm | restm));
-                    trips = __builtin_amdgcn_readfirstlane(trips - 1u);
-                } while (trips != 0u);
-                if constexpr (WC) wave_acc += leaves;
-                chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
-                if (chunks == 0u || chunk_done(st.w)) break;
-            }
-        };
-        if (wave_w)
-            run(std::true_type{});
-        else
-            run(std::false_type{});
+        uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 31u) / 32u);
+        for (;;) {
+            uint32_t trips = 32u;
+            do {
+                // p = lowest untried column; the untried set keeps its register.
+                uint32_t p, rest = st.w;
+                isa_take_lowest(rest, p);
+                const uint32_t nc = LEAFCTR ? st.x + p + step_k : (st.x | p);
+                const uint32_t nl = (st.y + p) << 1;
+                const uint32_t nr = (st.z + p) >> 1;
+                const uint32_t a = last & ~(nc | nl | nr);
+                if (STATS) steps32 += (p != 0u);
+                const uint64_t leafm = __builtin_amdgcn_ballot_w64(
+                    LEAFCTR ? (int32_t)nc < 0 : __popc(nc) == nm1);
+                const uint64_t anym = __builtin_amdgcn_ballot_w64(a != 0u);
+                const uint64_t restm = __builtin_amdgcn_ballot_w64(rest != 0u);
+                const uint64_t descm = anym & ~leafm;
+                isa_count(sum32, anym & leafm);
+                st.w = rest;
+                isa_push(st, top, descm & restm);
+                st.x = isa_sel(descm, nc, st.x);
+                st.y = isa_sel(descm, nl, st.y);
+                st.z = isa_sel(descm, nr, st.z);
+                st.w = isa_sel(descm, a, st.w);
+                // After the select, avail == 0 exactly when the lane did not
+                // descend (a descent has a != 0) and had no untried column left.
+                isa_pop(st, top, floor, ~(descm | restm));
+                trips = __builtin_amdgcn_readfirstlane(trips - 1u);
+            } while (trips != 0u);
+            chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
+            if (chunks == 0u || chunk_done(st.w)) break;
+        }
         } else {
         // Form 2.  The frame keeps the untried set negated, w = -avail (mod
         // 2^32), so that two lane masks come out of carries instead of
@@ -529,27 +481,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         atomicAdd(&P.totals[acc_s], (unsigned long long)acc_v);
     if (P.totals && !P.inst) {
         for (int off = 32; off > 0; off >>= 1) wtotal += shfl_xor_u64(wtotal, off);
-        wtotal += (uint64_t)wave_w * wave_acc;
         if (lane == 0 && wtotal != 0) atomicAdd(&P.totals[0], (unsigned long long)wtotal);
-    }
-}
-
-__global__ void nq_weight_range_kernel(const uint8_t* __restrict__ w, uint64_t len,
-                                       uint32_t* range) {
-    uint32_t lo = 0xffffffffu, hi = 0u;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
-        const uint32_t x = w ? w[i] : 1u;
-        lo = min(lo, x);
-        hi = max(hi, x);
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
-        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
-    }
-    if ((threadIdx.x & 63u) == 0u) {
-        atomicMin(&range[0], lo);
-        atomicMax(&range[1], hi);
     }
 }
 
@@ -728,19 +660,6 @@ int launch_fill_u32(uint32_t* dst, uint32_t value, uint64_t count, void* stream)
     if (grid > 0x7fffffffull) return NQ_EINVAL;
     hipLaunchKernelGGL(nq_fill_u32_kernel, dim3((uint32_t)grid), dim3(block), 0,
                        (hipStream_t)stream, dst, value, count);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
-    return NQ_OK;
-}
-
-int launch_weight_range(const uint8_t* w, uint64_t len, uint32_t* range, void* stream) {
-    int rc = launch_fill_u32(range, 0xffffffffu, 1, stream);
-    if (rc == NQ_OK) rc = launch_fill_u32(range + 1, 0u, 1, stream);
-    if (rc != NQ_OK || len == 0) return rc;
-    const uint32_t block = 256;
-    const uint64_t grid = std::min<uint64_t>((len + block - 1) / block, 2048);
-    hipLaunchKernelGGL(nq_weight_range_kernel, dim3((uint32_t)grid), dim3(block), 0,
-                       (hipStream_t)stream, w, len, range);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
     return NQ_OK;

@@ -57,9 +57,6 @@ struct DfsParams {
                                     // are never used to index (the entry is rejected)
     uint32_t idle_min;              // persistent: visit the scheduler early once this many
                                     // lanes of a wave are idle (0 = every refill_every steps)
-    const uint32_t* wrange;         // nullable, single-instance launches without per-entry
-                                    // outputs: {min, max} of the weights (device); when
-                                    // they are equal, form 1 counts leaves per wave
     uint32_t claim;                 // persistent: entries a wave claims per atomic on head
                                     // (at least what its idle lanes need); the surplus is
                                     // handed out at the wave's later visits
@@ -127,8 +124,6 @@ int launch_slot_init(const SlotInit* recs, uint32_t count, uint32_t* inst_n, uin
 int launch_zero_u64(unsigned long long* dst, uint64_t count, void* stream);
 // Enqueues dst[0..count) = value with a kernel.
 int launch_fill_u32(uint32_t* dst, uint32_t value, uint64_t count, void* stream);
-// Enqueues range[0] = min, range[1] = max of w[0..len) (w == nullptr: all 1).
-int launch_weight_range(const uint8_t* w, uint64_t len, uint32_t* range, void* stream);
 
 // Device frontier expansion (nq_expand.hip): scratch size for `len` parents,
 // and the expansion itself; *out_len gets the child count (the call waits on
