@@ -234,8 +234,9 @@ int nq_autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_
  *
  * nq_batch_create builds and uploads the concatenated frontiers of ninst >= 1
  * instances (as nq_count_batch; depths[i] in [1, ns[i]] or NULL for
- * opts->depth, else max(5, ns[i] - 12) -- at most 10 stack frames per lane --
- * capped at ns[i] - 2 and at least 1), allocates every device and
+ * opts->depth, else max(5, ns[i] - 11) -- at most 9 stack frames per lane --
+ * capped at ns[i] - 2 and at least 1; deep frontiers are built by device
+ * expansion), allocates every device and
  * pinned host buffer the launch needs, and captures one HIP graph: zero the
  * totals, zero the work head, the persistent DFS kernel, copy the totals to
  * the host.  The plan owns a private stream.  nq_batch_run replays the graph,

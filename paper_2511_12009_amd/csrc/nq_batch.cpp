@@ -48,11 +48,12 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 
-// Default depth of one instance: 5, or n - 12 for large boards, so that no
-// instance needs more than 10 stack frames (11 KB of LDS per wave: 14 resident
-// waves per CU) and the largest instances are cut into millions of subtrees.
+// Default depth of one instance: 5, or n - 11 for large boards, so that no
+// instance needs more than 9 stack frames (10 KB of LDS per wave: 16 resident
+// waves per CU) and the largest instances are cut into tens of millions of
+// subtrees (their frontiers are built by device expansion).
 uint32_t batch_default_depth(uint32_t n, uint32_t requested) {
-    uint32_t k = requested ? requested : std::max<uint32_t>(5u, n > 12 ? n - 12 : 0u);
+    uint32_t k = requested ? requested : std::max<uint32_t>(5u, n > 11 ? n - 11 : 0u);
     const uint32_t cap = n > 2 ? n - 2 : 1u;
     return std::max<uint32_t>(1u, std::min(k, cap));
 }
@@ -75,16 +76,22 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
         return code;
     };
     try {
-        // Frontier sizes, depth and stack needs per instance.
+        if ((e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess) {
+            set_hip_error(e);
+            return fail(NQ_EDEVICE);
+        }
+        // Every instance's frontier on the device (deep ones by device
+        // expansion), then one concatenated copy with instance ids.
         std::vector<uint32_t> k(ninst);
-        std::vector<uint64_t> F(ninst), off(ninst + 1, 0);
+        std::vector<uint64_t> off(ninst + 1, 0);
+        std::vector<DeviceFrontier> fr(ninst);
         uint32_t frames = 1;
         bool leafctr = true;
         for (uint32_t i = 0; i < ninst; ++i) {
             k[i] = depths ? depths[i] : batch_default_depth(ns[i], opts ? opts->depth : 0);
-            rc = frontier_fill(ns[i], k[i], nullptr, nullptr, nullptr, nullptr, 0, &F[i], nullptr);
-            if (rc != NQ_OK) return fail(rc);
-            off[i + 1] = off[i] + F[i];
+            if ((rc = build_device_frontier(ns[i], k[i], b->stream, &fr[i])) != NQ_OK)
+                return fail(rc);
+            off[i + 1] = off[i] + fr[i].len;
             frames = std::max(frames, frames_needed(ns[i], k[i]));
             leafctr = leafctr && leafctr_ok(ns[i], k[i]);
         }
@@ -105,40 +112,34 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
             return fail(NQ_ENOMEM);
         }
         std::memset(b->h_totals, 0, std::max<size_t>(8, ninst * 8ull));
-        if ((e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess) {
-            set_hip_error(e);
-            return fail(NQ_EDEVICE);
-        }
         char* d = static_cast<char*>(b->dev);
-        // Host staging, one instance at a time.
+        const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
+        for (uint32_t i = 0; i < ninst; ++i) {
+            const uint64_t o = off[i], m = fr[i].len;
+            if (m == 0) continue;
+            if ((e = hipMemcpyAsync(d + o * 4, fr[i].cols, m * 4, d2d, b->stream)) !=
+                    hipSuccess ||
+                (e = hipMemcpyAsync(d + o_ld + o * 4, fr[i].ld, m * 4, d2d, b->stream)) !=
+                    hipSuccess ||
+                (e = hipMemcpyAsync(d + o_rd + o * 4, fr[i].rd, m * 4, d2d, b->stream)) !=
+                    hipSuccess ||
+                (e = hipMemcpyAsync(d + o_w + o, fr[i].w, m, d2d, b->stream)) != hipSuccess) {
+                set_hip_error(e);
+                return fail(NQ_EDEVICE);
+            }
+            rc = launch_fill_u32(reinterpret_cast<uint32_t*>(d + o_inst) + o, i, m, b->stream);
+            if (rc != NQ_OK) return fail(rc);
+        }
         {
-            std::vector<uint32_t> hc(total), hl(total), hr(total), hi(total);
-            std::vector<uint8_t> hw(total);
-            for (uint32_t i = 0; i < ninst; ++i) {
-                uint64_t got = 0;
-                if (F[i])
-                    rc = frontier_fill(ns[i], k[i], hc.data() + off[i], hl.data() + off[i],
-                                       hr.data() + off[i], hw.data() + off[i], F[i], &got, nullptr);
-                if (rc != NQ_OK) return fail(rc);
-                std::fill(hi.begin() + off[i], hi.begin() + off[i + 1], i);
-            }
             std::vector<uint32_t> hn(ns, ns + ninst);
-            const hipMemcpyKind h2d = hipMemcpyHostToDevice;
-            if (total) {
-                if ((e = hipMemcpy(d, hc.data(), total * 4, h2d)) != hipSuccess ||
-                    (e = hipMemcpy(d + o_ld, hl.data(), total * 4, h2d)) != hipSuccess ||
-                    (e = hipMemcpy(d + o_rd, hr.data(), total * 4, h2d)) != hipSuccess ||
-                    (e = hipMemcpy(d + o_inst, hi.data(), total * 4, h2d)) != hipSuccess ||
-                    (e = hipMemcpy(d + o_w, hw.data(), total, h2d)) != hipSuccess) {
-                    set_hip_error(e);
-                    return fail(NQ_EDEVICE);
-                }
-            }
-            if (ninst && (e = hipMemcpy(d + o_n, hn.data(), ninst * 4ull, h2d)) != hipSuccess) {
+            if ((e = hipMemcpyAsync(d + o_n, hn.data(), ninst * 4ull, hipMemcpyHostToDevice,
+                                    b->stream)) != hipSuccess ||
+                (e = hipStreamSynchronize(b->stream)) != hipSuccess) {
                 set_hip_error(e);
                 return fail(NQ_EDEVICE);
             }
         }
+        fr.clear();                                   // per-instance copies no longer needed
         b->d_totals = reinterpret_cast<unsigned long long*>(d + o_tot);
         DfsParams& P = b->P;
         P.cols = reinterpret_cast<uint32_t*>(d);
