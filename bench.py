@@ -244,8 +244,8 @@ def main():
                          "counters), then one persistent DFS launch at --depth; no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by splitting the frontier, see the design notes)",
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              "(subproblems are independent: the path would shard by splitting the frontier)",
               file=sys.stderr)
         sys.exit(2)
 
