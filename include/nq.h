@@ -160,7 +160,8 @@ typedef struct nq_opts {
  * nq_count -- Q(n): the number of ways to place n non-attacking queens.
  *
  * Builds the frontier of depth opts->depth (on the host, nq_frontier; for depth
- * >= 7 a shallower one on the host that nq_expand deepens on the device) in
+ * >= 7 the depth-5 one on the host, deepened on the device by nq_expand in
+ * steps of at most three rows) in
  * device memory owned by the library, runs the DFS kernels (Algorithm 2 with
  * the last-row step of Algorithm 3, one subproblem per lane) and returns the
  * weighted total in *out_total.  Synchronous: returns after the result is on the

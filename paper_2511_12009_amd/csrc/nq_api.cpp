@@ -149,95 +149,142 @@ static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
     return rc;
 }
 
+
+namespace {
+
+// Allocates the arrays of a frontier of `len` entries (cols | ld | rd | weight).
+int alloc_frontier(uint64_t len, DeviceFrontier* f) {
+    const size_t o_ld = len * 4, o_rd = 2 * len * 4, o_w = 3 * len * 4;
+    DevBuf arr;
+    int rc = arr.alloc(o_w + len + 16);
+    if (rc != NQ_OK) return rc;
+    char* b = arr.as<char>();
+    f->dev = arr.p;
+    arr.p = nullptr;
+    f->len = len;
+    f->cols = reinterpret_cast<uint32_t*>(b);
+    f->ld = reinterpret_cast<uint32_t*>(b + o_ld);
+    f->rd = reinterpret_cast<uint32_t*>(b + o_rd);
+    f->w = reinterpret_cast<uint8_t*>(b + o_w);
+    return NQ_OK;
+}
+
+// The host frontier of depth `depth` (nq_frontier) uploaded to the device.
+int host_frontier(uint32_t n, uint32_t depth, hipStream_t s, DeviceFrontier* out) {
+    uint64_t F = 0;
+    std::vector<uint64_t> first_row;
+    int rc = frontier_fill(n, depth, nullptr, nullptr, nullptr, nullptr, 0, &F, nullptr);
+    if (rc != NQ_OK) return rc;
+    std::vector<uint32_t> hc(F), hl(F), hr(F);
+    std::vector<uint8_t> hw(F);
+    rc = frontier_fill(n, depth, hc.data(), hl.data(), hr.data(), hw.data(), F, &F, &first_row);
+    if (rc != NQ_OK) return rc;
+    if ((rc = alloc_frontier(F, out)) != NQ_OK) return rc;
+    if (F) {
+        NQ_HIP(hipMemcpyAsync(out->cols, hc.data(), F * 4, hipMemcpyHostToDevice, s));
+        NQ_HIP(hipMemcpyAsync(out->ld, hl.data(), F * 4, hipMemcpyHostToDevice, s));
+        NQ_HIP(hipMemcpyAsync(out->rd, hr.data(), F * 4, hipMemcpyHostToDevice, s));
+        NQ_HIP(hipMemcpyAsync(out->w, hw.data(), F, hipMemcpyHostToDevice, s));
+    }
+    NQ_HIP(hipStreamSynchronize(s));              // the host vectors die here
+    out->first_row = std::move(first_row);
+    return NQ_OK;
+}
+
+// `in` expanded by `rows` (1..3) on the device into `out`; the row-0 runs are
+// carried over, and `offsets` (nullable) receives the index of the first child
+// of every entry of `in` (offsets[in.len] = out->len).
+int expand_frontier(uint32_t n, const DeviceFrontier& in, uint32_t rows, hipStream_t s,
+                    DeviceFrontier* out, std::vector<uint64_t>* offsets) {
+    if (in.len == 0) {                            // nothing to expand
+        if (offsets) offsets->assign(1, 0);
+        out->first_row.assign(in.first_row.size(), 0);
+        return alloc_frontier(0, out);
+    }
+    DevBuf scratch;
+    int rc = scratch.alloc(expand_scratch_bytes(in.len));
+    if (rc != NQ_OK) return rc;
+    uint64_t F = 0;
+    rc = expand_device(n, rows, in.cols, in.ld, in.rd, in.w, in.len, nullptr, nullptr, nullptr,
+                       nullptr, 0, &F, scratch.p, s);
+    if (rc != NQ_OK) return rc;
+    std::vector<uint64_t> first_row = in.first_row;
+    const uint64_t* offs = scratch.as<uint64_t>() + (in.len + 1);
+    if (offsets) {
+        offsets->resize(in.len + 1);
+        NQ_HIP(hipMemcpy(offsets->data(), offs, (in.len + 1) * 8, hipMemcpyDeviceToHost));
+        for (auto& o : first_row) o = (*offsets)[o];
+    } else {
+        for (auto& o : first_row) {
+            uint64_t v = 0;
+            NQ_HIP(hipMemcpy(&v, offs + o, 8, hipMemcpyDeviceToHost));
+            o = v;
+        }
+    }
+    if ((rc = alloc_frontier(F, out)) != NQ_OK) return rc;
+    uint64_t got = 0;
+    rc = expand_device(n, rows, in.cols, in.ld, in.rd, in.w, in.len, out->cols, out->ld, out->rd,
+                       out->w, F, &got, scratch.p, s);
+    if (rc != NQ_OK) return rc;
+    NQ_HIP(hipStreamSynchronize(s));              // the scratch dies here
+    out->first_row = std::move(first_row);
+    return NQ_OK;
+}
+
+}  // namespace
+
 DeviceFrontier::~DeviceFrontier() {
     if (dev) (void)hipFree(dev);
 }
 
+DeviceFrontier& DeviceFrontier::operator=(DeviceFrontier&& o) noexcept {
+    if (this != &o) {
+        if (dev) (void)hipFree(dev);
+        dev = o.dev; len = o.len; cols = o.cols; ld = o.ld; rd = o.rd; w = o.w;
+        first_row = std::move(o.first_row);
+        o.dev = nullptr;
+        o.len = 0;
+    }
+    return *this;
+}
+
 int build_device_frontier(uint32_t n, uint32_t depth, void* stream, DeviceFrontier* out) {
-    const uint32_t host_depth = depth >= 7 ? depth - std::min<uint32_t>(2, depth - 5) : depth;
-    return build_device_frontier_at(n, host_depth, depth - host_depth, stream, out, nullptr);
+    if (!out || out->dev || depth > n) return NQ_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    // Depth 5 on the host (3e5 entries at N = 20), the rest in device
+    // expansions of up to three rows each.
+    uint32_t have = depth >= 7 ? 5u : depth;
+    DeviceFrontier cur;
+    int rc = host_frontier(n, have, s, &cur);
+    if (rc != NQ_OK) return rc;
+    while (have < depth) {
+        // equal steps (5 -> 7 -> 9, not 5 -> 8 -> 9): the last input stays small
+        const uint32_t left = depth - have, steps = (left + 2) / 3;
+        const uint32_t rows = (left + steps - 1) / steps;
+        DeviceFrontier next;
+        if ((rc = expand_frontier(n, cur, rows, s, &next, nullptr)) != NQ_OK) return rc;
+        cur = std::move(next);
+        have += rows;
+    }
+    *out = std::move(cur);
+    return NQ_OK;
 }
 
 int build_device_frontier_at(uint32_t n, uint32_t host_depth, uint32_t rows, void* stream,
                              DeviceFrontier* out, std::vector<uint64_t>* offsets) {
     if (!out || out->dev || rows > 3 || host_depth + rows > n) return NQ_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    uint64_t Fh = 0;
-    std::vector<uint64_t> first_row;
-    int rc = frontier_fill(n, host_depth, nullptr, nullptr, nullptr, nullptr, 0, &Fh, nullptr);
+    DeviceFrontier cur;
+    int rc = host_frontier(n, host_depth, s, &cur);
     if (rc != NQ_OK) return rc;
-    std::vector<uint32_t> hc(Fh), hl(Fh), hr(Fh);
-    std::vector<uint8_t> hw(Fh);
-    rc = frontier_fill(n, host_depth, hc.data(), hl.data(), hr.data(), hw.data(), Fh, &Fh,
-                       &first_row);
-    if (rc != NQ_OK) return rc;
-    DevBuf shallow, scratch;
-    uint64_t F = Fh;
-    char* sb = nullptr;
-    if (rows) {
-        // shallow frontier + expansion scratch, then the size of the deep one
-        if ((rc = shallow.alloc(Fh * 13 + 64)) != NQ_OK) return rc;
-        sb = shallow.as<char>();
-        if (Fh) {
-            NQ_HIP(hipMemcpyAsync(sb, hc.data(), Fh * 4, hipMemcpyHostToDevice, s));
-            NQ_HIP(hipMemcpyAsync(sb + Fh * 4, hl.data(), Fh * 4, hipMemcpyHostToDevice, s));
-            NQ_HIP(hipMemcpyAsync(sb + Fh * 8, hr.data(), Fh * 4, hipMemcpyHostToDevice, s));
-            NQ_HIP(hipMemcpyAsync(sb + Fh * 12, hw.data(), Fh, hipMemcpyHostToDevice, s));
-        }
-        if ((rc = scratch.alloc(expand_scratch_bytes(Fh))) != NQ_OK) return rc;
-        rc = expand_device(n, rows, reinterpret_cast<uint32_t*>(sb),
-                           reinterpret_cast<uint32_t*>(sb + Fh * 4),
-                           reinterpret_cast<uint32_t*>(sb + Fh * 8),
-                           reinterpret_cast<uint8_t*>(sb + Fh * 12), Fh, nullptr, nullptr,
-                           nullptr, nullptr, 0, &F, scratch.p, s);
-        if (rc != NQ_OK) return rc;
-        // row-0 runs of the deep frontier: the expansion offsets of the
-        // shallow runs' starts (offsets[Fh] = F)
-        const uint64_t* offs = scratch.as<uint64_t>() + (Fh + 1);
-        if (offsets) {
-            offsets->resize(Fh + 1);
-            NQ_HIP(hipMemcpy(offsets->data(), offs, (Fh + 1) * 8, hipMemcpyDeviceToHost));
-            for (auto& o : first_row) o = (*offsets)[o];
-        } else {
-            for (auto& o : first_row) {
-                uint64_t v = 0;
-                NQ_HIP(hipMemcpy(&v, offs + o, 8, hipMemcpyDeviceToHost));
-                o = v;
-            }
-        }
-    } else if (offsets) {
-        offsets->clear();
+    if (rows == 0) {
+        if (offsets) offsets->clear();
+        *out = std::move(cur);
+        return NQ_OK;
     }
-    const size_t o_ld = F * 4, o_rd = 2 * F * 4, o_w = 3 * F * 4;
-    DevBuf arr;
-    if ((rc = arr.alloc(o_w + F + 16)) != NQ_OK) return rc;
-    char* b = arr.as<char>();
-    if (rows) {
-        uint64_t got = 0;
-        rc = expand_device(n, rows, reinterpret_cast<uint32_t*>(sb),
-                           reinterpret_cast<uint32_t*>(sb + Fh * 4),
-                           reinterpret_cast<uint32_t*>(sb + Fh * 8),
-                           reinterpret_cast<uint8_t*>(sb + Fh * 12), Fh,
-                           reinterpret_cast<uint32_t*>(b), reinterpret_cast<uint32_t*>(b + o_ld),
-                           reinterpret_cast<uint32_t*>(b + o_rd),
-                           reinterpret_cast<uint8_t*>(b + o_w), F, &got, scratch.p, s);
-        if (rc != NQ_OK) return rc;
-    } else if (F) {
-        NQ_HIP(hipMemcpyAsync(b, hc.data(), F * 4, hipMemcpyHostToDevice, s));
-        NQ_HIP(hipMemcpyAsync(b + o_ld, hl.data(), F * 4, hipMemcpyHostToDevice, s));
-        NQ_HIP(hipMemcpyAsync(b + o_rd, hr.data(), F * 4, hipMemcpyHostToDevice, s));
-        NQ_HIP(hipMemcpyAsync(b + o_w, hw.data(), F, hipMemcpyHostToDevice, s));
-    }
-    // the host vectors and the scratch die here
-    NQ_HIP(hipStreamSynchronize(s));
-    out->dev = arr.p;
-    arr.p = nullptr;
-    out->len = F;
-    out->cols = reinterpret_cast<uint32_t*>(b);
-    out->ld = reinterpret_cast<uint32_t*>(b + o_ld);
-    out->rd = reinterpret_cast<uint32_t*>(b + o_rd);
-    out->w = reinterpret_cast<uint8_t*>(b + o_w);
-    out->first_row = std::move(first_row);
+    DeviceFrontier next;
+    if ((rc = expand_frontier(n, cur, rows, s, &next, offsets)) != NQ_OK) return rc;
+    *out = std::move(next);
     return NQ_OK;
 }
 

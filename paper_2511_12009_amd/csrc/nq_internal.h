@@ -170,7 +170,7 @@ struct DeviceFrontier {
           first_row(std::move(o.first_row)) {
         o.dev = nullptr;
     }
-    DeviceFrontier& operator=(DeviceFrontier&&) = delete;
+    DeviceFrontier& operator=(DeviceFrontier&& o) noexcept;   // frees what it held
     ~DeviceFrontier();
 };
 // Builds it on `stream` and waits for it.  NQ_ENOMEM when it does not fit.
