@@ -275,11 +275,14 @@ int nq_batch_destroy(nq_batch* batch);
  * allow, and launches bounded persistent "epochs" over the newly admitted
  * subproblems on four rotating streams, so new work overlaps the tail of
  * older work.  A request's result is published to pinned host memory by the
- * GPU lane that retires its last subproblem.
+ * GPU lane that retires its last subproblem (retirements are added to the
+ * request's total and remaining count once per wave and request).
  *
  * nq_serve_create: opts may set depth (= the LDS stack frames per lane of the
- * epoch kernel, default 14: a request whose subproblems need more stack than
- * that is refused with NQ_EINVAL at submit), wg_size, waves_per_cu and
+ * epoch kernel, default 14, at most 26 (NQ_EINVAL beyond): a request whose
+ * subproblems need more stack than that is refused with NQ_EINVAL at submit;
+ * each epoch's LDS stack is sized for the deepest request in it), wg_size,
+ * waves_per_cu and
  * refill_every; hbm_budget_bytes (0 = 8 GiB) is split between the work ring
  * (17 B per subproblem) and the resident slice frontiers.
  * nq_serve_submit: non-blocking; NQ_EINVAL for a malformed request, NQ_EFULL

@@ -62,21 +62,43 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
 
 }  // namespace
 
-// Serving: counts one retired entry of instance s; the lane that retires the
-// last one publishes the instance's total to host memory (value first, then
-// the generation flag, each as a system-scope store, so a host that sees the
-// flag also sees the value).
-__device__ __forceinline__ void publish_if_last(uint32_t* remaining, unsigned long long* totals,
-                                                const uint32_t* gen, unsigned long long* host_val,
-                                                unsigned long long* host_flag, uint32_t s) {
-    __threadfence();                                      // totals add before the count
-    const uint32_t before = atomicSub(&remaining[s], 1u);
-    if (before == 1u) {
-        __threadfence();
-        const unsigned long long t = atomicAdd(&totals[s], 0ull);
-        __hip_atomic_store(&host_val[s], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&host_flag[s], (unsigned long long)gen[s], __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_SYSTEM);
+// Serving: adds the entries that the wave's lanes retire at one scheduler
+// visit to their requests, with one atomic add to the total and one atomic
+// subtraction from the remaining count per request present among them (the
+// lanes that retire together mostly hold entries of one request, so a request
+// of F entries costs about F / 64 atomic pairs, not F on one address).  The
+// lane whose subtraction takes a request's remaining count to zero publishes
+// its total to host memory: value first, then the generation flag, each a
+// system-scope store, so a host that sees the flag also sees the value.  Every
+// lane of the wave calls it; `retiring` lanes pass their request slot `s` and
+// weighted count `val`.
+__device__ __forceinline__ void retire_to_requests(uint32_t* remaining, unsigned long long* totals,
+                                                   const uint32_t* gen,
+                                                   unsigned long long* host_val,
+                                                   unsigned long long* host_flag, bool retiring,
+                                                   uint32_t s, uint64_t val, uint32_t lane) {
+    uint64_t pend = __builtin_amdgcn_ballot_w64(retiring);
+    while (pend != 0) {
+        const int leader = __ffsll((unsigned long long)pend) - 1;
+        const uint32_t s0 = (uint32_t)__shfl((int)s, leader, 64);
+        const bool mine = retiring && s == s0;
+        const uint64_t grp = __builtin_amdgcn_ballot_w64(mine);
+        uint64_t add = mine ? val : 0u;
+        for (int off = 32; off > 0; off >>= 1) add += shfl_xor_u64(add, off);
+        if ((int)lane == leader) {
+            const uint32_t cnt = (uint32_t)__popcll(grp);
+            if (add != 0) atomicAdd(&totals[s0], (unsigned long long)add);
+            __threadfence();                              // the total before the count
+            const uint32_t before = atomicSub(&remaining[s0], cnt);
+            if (before == cnt) {
+                __threadfence();
+                const unsigned long long t = atomicAdd(&totals[s0], 0ull);
+                __hip_atomic_store(&host_val[s0], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&host_flag[s0], (unsigned long long)gen[s0], __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        pend &= ~grp;
     }
 }
 
@@ -293,6 +315,9 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         // ---- scheduler visit: flush counters, retire finished lanes, refill.
         sum64 += sum32; sum32 = 0;
         if (STATS) { steps64 += steps32; steps32 = 0; }
+        bool req_retire = false;          // serving: this lane retires an entry now
+        uint32_t req_slot = 0u;
+        uint64_t req_val = 0u;
         if (has_task && v == 0u) {
             const bool ok = sum64 != kCountInvalid;
             if (P.counts) P.counts[idx] = sum64;
@@ -304,9 +329,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 if (!P.inst) {
                     wtotal += w * sum64;
                 } else if (P.remaining) {
-                    // serving: the total must be complete before the request's
-                    // remaining count can reach zero
-                    atomicAdd(&P.totals[s], (unsigned long long)(w * sum64));
+                    req_val = w * sum64;          // serving: added per wave below
                 } else {
                     // batches: a lane's consecutive entries mostly belong to one
                     // instance; add to its total when the instance changes
@@ -318,10 +341,13 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                     acc_v += w * sum64;
                 }
             }
-            if (P.remaining && inst_ok)
-                publish_if_last(P.remaining, P.totals, P.inst_gen, P.host_val, P.host_flag, s);
+            req_retire = P.remaining && inst_ok;
+            req_slot = s;
             has_task = false;
         }
+        if (P.remaining)
+            retire_to_requests(P.remaining, P.totals, P.inst_gen, P.host_val, P.host_flag,
+                               req_retire, req_slot, req_val, lane);
         if (PERSISTENT && !exhausted) {
             // Idle lanes take, in rank order, the wave's unused claimed
             // entries [qlo, qhi) first, then a fresh block of at least

@@ -47,9 +47,10 @@ struct DfsParams {
     uint32_t refill_every;          // DFS steps between scheduler visits
     uint32_t reverse;               // persistent: claim entries from the last one down
     // Serving (all null / 0 otherwise).  Entries live in a ring: logical entry
-    // i is physical (base + i) mod wrap.  Every retired entry decrements
-    // remaining[inst]; the lane that takes it to zero publishes the instance's
-    // total to host-visible memory: host_val[inst] = total, then
+    // i is physical (base + i) mod wrap.  The entries of one instance that a
+    // wave retires together are added to totals[inst] and subtracted from
+    // remaining[inst] at once; the subtraction that takes it to zero publishes
+    // the instance's total to host-visible memory: host_val[inst] = total, then
     // host_flag[inst] = inst_gen[inst].
     uint64_t base;
     uint64_t wrap;

@@ -91,7 +91,12 @@ struct nq_server {
     uint64_t resident_bytes = 0;
     nq_opts launch{};
     uint32_t cu_count = 0;
-    nqi::LaunchCfg cfg{};
+    nqi::DeviceInfo devinfo{};
+    // Launch shape of an epoch whose deepest subproblem needs f stack frames
+    // (planned on first use): the LDS stack, and so the waves per CU, is sized
+    // for the requests in the epoch, not for the server's limit.
+    nqi::LaunchCfg cfg_by_frames[NQ_MAX_N + 1] = {};
+    bool cfg_ready[NQ_MAX_N + 1] = {};
 
     // device memory
     void* dev = nullptr;
@@ -237,6 +242,7 @@ int admit_and_launch(nq_server* s) {
     Epoch ep;
     const uint64_t epoch_start = s->ring_tail;
     std::vector<uint64_t> taken;
+    uint32_t frames = 0;                                  // deepest stack of the epoch
     struct Copy { const Resident* res; uint64_t src, pos, len; uint32_t slot; };
     std::vector<Copy> copies;
     while (!s->pending.empty() && !s->free_slots.empty()) {
@@ -276,6 +282,7 @@ int admit_and_launch(nq_server* s) {
         r.ring_len = F;
         r.entries = F;
         s->ring_tail += F;
+        frames = std::max(frames, frames_needed(r.rq.n, r.depth + res->rows));
         ep.inits.push_back({slot, r.rq.n, (uint32_t)F, r.gen});
         copies.push_back({res, src, r.ring_start, F, slot});
         r.state = ReqState::Admitted;
@@ -325,7 +332,7 @@ int admit_and_launch(nq_server* s) {
     P.totals = s->s_tot;
     P.head = s->heads + (s->epoch_no % kHeads);
     P.len = n_entries;
-    P.frames = s->max_frames;
+    P.frames = frames;
     P.refill_every = s->launch.refill_every ? s->launch.refill_every : 512u;
     P.idle_min = default_idle_min();
     P.reverse = 0;                                      // arrival order
@@ -335,7 +342,14 @@ int admit_and_launch(nq_server* s) {
     P.inst_gen = s->s_gen;
     P.host_val = s->d_val;
     P.host_flag = s->d_flag;
-    LaunchCfg cfg = s->cfg;
+    if (!s->cfg_ready[frames]) {
+        if ((rc = plan_launch(s->devinfo, NQ_MODE_PERSISTENT, s->launch.wg_size,
+                              s->launch.waves_per_cu, frames, 1, false, true,
+                              &s->cfg_by_frames[frames])) != NQ_OK)
+            return rc;
+        s->cfg_ready[frames] = true;
+    }
+    LaunchCfg cfg = s->cfg_by_frames[frames];
     const uint64_t waves = (n_entries + 63) / 64;
     const uint64_t per_wg = cfg.wg_size / 64u;
     cfg.grid = (uint32_t)std::min<uint64_t>(cfg.grid, (waves + per_wg - 1) / per_wg);
@@ -399,6 +413,10 @@ int serve_create(const nq_opts* opts, uint64_t hbm_budget, nq_server** out) {
     s->budget = hbm_budget ? hbm_budget : (8ull << 30);
     // Frames: requests whose subproblems need more are refused at submit.
     s->max_frames = (opts && opts->depth) ? opts->depth : 14u;
+    if (s->max_frames > NQ_MAX_N - 2) {                  // deeper than any board needs
+        delete s;
+        return NQ_EINVAL;
+    }
     // Half of the budget is the work ring, the other half resident frontiers.
     s->ring_cap = std::min<uint64_t>(1ull << 31,
                                      std::max<uint64_t>(1u << 16, (s->budget / 2) / kRingEntryBytes));
@@ -410,14 +428,16 @@ int serve_create(const nq_opts* opts, uint64_t hbm_budget, nq_server** out) {
         destroy_all(s);
         return rc;
     };
-    DeviceInfo dev;
-    int rc = device_info(&dev);
+    int rc = device_info(&s->devinfo);
     if (rc != NQ_OK) return fail(rc);
-    s->cu_count = (uint32_t)dev.cu_count;
-    if ((rc = plan_launch(dev, NQ_MODE_PERSISTENT, opts ? opts->wg_size : 0,
-                          opts ? opts->waves_per_cu : 0, s->max_frames, 1, false,
-                          true, &s->cfg)) != NQ_OK)
+    s->cu_count = (uint32_t)s->devinfo.cu_count;
+    // The largest epoch must fit: planned here so that a bad launch option is
+    // refused at creation.
+    if ((rc = plan_launch(s->devinfo, NQ_MODE_PERSISTENT, s->launch.wg_size,
+                          s->launch.waves_per_cu, s->max_frames, 1, false, true,
+                          &s->cfg_by_frames[s->max_frames])) != NQ_OK)
         return fail(rc);
+    s->cfg_ready[s->max_frames] = true;
     const uint64_t R = s->ring_cap, S = s->max_slots;
     const size_t o_ld = R * 4, o_rd = R * 8, o_inst = R * 12, o_w = R * 16;
     const size_t o_sn = (o_w + R + 255) / 256 * 256, o_rem = o_sn + S * 4, o_gen = o_rem + S * 4;
