@@ -56,26 +56,38 @@ def golden_nodes(n, k):
     return None
 
 
+KERNEL_FILES = ("paper_2511_12009_amd/csrc/nq_dfs.hip", "paper_2511_12009_amd/csrc/nq_internal.h",
+                "paper_2511_12009_amd/build.py")
+
+
+def kernel_digest():
+    """sha256 over the DFS kernel's source, its parameter header and the build
+    script (compiler flags), in that order."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_FILES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def profiled_traffic(n, k):
     """HBM bytes per launch of the default persistent DFS kernel at (n, k) from
     the committed counter summary (profiles/), or None when there is none, when
-    the DFS kernel source has changed since the counters were taken (the summary
-    records its sha256), or when an environment override selects another
-    kernel form or scheduler setting."""
+    the kernel's source, header or build flags have changed since the counters
+    were taken (the summary records their kernel_digest), or when an environment
+    override selects another kernel form or scheduler setting."""
     if any(os.environ.get(v) for v in ("NQ_DFS_LOOP", "NQ_IDLE_MIN", "NQ_CLAIM")):
         return None
     import glob
-    import hashlib
-    src = os.path.join(ROOT, "paper_2511_12009_amd", "csrc", "nq_dfs.hip")
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
+    digest = kernel_digest()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as f:
             for line in f:
                 if not line.startswith("counters:"):
                     continue
                 kv = dict(x.split("=", 1) for x in line.split()[1:] if "=" in x)
-                if (kv.get("source_sha256") == digest and int(kv.get("n", -1)) == n and int(kv.get("depth", -1)) == k):
+                if (kv.get("kernel_sha256") == digest and int(kv.get("n", -1)) == n and int(kv.get("depth", -1)) == k):
                     return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
     return None
 

@@ -240,8 +240,11 @@ __device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, u
 
 // LOOP selects the inner-loop form: 0 = plain C++ (the compiler places the
 // exec masks), 1 = hand-placed exec masks (the default), 2 = as 1 with the
-// untried set kept negated so that two lane masks come from carries.
-template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP>
+// untried set kept negated so that two lane masks come from carries.  SERVE
+// (persistent launches of the serving loop, P.remaining set) compiles in the
+// per-request retirement; it is a template flag so that the scheduler visit
+// of every other launch carries none of its code.
+template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP, bool SERVE>
 __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     extern __shared__ uint4 lds_stack[];
     const int32_t lds = (int32_t)(uint32_t)(uintptr_t)(lds_frame*)lds_stack;
@@ -328,7 +331,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 const uint64_t w = P.weight ? (uint64_t)P.weight[idx] : 1u;
                 if (!P.inst) {
                     wtotal += w * sum64;
-                } else if (P.remaining) {
+                } else if (SERVE) {
                     req_val = w * sum64;          // serving: added per wave below
                 } else {
                     // batches: a lane's consecutive entries mostly belong to one
@@ -341,11 +344,11 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                     acc_v += w * sum64;
                 }
             }
-            req_retire = P.remaining && inst_ok;
+            req_retire = SERVE && inst_ok;
             req_slot = s;
             has_task = false;
         }
-        if (P.remaining)
+        if (SERVE)
             retire_to_requests(P.remaining, P.totals, P.inst_gen, P.host_val, P.host_flag,
                                req_retire, req_slot, req_val, lane);
         if (PERSISTENT && !exhausted) {
@@ -503,7 +506,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         c = st.x; l = st.y; r = st.z; v = st.w;
     }
 
-    if (P.totals && P.inst && !P.remaining && acc_v)
+    if (!SERVE && P.totals && P.inst && acc_v)
         atomicAdd(&P.totals[acc_s], (unsigned long long)acc_v);
     if (P.totals && !P.inst) {
         for (int off = 32; off > 0; off >>= 1) wtotal += shfl_xor_u64(wtotal, off);
@@ -534,14 +537,17 @@ __global__ void nq_fill_u32_kernel(uint32_t* dst, uint32_t value, uint64_t count
     if (i < count) dst[i] = value;
 }
 
-template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP>
+template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP, bool SERVE = false>
 static const void* kernel_ptr() {
-    return reinterpret_cast<const void*>(&nq_dfs_kernel<PERSISTENT, STATS, LEAFCTR, LOOP>);
+    return reinterpret_cast<const void*>(&nq_dfs_kernel<PERSISTENT, STATS, LEAFCTR, LOOP, SERVE>);
 }
 
+// The kernel for a launch shape; serving launches exist only as persistent,
+// row-counter, no-statistics kernels (nullptr otherwise).
 template <int LOOP>
-static const void* select_kernel_loop(uint32_t mode, bool stats, bool leafctr) {
+static const void* select_kernel_loop(uint32_t mode, bool stats, bool leafctr, bool serve) {
     const bool pers = mode == NQ_MODE_PERSISTENT;
+    if (serve) return (pers && !stats && leafctr) ? kernel_ptr<true, false, true, LOOP, true>() : nullptr;
     if (pers) {
         if (stats)
             return leafctr ? kernel_ptr<true, true, true, LOOP>() : kernel_ptr<true, true, false, LOOP>();
@@ -592,11 +598,11 @@ uint32_t default_idle_min() {
     return v;
 }
 
-static const void* select_kernel(uint32_t mode, bool stats, bool leafctr) {
+static const void* select_kernel(uint32_t mode, bool stats, bool leafctr, bool serve) {
     switch (loop_form()) {
-        case 1: return select_kernel_loop<1>(mode, stats, leafctr);
-        case 2: return select_kernel_loop<2>(mode, stats, leafctr);
-        default: return select_kernel_loop<0>(mode, stats, leafctr);
+        case 1: return select_kernel_loop<1>(mode, stats, leafctr, serve);
+        case 2: return select_kernel_loop<2>(mode, stats, leafctr, serve);
+        default: return select_kernel_loop<0>(mode, stats, leafctr, serve);
     }
 }
 
@@ -631,7 +637,8 @@ int device_info(DeviceInfo* out) {
 }
 
 int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t waves_per_cu,
-                uint32_t frames, uint64_t len, bool stats, bool leafctr, LaunchCfg* cfg) {
+                uint32_t frames, uint64_t len, bool stats, bool leafctr, LaunchCfg* cfg,
+                bool serve) {
     if (mode != NQ_MODE_PLAIN && mode != NQ_MODE_PERSISTENT) return NQ_EINVAL;
     if (wg_size == 0) {
         // Plain: up to 4 waves per workgroup, as many as the LDS stacks allow.
@@ -649,6 +656,9 @@ int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t
     cfg->lds_bytes = (uint32_t)lds;
     cfg->stats = stats;
     cfg->leafctr = leafctr;
+    cfg->serve = serve;
+    const void* fn = select_kernel(mode, stats, leafctr, serve);
+    if (!fn) return NQ_EINVAL;
     if (mode == NQ_MODE_PLAIN) {
         const uint64_t g = (len + wg_size - 1) / wg_size;
         if (g > 0x7fffffffull) return NQ_EINVAL;
@@ -657,7 +667,7 @@ int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t
     }
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, select_kernel(mode, stats, cfg->leafctr), (int)wg_size, (size_t)lds);
+        &per_cu, fn, (int)wg_size, (size_t)lds);
     if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
     if (per_cu < 1) return NQ_EINVAL;
     if (waves_per_cu) {
@@ -710,7 +720,10 @@ int launch_dfs(const LaunchCfg& cfg, const DfsParams& P, void* stream) {
         if (rc != NQ_OK) return rc;
     }
     const dim3 grid(cfg.grid), block(cfg.wg_size);
-    const void* fn = select_kernel(cfg.mode, cfg.stats, cfg.leafctr);
+    // A serving launch (P.remaining set) needs a launch shape planned for it.
+    if (cfg.serve != (P.remaining != nullptr)) return NQ_EINVAL;
+    const void* fn = select_kernel(cfg.mode, cfg.stats, cfg.leafctr, cfg.serve);
+    if (!fn) return NQ_EINVAL;
     void* args[] = {const_cast<DfsParams*>(&P)};
     hipError_t le = hipLaunchKernel(fn, grid, block, args, cfg.lds_bytes, s);
     if (le != hipSuccess) { set_hip_error(le); return NQ_EDEVICE; }

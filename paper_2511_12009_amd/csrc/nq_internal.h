@@ -86,6 +86,7 @@ struct LaunchCfg {
     uint32_t lds_bytes;     // dynamic LDS per workgroup
     bool stats;             // count DFS steps per entry
     bool leafctr;           // row counter in the high bits of cols (see the kernel)
+    bool serve;             // serving epoch: per-request retirement (P.remaining set)
 };
 
 // True when the row-counter form of the leaf test holds for every entry of an
@@ -108,9 +109,11 @@ struct DeviceInfo {
 
 int device_info(DeviceInfo* out);
 
-// Fills `cfg` for `len` entries needing `frames` frames per lane.
+// Fills `cfg` for `len` entries needing `frames` frames per lane; `serve`
+// plans a serving epoch (persistent, leafctr, no statistics only).
 int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t waves_per_cu,
-                uint32_t frames, uint64_t len, bool stats, bool leafctr, LaunchCfg* cfg);
+                uint32_t frames, uint64_t len, bool stats, bool leafctr, LaunchCfg* cfg,
+                bool serve = false);
 
 // Enqueues the DFS kernel (and, for the persistent mode, the zeroing of
 // *P.head) on `stream`.  Returns NQ_OK or NQ_EDEVICE.

@@ -345,7 +345,7 @@ int admit_and_launch(nq_server* s) {
     if (!s->cfg_ready[frames]) {
         if ((rc = plan_launch(s->devinfo, NQ_MODE_PERSISTENT, s->launch.wg_size,
                               s->launch.waves_per_cu, frames, 1, false, true,
-                              &s->cfg_by_frames[frames])) != NQ_OK)
+                              &s->cfg_by_frames[frames], true)) != NQ_OK)
             return rc;
         s->cfg_ready[frames] = true;
     }
@@ -435,7 +435,7 @@ int serve_create(const nq_opts* opts, uint64_t hbm_budget, nq_server** out) {
     // refused at creation.
     if ((rc = plan_launch(s->devinfo, NQ_MODE_PERSISTENT, s->launch.wg_size,
                           s->launch.waves_per_cu, s->max_frames, 1, false, true,
-                          &s->cfg_by_frames[s->max_frames])) != NQ_OK)
+                          &s->cfg_by_frames[s->max_frames], true)) != NQ_OK)
         return fail(rc);
     s->cfg_ready[s->max_frames] = true;
     const uint64_t R = s->ring_cap, S = s->max_slots;

@@ -91,3 +91,29 @@ def test_n21_slices_sum_to_q21(known_counts):
             if i % 200 == 0:
                 _say("slices done", i)
         assert total == known_counts[21]
+
+
+def test_many_tiny_slices_share_waves():
+    """Hundreds of 1..7-entry slices of the N=13 depth-4 frontier submitted at
+    once: one wave retires entries of many requests at the same visit, and each
+    request's total and completion must still be its own (oracle per slice)."""
+    nq = _nq()
+    pre, w = oracle.frontier(13, 4)
+    F = len(pre)
+    assert nq.frontier_size(13, 4) == F and F < 2 ** 16       # kept unexpanded
+    ref, _ = oracle.count_prefixes(13, pre, threads=8)
+    wref = ref * w.astype(np.uint64)
+    rng = np.random.default_rng(20251112)
+    spans, s = [], 0
+    while s < F:
+        ln = int(rng.integers(1, 8))
+        spans.append((s, min(ln, F - s)))
+        s += ln
+    with nq.Server() as srv:
+        _say("tiny slices", len(spans))
+        tickets = [srv.submit_slice(13, 4, a, ln) for a, ln in spans]
+        for (a, ln), t in zip(spans, tickets):
+            r = srv.wait(t, timeout_s=120)
+            assert r["status"] == 0
+            assert r["entries"] == ln
+            assert r["count"] == int(wref[a:a + ln].sum()), (a, ln)
