@@ -15,8 +15,10 @@ unless --depth is given.  Frontiers deeper than 8 rows are built on the host at
 depth k-2 and expanded on the device (nq_expand) before the timed region.  Printed: one JSON line with the metric, the "plain"
 form (one launch per row-0 column over the same frontier), the end-to-end
 nq_count wall time, the int-ALU roofline of the DFS kernel, the ragged
-256-instance batch (one graph replay), the serving loop at a few request
-rates (p50/p99 latency, throughput) and the oracle timed on the host cores.
+256-instance batch (one graph replay), one GPU's share of an N=21 count
+dealt round-robin over 8 GPUs (all 8 shares run in turn; their totals must add
+up to Q(21)), the serving loop at a few request rates (p50/p99 latency,
+throughput) and the oracle timed on the host cores.
 """
 import argparse
 import json
@@ -120,6 +122,36 @@ def bench_batch(nq, known):
     return {"instances": len(ns), "subproblems": entries, "replay_ms": ms,
             "build_ms": build_ms, "exact": ok,
             "form": "one persistent launch over every instance's frontier, HIP graph replay"}
+
+
+def bench_shards(nq, torch, known, shares=8, n=21, k=6, deepen=3):
+    """One GPU's share of a count sharded over `shares` GPUs: the N=21 depth-6
+    frontier dealt round-robin, each share deepened on the device and searched
+    by one persistent launch.  Per-share kernel times; the share totals must
+    add up to Q(21)."""
+    dev = torch.device("cuda:0")
+    cols, ld, rd, w = nq.frontier(n, k)
+    ms, entries, grand = [], [], 0
+    for r in range(shares):
+        t = [torch.from_numpy(np.ascontiguousarray(x[r::shares]).view(np.int32)).to(dev)
+             for x in (cols, ld, rd)]
+        tw = torch.from_numpy(np.ascontiguousarray(w[r::shares])).to(dev)
+        c, l, rr, ww = nq.expand(n, deepen, t[0], t[1], t[2], tw)
+        tot = torch.zeros(1, dtype=torch.int64, device=dev)
+        _, _, m = nq.count_subproblems(n, c, l, rr, weight=ww, counts=False, total=tot,
+                                       depth=k + deepen, timing=True)
+        grand += int(tot.item())
+        ms.append(m)
+        entries.append(c.numel())
+        del c, l, rr, ww, t, tw
+        print(f"[bench] share {r}/{shares}: {entries[-1]} subproblems, {m:.1f} ms",
+              file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    if grand != known[n]:
+        raise SystemExit(f"bench.py: shares of N={n} add up to {grand}, not {known[n]}")
+    return {"n": n, "frontier_depth": k, "shares": shares, "search_depth": k + deepen,
+            "split": "round-robin over the frontier", "share_ms": ms, "share_subproblems": entries,
+            "max_over_mean": max(ms) / (sum(ms) / len(ms)), "sum_exact": True}
 
 
 def bench_serving(nq, known, rates, seconds):
@@ -251,6 +283,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-shards", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="counter runs: one 256 MiB device copy (calibrates the HBM byte "
                          "counters), then one persistent DFS launch at --depth; no JSON line")
@@ -385,6 +418,9 @@ def main():
     if not args.no_batch:
         print("[bench] ragged batch (256 instances)", file=sys.stderr, flush=True)
         out["batch"] = bench_batch(nq, known)
+    if not args.no_shards:
+        print("[bench] one GPU's share of N=21 over 8 GPUs", file=sys.stderr, flush=True)
+        out["shard"] = bench_shards(nq, torch, known)
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
     if rates:
         print("[bench] serving", file=sys.stderr, flush=True)
