@@ -231,6 +231,23 @@ int nq_autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_
                 nq_tuned* out);
 
 /*
+ * nq_set_loop_form -- choose the DFS inner-loop form of the launches planned
+ * from now on, to measure the forms against each other; all give the same
+ * counts.  form: -1 = the default (1, or NQ_DFS_LOOP from the environment),
+ * 0 = compiler-scheduled C++ step, 1 = hand-placed exec masks (default),
+ * 2 = form 1 with the untried set negated, 4 = the frame being expanded read
+ * from the LDS stack at every step with its untried set written back
+ * (Algorithm 2 as printed in Section 2, with the last-row step of Algorithm 3,
+ * Section 3.2.3), 5 = form 0 without the last-row step (Algorithm 2 alone).
+ * Forms 4 and 5 need one LDS frame more per lane.  *previous (nullable)
+ * receives the form in use.  NQ_EINVAL for any other form (3 included).
+ * Process-wide; a launch keeps the form it was planned with (a server's epochs
+ * or a batch plan made before the call keep theirs), so set it while no other
+ * thread plans launches.  Touches no device.
+ */
+int nq_set_loop_form(int form, int* previous);
+
+/*
  * Reusable batch plan: nq_count_batch split into set-up and replay.
  *
  * nq_batch_create builds and uploads the concatenated frontiers of ninst >= 1

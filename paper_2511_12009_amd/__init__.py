@@ -31,6 +31,7 @@ from ._native import (  # noqa: F401
     frontier,
     frontier_runs,
     frontier_size,
+    set_loop_form,
     lib,
     library_path,
 )

@@ -126,6 +126,8 @@ def lib():
         L.nq_batch_entries.restype = u64
         L.nq_batch_destroy.argtypes = [vp]
         L.nq_batch_destroy.restype = ct.c_int
+        L.nq_set_loop_form.argtypes = [ct.c_int, ct.POINTER(ct.c_int)]
+        L.nq_set_loop_form.restype = ct.c_int
         _LIB = L
     return _LIB
 
@@ -282,6 +284,14 @@ def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None
         None if counts is False else counts.data_ptr(), total.data_ptr(), ct.byref(o)),
         "nq_count_subproblems")
     return (counts, total, ms.value) if timing else (counts, total)
+
+
+def set_loop_form(form: int) -> int:
+    """nq_set_loop_form: the DFS inner-loop form of launches planned from now on
+    (-1 = default; 0, 1, 2, 4 or 5); returns the form that was in use."""
+    prev = ct.c_int(0)
+    _check(lib().nq_set_loop_form(int(form), ct.byref(prev)), "nq_set_loop_form")
+    return prev.value
 
 
 def count_batch(ns, depths=None, mode="persistent", wg_size: int = 0, waves_per_cu: int = 0,

@@ -308,6 +308,8 @@ extern "C" const char* nq_strerror(int status) {
 
 extern "C" int nq_last_hip_error(void) { return g_last_hip_error; }
 
+extern "C" int nq_set_loop_form(int form, int* previous) { return set_loop_form(form, previous); }
+
 extern "C" int nq_expand(uint32_t n, uint32_t rows, const uint32_t* d_cols, const uint32_t* d_ld,
                          const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len,
                          uint32_t* d_ocols, uint32_t* d_old, uint32_t* d_ord, uint8_t* d_oweight,

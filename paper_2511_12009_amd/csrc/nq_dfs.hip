@@ -32,6 +32,7 @@
 // first shortens the tail of the launch.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdlib>
 
 #include "nq_internal.h"
@@ -40,6 +41,9 @@ namespace nqi {
 
 // Default inner-loop form of the DFS kernels (see nq_dfs_kernel).
 constexpr int kDefaultLoop = 1;
+constexpr int kLoopForms = 6;          // forms 0..5 (3 is not used)
+// LDS frames per lane that a form needs beyond N - 2 - placed.
+constexpr uint32_t kFormExtraFrames[kLoopForms] = {0, 0, 0, 0, 1, 1};
 
 namespace {
 
@@ -127,6 +131,11 @@ typedef __attribute__((address_space(3))) u32x4 lds_frame;
 // A frame addressed by its absolute LDS byte address.
 __device__ __forceinline__ lds_frame* frame_at(int32_t addr) {
     return (lds_frame*)(uintptr_t)(uint32_t)addr;
+}
+
+// One 32-bit word of the LDS stack by its absolute byte address.
+__device__ __forceinline__ __attribute__((address_space(3))) uint32_t* word_at(int32_t addr) {
+    return (__attribute__((address_space(3))) uint32_t*)(uintptr_t)(uint32_t)addr;
 }
 
 // Exec-masked helpers for the hand-scheduled loops (forms 1 and 2).  Each block
@@ -240,7 +249,13 @@ __device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, u
 
 // LOOP selects the inner-loop form: 0 = plain C++ (the compiler places the
 // exec masks), 1 = hand-placed exec masks (the default), 2 = as 1 with the
-// untried set kept negated so that two lane masks come from carries.  SERVE
+// untried set kept negated so that two lane masks come from carries.  Two
+// more forms exist to measure the paper's own design choices: 4 keeps the
+// frame being expanded in the LDS stack too (read every step, its untried set
+// written back: Algorithm 2 as the paper prints it, with the last-row step of
+// Algorithm 3) and 5 is form 0 without the last-row step (the last row is
+// searched like any other).  Both need one LDS frame more per lane, which the
+// launcher adds to P.frames (kFormExtraFrames).  SERVE
 // (persistent launches of the serving loop, P.remaining set) compiles in the
 // per-request retirement; it is a template flag so that the scheduler visit
 // of every other launch carries none of its code.
@@ -299,7 +314,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
             sum64 = kCountInvalid;        // instance id or board size out of range
         } else if (placed >= nm1) {
             sum32 = (placed == n) ? 1u : __popc(avail);
-        } else if (n - 2u - placed > P.frames ||
+        } else if (n - 2u - placed > P.frames - kFormExtraFrames[LOOP] ||
                    (LEAFCTR && nm1 - placed > (1u << (31u - n)))) {
             sum64 = kCountInvalid;        // does not fit this launch's stack or counter
         } else if (avail != 0u) {
@@ -467,6 +482,68 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
             chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
             if (chunks == 0u || chunk_done(st.w)) break;
         }
+        } else if (LOOP == 4) {
+        // The paper's loop as printed: the frame being expanded is the top
+        // of the LDS stack, read at every step, with its untried set written
+        // back; a child is pushed on top of it; an exhausted frame is popped
+        // at the next step.  Registers carry no frame between scheduler
+        // visits: a new entry is pushed when the lane enters, and the lane's
+        // `v` is 1 while its stack holds a frame.
+        if (st.w != 0u && top == floor) {
+            top += 1024;
+            *frame_at(top) = st;
+        }
+        for (uint32_t it = 0; it < P.refill_every; ++it) {
+            const u32x4 f = *frame_at(top);
+            const uint32_t p = f.w & (0u - f.w);
+            if (p == 0u) {                            // exhausted (or the sentinel)
+                top = max(top - 1024, floor);
+            } else {
+                *(word_at(top) + 3) = f.w ^ p;
+                const uint32_t nc = LEAFCTR ? f.x + p + step_k : (f.x | p);
+                const uint32_t nl = (f.y + p) << 1;
+                const uint32_t nr = (f.z + p) >> 1;
+                const uint32_t a = last & ~(nc | nl | nr);
+                if (STATS) steps32 += 1u;
+                const bool leaf = LEAFCTR ? (int32_t)nc < 0 : __popc(nc) == nm1;
+                if (leaf) {
+                    sum32 += (a != 0u) ? 1u : 0u;
+                } else if (a != 0u) {
+                    top += 1024;
+                    *frame_at(top) = u32x4{nc, nl, nr, a};
+                }
+            }
+        }
+        st.w = (top != floor) ? 1u : 0u;
+        } else if (LOOP == 5) {
+        // Form 0 without the last-row step: a queen placed in row N-2 is a
+        // frame like any other, and a solution is counted when the last row
+        // gets its queen (the board is full).  Placements in the last row are
+        // not DFS nodes (they are the solutions), so STATS leaves them out.
+        for (uint32_t it = 0; it < P.refill_every; ++it) {
+            const uint32_t p = st.w & (0u - st.w);
+            st.w ^= p;
+            const uint32_t nc = LEAFCTR ? st.x + p + step_k : (st.x | p);
+            const uint32_t nl = (st.y + p) << 1;
+            const uint32_t nr = (st.z + p) >> 1;
+            const uint32_t a = last & ~(nc | nl | nr);
+            const bool full = p != 0u && (nc & last) == last;
+            if (STATS) steps32 += (p != 0u && !full);
+            sum32 += full ? 1u : 0u;
+            const bool desc = a != 0u;                // never on a full board
+            if (desc && st.w != 0u) {
+                top += 1024;
+                *frame_at(top) = st;
+            }
+            st.x = desc ? nc : st.x;
+            st.y = desc ? nl : st.y;
+            st.z = desc ? nr : st.z;
+            st.w = desc ? a : st.w;
+            if (st.w == 0u) {
+                st = *frame_at(top);
+                top = max(top - 1024, floor);
+            }
+        }
         } else {
         // Form 2.  The frame keeps the untried set negated, w = -avail (mod
         // 2^32), so that two lane masks come out of carries instead of
@@ -558,15 +635,27 @@ static const void* select_kernel_loop(uint32_t mode, bool stats, bool leafctr, b
     return leafctr ? kernel_ptr<false, false, true, LOOP>() : kernel_ptr<false, false, false, LOOP>();
 }
 
-// Inner-loop form: NQ_DFS_LOOP=0..2 in the environment overrides the default
-// (for measurements).
+// Inner-loop form of the launches planned from now on: NQ_DFS_LOOP=0..5 in the
+// environment overrides the default, and set_loop_form (nq_set_loop_form) sets
+// it at run time (for measurements of the forms against each other).
+static std::atomic<int> g_loop_form{-1};
+
 static int loop_form() {
-    static const int form = [] {
-        const char* e = std::getenv("NQ_DFS_LOOP");
-        if (e && e[0] >= '0' && e[0] <= '2' && e[1] == 0) return e[0] - '0';
-        return kDefaultLoop;
-    }();
-    return form;
+    int f = g_loop_form.load(std::memory_order_relaxed);
+    if (f >= 0) return f;
+    const char* e = std::getenv("NQ_DFS_LOOP");
+    f = kDefaultLoop;
+    if (e && e[0] >= '0' && e[0] <= '5' && e[0] != '3' && e[1] == 0) f = e[0] - '0';
+    int expect = -1;
+    g_loop_form.compare_exchange_strong(expect, f);
+    return g_loop_form.load(std::memory_order_relaxed);
+}
+
+int set_loop_form(int form, int* previous) {
+    if (form < -1 || form >= kLoopForms || form == 3) return NQ_EINVAL;
+    if (previous) *previous = loop_form();
+    g_loop_form.store(form, std::memory_order_relaxed);   // -1: read again on next use
+    return NQ_OK;
 }
 
 uint32_t default_claim(uint64_t len, const LaunchCfg& cfg) {
@@ -598,11 +687,14 @@ uint32_t default_idle_min() {
     return v;
 }
 
-static const void* select_kernel(uint32_t mode, bool stats, bool leafctr, bool serve) {
-    switch (loop_form()) {
+static const void* select_kernel(int form, uint32_t mode, bool stats, bool leafctr, bool serve) {
+    switch (form) {
+        case 0: return select_kernel_loop<0>(mode, stats, leafctr, serve);
         case 1: return select_kernel_loop<1>(mode, stats, leafctr, serve);
         case 2: return select_kernel_loop<2>(mode, stats, leafctr, serve);
-        default: return select_kernel_loop<0>(mode, stats, leafctr, serve);
+        case 4: return select_kernel_loop<4>(mode, stats, leafctr, serve);
+        case 5: return select_kernel_loop<5>(mode, stats, leafctr, serve);
+        default: return nullptr;
     }
 }
 
@@ -640,6 +732,8 @@ int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t
                 uint32_t frames, uint64_t len, bool stats, bool leafctr, LaunchCfg* cfg,
                 bool serve) {
     if (mode != NQ_MODE_PLAIN && mode != NQ_MODE_PERSISTENT) return NQ_EINVAL;
+    const int form = loop_form();
+    frames += kFormExtraFrames[form];
     if (wg_size == 0) {
         // Plain: up to 4 waves per workgroup, as many as the LDS stacks allow.
         const uint64_t per_wave = 64ull * (frames + 1u) * 16u;
@@ -657,7 +751,8 @@ int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t
     cfg->stats = stats;
     cfg->leafctr = leafctr;
     cfg->serve = serve;
-    const void* fn = select_kernel(mode, stats, leafctr, serve);
+    cfg->form = form;
+    const void* fn = select_kernel(form, mode, stats, leafctr, serve);
     if (!fn) return NQ_EINVAL;
     if (mode == NQ_MODE_PLAIN) {
         const uint64_t g = (len + wg_size - 1) / wg_size;
@@ -715,16 +810,21 @@ int launch_slot_init(const SlotInit* recs, uint32_t count, uint32_t* inst_n, uin
 int launch_dfs(const LaunchCfg& cfg, const DfsParams& P, void* stream) {
     if (P.len == 0 || cfg.grid == 0) return NQ_OK;
     hipStream_t s = (hipStream_t)stream;
+    // A serving launch (P.remaining set) needs a launch shape planned for it,
+    // and the LDS planned must hold the stacks of the form it was planned for.
+    if (cfg.serve != (P.remaining != nullptr)) return NQ_EINVAL;
+    if (cfg.form < 0 || cfg.form >= kLoopForms) return NQ_EINVAL;
+    const void* fn = select_kernel(cfg.form, cfg.mode, cfg.stats, cfg.leafctr, cfg.serve);
+    if (!fn) return NQ_EINVAL;
+    DfsParams Q = P;
+    Q.frames += kFormExtraFrames[cfg.form];
+    if ((uint64_t)cfg.lds_bytes < (uint64_t)cfg.wg_size * (Q.frames + 1u) * 16u) return NQ_EINVAL;
     if (cfg.mode == NQ_MODE_PERSISTENT) {
         int rc = launch_zero_u64(P.head, 1, stream);
         if (rc != NQ_OK) return rc;
     }
     const dim3 grid(cfg.grid), block(cfg.wg_size);
-    // A serving launch (P.remaining set) needs a launch shape planned for it.
-    if (cfg.serve != (P.remaining != nullptr)) return NQ_EINVAL;
-    const void* fn = select_kernel(cfg.mode, cfg.stats, cfg.leafctr, cfg.serve);
-    if (!fn) return NQ_EINVAL;
-    void* args[] = {const_cast<DfsParams*>(&P)};
+    void* args[] = {&Q};
     hipError_t le = hipLaunchKernel(fn, grid, block, args, cfg.lds_bytes, s);
     if (le != hipSuccess) { set_hip_error(le); return NQ_EDEVICE; }
     hipError_t e = hipGetLastError();

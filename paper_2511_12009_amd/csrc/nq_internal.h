@@ -87,7 +87,13 @@ struct LaunchCfg {
     bool stats;             // count DFS steps per entry
     bool leafctr;           // row counter in the high bits of cols (see the kernel)
     bool serve;             // serving epoch: per-request retirement (P.remaining set)
+    int form;               // inner-loop form the launch was planned for
 };
+
+// Sets the inner-loop form of the DFS launches planned from now on (-1 = the
+// default); *previous (nullable) receives the form in use.  NQ_EINVAL for an
+// unknown form.
+int set_loop_form(int form, int* previous);
 
 // True when the row-counter form of the leaf test holds for every entry of an
 // n board with at least `min_placed` queens placed: the counter needs

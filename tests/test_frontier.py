@@ -116,3 +116,20 @@ def test_frontier_runs_cover_row0_columns():
         pre, _ = oracle.frontier(n, k)
         starts = [i for i in range(len(pre)) if i == 0 or pre[i][0] != pre[i - 1][0]]
         assert runs == starts + [len(pre)]
+
+
+def test_loop_form_setter_validates_and_restores():
+    """nq_set_loop_form touches no device: unknown forms are refused, and -1
+    restores the default."""
+    import paper_2511_12009_amd as nq
+    prev = nq.set_loop_form(-1)
+    try:
+        for bad in (-2, 3, 6, 100):
+            with pytest.raises(nq.NQError):
+                nq.set_loop_form(bad)
+        assert nq.set_loop_form(4) == 1
+        assert nq.set_loop_form(5) == 4
+        assert nq.set_loop_form(-1) == 5
+        assert nq.set_loop_form(-1) == 1
+    finally:
+        nq.set_loop_form(prev)
