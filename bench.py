@@ -239,6 +239,59 @@ def profile_run(nq, torch, k, args):
           file=sys.stderr, flush=True)
 
 
+def run_ablation(nq, torch):
+    """The paper's design choices measured on this GPU (N=20, one launch over the
+    resident frontier, kernel time from HIP events; every run checked against
+    Q(20)): the pre-placement depth (its Table 3), the block size of the plain
+    launch (its Table 4), the frame kept in registers or re-read from the LDS
+    stack every step, and the last-row step on or off (its Table 5)."""
+    dev = torch.device("cuda:0")
+    out = {"n": N, "depth_sweep": [], "plain_block_sweep": [], "forms": []}
+
+    def once(t, k, **kw):
+        total = torch.zeros(1, dtype=torch.int64, device=dev)
+        _, _, ms = nq.count_subproblems(N, t[0], t[1], t[2], weight=t[3], counts=False,
+                                        total=total, depth=k, timing=True, **kw)
+        if int(total.item()) != EXPECT:
+            raise SystemExit(f"bench.py: ablation total {int(total.item())} != {EXPECT} ({kw})")
+        return ms
+
+    for k in range(5, 11):
+        t = device_frontier(nq, torch, dev, k)
+        ms = min(once(t, k), once(t, k))
+        nodes = golden_nodes(N, k)
+        out["depth_sweep"].append({"depth": k, "subproblems": t[0].numel(), "kernel_ms": ms,
+                                   "nodes_per_s": nodes / (ms / 1e3) if nodes else None})
+        print(f"[bench] ablation depth {k}: {ms:.1f} ms", file=sys.stderr, flush=True)
+        if k == 6:
+            for wg in (64, 128, 256, 512, 1024):
+                try:
+                    pm = once(t, k, mode="plain", wg_size=wg)
+                except nq.NQError as e:               # stacks exceed the LDS of a workgroup
+                    pm = None
+                    print(f"[bench] ablation plain k=6 wg {wg}: {e}", file=sys.stderr, flush=True)
+                out["plain_block_sweep"].append({"depth": k, "wg_size": wg, "kernel_ms": pm})
+                if pm is not None:
+                    print(f"[bench] ablation plain k=6 wg {wg}: {pm:.1f} ms", file=sys.stderr,
+                          flush=True)
+        if k == 9:
+            names = {0: "registers, compiler-scheduled step", 1: "registers, hand-placed exec masks",
+                     2: "registers, negated untried set", 4: "frame re-read from LDS every step",
+                     5: "registers, no last-row step"}
+            for form in (1, 0, 2, 4, 5):
+                nq.set_loop_form(form)
+                try:
+                    fm = min(once(t, k), once(t, k))
+                finally:
+                    nq.set_loop_form(-1)
+                out["forms"].append({"form": form, "what": names[form], "depth": k,
+                                     "kernel_ms": fm})
+                print(f"[bench] ablation form {form}: {fm:.1f} ms", file=sys.stderr, flush=True)
+        del t
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(k, budget_s):
     """The oracle on a seeded sample of the N=20 frontier (depth min(k, 8), so
     that the prefix list stays small), all host cores."""
@@ -284,6 +337,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-shards", action="store_true")
+    ap.add_argument("--ablation", action="store_true",
+                    help="measure the paper's design choices (depth, plain block size, loop "
+                         "forms) at N=20 and print them as one JSON line instead")
     ap.add_argument("--profile", action="store_true",
                     help="counter runs: one 256 MiB device copy (calibrates the HBM byte "
                          "counters), then one persistent DFS launch at --depth; no JSON line")
@@ -299,6 +355,9 @@ def main():
 
     if args.profile:
         profile_run(nq, torch, args.depth or 8, args)
+        return
+    if args.ablation:
+        print(json.dumps({"ablation": run_ablation(nq, torch)}), flush=True)
         return
 
     tuned = None
