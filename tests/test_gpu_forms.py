@@ -53,7 +53,7 @@ def test_small_boards(nq_form, known_counts):
     for mode in ("plain", "persistent"):
         _say("form", form, "small boards", mode)
         for n in range(1, 11):
-            for k in sorted({1, 2, n // 2, n - 1, n} - {0}):
+            for k in sorted(k for k in {1, 2, n // 2, n - 1, n} if 1 <= k <= n):
                 assert nq.count(n, depth=k, mode=mode) == known_counts[n], (form, n, k, mode)
 
 
