@@ -75,7 +75,7 @@ def test_per_subproblem_and_nodes(nq_form):
 def test_random_prefixes_with_dead_entries(nq_form):
     nq, form = nq_form
     rng = np.random.default_rng(2512)
-    for n in (5, 11, 16):
+    for n in (5, 11, 13):
         for k in sorted({1, 2, n // 2, n - 1, n}):
             pre_all, _ = oracle.frontier(n, k)
             if len(pre_all) == 0:
