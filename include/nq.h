@@ -206,6 +206,34 @@ int nq_count_batch(uint32_t ninst, const uint32_t* ns, const uint32_t* depths,
                    const nq_opts* opts, uint64_t* out_totals);
 
 /*
+ * nq_count_resumable -- Q(n) as a sequence of chunks whose progress is kept in
+ * a file, so that a long count that stops (a lost job, a time limit) resumes
+ * where it stopped instead of starting over.  The paper runs N = 27 for months
+ * and names fault tolerance as future work (Section 6); subproblems are
+ * independent (Section 1), so a chunk's weighted count never changes and can
+ * be recorded once it is done.
+ *
+ * The host frontier of depth min(depth, 5) (nq_frontier order) is cut into
+ * `chunks` contiguous ranges (0 = 64); range i covers entries
+ * [F*i/chunks, F*(i+1)/chunks).  Each range is deepened on the device to the
+ * count's depth (opts->depth; 0 = as nq_count chooses) and searched by one
+ * launch (opts->mode etc. as for nq_count).  After every range the file at
+ * `path` is replaced (written to path.tmp, flushed, renamed) by one text line:
+ *   nq-progress 1 n=.. depth=.. host_depth=.. chunks=.. done=.. total=.. check=..
+ * (total = the weighted count of the ranges done; check = FNV-1a 64 of the text
+ * before " check=").  A call that finds a record of the same n, depth, host
+ * depth and chunks continues after its last range; a record of another count,
+ * or a file that is not one intact record, is NQ_EINVAL (and left as it is).
+ * At most max_chunks ranges are counted per call (0 = all).  Returns NQ_OK with
+ * *out_total = Q(n) when every range is done, NQ_EAGAIN with the partial total
+ * while ranges remain; *out_done = ranges done.  opts->counts_out and
+ * opts->d_nodes must be NULL.  NQ_EINVAL also when the file cannot be written.
+ * Synchronous; one call at a time per file.
+ */
+int nq_count_resumable(uint32_t n, const nq_opts* opts, const char* path, uint32_t chunks,
+                       uint32_t max_chunks, uint64_t* out_total, uint32_t* out_done);
+
+/*
  * nq_autotune -- measure the best pre-placement depth and launch shape for n.
  *
  * Times complete persistent counts of n on the current device: every depth in

@@ -26,6 +26,7 @@ from ._native import (  # noqa: F401
     autotune,
     count,
     count_batch,
+    count_resumable,
     count_subproblems,
     expand,
     frontier,

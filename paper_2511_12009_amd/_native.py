@@ -126,6 +126,8 @@ def lib():
         L.nq_batch_entries.restype = u64
         L.nq_batch_destroy.argtypes = [vp]
         L.nq_batch_destroy.restype = ct.c_int
+        L.nq_count_resumable.argtypes = [u32, ct.POINTER(NqOpts), ct.c_char_p, u32, u32, pu64, pu32]
+        L.nq_count_resumable.restype = ct.c_int
         L.nq_set_loop_form.argtypes = [ct.c_int, ct.POINTER(ct.c_int)]
         L.nq_set_loop_form.restype = ct.c_int
         _LIB = L
@@ -284,6 +286,23 @@ def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None
         None if counts is False else counts.data_ptr(), total.data_ptr(), ct.byref(o)),
         "nq_count_subproblems")
     return (counts, total, ms.value) if timing else (counts, total)
+
+
+def count_resumable(n: int, path: str, chunks: int = 0, max_chunks: int = 0, depth: int = 0,
+                    mode="persistent", waves_per_cu: int = 0, refill_every: int = 0,
+                    claim: int = 0):
+    """nq_count_resumable: Q(n) in chunks whose progress is kept in the file
+    `path`; returns (total, chunks_done, finished).  While not finished, total
+    is the weighted count of the chunks done so far; call again to go on."""
+    o = _opts(depth, mode, 0, waves_per_cu, refill_every, None, 0, claim)
+    total = ct.c_uint64()
+    done = ct.c_uint32()
+    rc = lib().nq_count_resumable(n, ct.byref(o), os.fsencode(path), chunks, max_chunks,
+                                  ct.byref(total), ct.byref(done))
+    if rc == NQ_EAGAIN:
+        return total.value, done.value, False
+    _check(rc, "nq_count_resumable")
+    return total.value, done.value, True
 
 
 def set_loop_form(form: int) -> int:

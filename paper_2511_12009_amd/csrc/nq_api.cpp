@@ -1,10 +1,14 @@
-// C-ABI entry points: status text, nq_count, nq_count_subproblems, nq_count_batch.
+// C-ABI entry points: status text, nq_count, nq_count_subproblems, nq_count_batch,
+// nq_count_resumable.
 #include <hip/hip_runtime.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "nq_internal.h"
@@ -416,6 +420,177 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
         if (opts_in && opts_in->kernel_ms_out) *opts_in->kernel_ms_out = ms;
         *out_total = total;
         return NQ_OK;
+    } catch (const std::bad_alloc&) {
+        return NQ_ENOMEM;
+    } catch (...) {
+        return NQ_EINVAL;
+    }
+}
+
+// ---- nq_count_resumable: a long count in chunks, with its progress in a file.
+
+namespace {
+
+constexpr uint32_t kResumeHostDepth = 5;   // chunks are ranges of this host frontier
+constexpr uint32_t kResumeChunks = 64;
+
+struct Progress {
+    uint32_t n = 0, depth = 0, host_depth = 0, chunks = 0, done = 0;
+    uint64_t total = 0;
+};
+
+// FNV-1a (64-bit) of the record text: catches a torn or edited file.
+uint64_t fnv1a64(const std::string& s) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (unsigned char ch : s) {
+        h ^= ch;
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+std::string progress_body(const Progress& p) {
+    char buf[192];
+    std::snprintf(buf, sizeof buf,
+                  "nq-progress 1 n=%u depth=%u host_depth=%u chunks=%u done=%u total=%llu", p.n,
+                  p.depth, p.host_depth, p.chunks, p.done, (unsigned long long)p.total);
+    return buf;
+}
+
+// NQ_OK with *exists = false when there is no file; NQ_EINVAL when the file
+// cannot be read or is not one intact record.
+int progress_read(const char* path, Progress* p, bool* exists) {
+    *exists = false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return access(path, F_OK) == 0 ? NQ_EINVAL : NQ_OK;
+    char line[256] = {};
+    const bool got = std::fgets(line, sizeof line, f) != nullptr;
+    std::fclose(f);
+    if (!got) return NQ_EINVAL;
+    unsigned n, depth, hd, chunks, done;
+    unsigned long long total, check;
+    if (std::sscanf(line,
+                    "nq-progress 1 n=%u depth=%u host_depth=%u chunks=%u done=%u total=%llu "
+                    "check=%llx",
+                    &n, &depth, &hd, &chunks, &done, &total, &check) != 7)
+        return NQ_EINVAL;
+    Progress q;
+    q.n = n; q.depth = depth; q.host_depth = hd; q.chunks = chunks; q.done = done; q.total = total;
+    if (fnv1a64(progress_body(q)) != check || q.done > q.chunks) return NQ_EINVAL;
+    *p = q;
+    *exists = true;
+    return NQ_OK;
+}
+
+// Writes the record to path.tmp, flushes it to the disk and renames it over
+// path, so the file always holds one complete record.
+int progress_write(const char* path, const Progress& p) {
+    const std::string body = progress_body(p);
+    char tail[40];
+    std::snprintf(tail, sizeof tail, " check=%016llx\n", (unsigned long long)fnv1a64(body));
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return NQ_EINVAL;
+    bool ok = std::fputs((body + tail).c_str(), f) >= 0 && std::fflush(f) == 0 &&
+              fsync(fileno(f)) == 0;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) return NQ_EINVAL;
+    return NQ_OK;
+}
+
+}  // namespace
+
+extern "C" int nq_count_resumable(uint32_t n, const nq_opts* opts_in, const char* path,
+                                  uint32_t chunks, uint32_t max_chunks, uint64_t* out_total,
+                                  uint32_t* out_done) {
+    if (n < 1 || n > NQ_MAX_N || !path || !*path || !out_total || !out_done) return NQ_EINVAL;
+    if (opts_in && (opts_in->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
+    if (opts_in && (opts_in->counts_out || opts_in->d_nodes)) return NQ_EINVAL;
+    nq_opts local{};
+    if (opts_in) local = *opts_in;
+    local.kernel_ms_out = nullptr;
+    if (local.depth == 0) {
+        nq_tuned t;
+        if (tune_lookup(n, &t) == NQ_OK) {
+            local.depth = t.depth;
+            if (!local.waves_per_cu) local.waves_per_cu = t.waves_per_cu;
+            if (!local.refill_every) local.refill_every = t.refill_every;
+            if (!local.claim) local.claim = t.claim;
+        }
+    }
+    const uint32_t depth = local.depth ? local.depth : auto_depth(n);
+    if (depth > n) return NQ_EINVAL;
+    local.depth = depth;
+    try {
+        Progress pr;
+        pr.n = n;
+        pr.depth = depth;
+        pr.host_depth = std::min(depth, kResumeHostDepth);
+        pr.chunks = chunks ? chunks : kResumeChunks;
+        Progress old;
+        bool exists = false;
+        int rc = progress_read(path, &old, &exists);
+        if (rc != NQ_OK) return rc;
+        if (exists) {
+            if (old.n != pr.n || old.depth != pr.depth || old.host_depth != pr.host_depth ||
+                old.chunks != pr.chunks)
+                return NQ_EINVAL;                       // the file of another count
+            pr = old;
+        }
+        if (pr.done < pr.chunks) {
+            uint64_t Fh = 0;
+            if ((rc = frontier_fill(n, pr.host_depth, nullptr, nullptr, nullptr, nullptr, 0, &Fh,
+                                    nullptr)) != NQ_OK)
+                return rc;
+            std::vector<uint32_t> hc(Fh), hl(Fh), hr(Fh);
+            std::vector<uint8_t> hw(Fh);
+            if ((rc = frontier_fill(n, pr.host_depth, hc.data(), hl.data(), hr.data(), hw.data(),
+                                    Fh, &Fh, nullptr)) != NQ_OK)
+                return rc;
+            hipStream_t s = (hipStream_t)local.stream;
+            DevBuf tot;
+            if ((rc = tot.alloc(8)) != NQ_OK) return rc;
+            auto* d_total = tot.as<unsigned long long>();
+            uint32_t ran = 0;
+            while (pr.done < pr.chunks && (max_chunks == 0 || ran < max_chunks)) {
+                const uint64_t lo = Fh * pr.done / pr.chunks, hi = Fh * (pr.done + 1) / pr.chunks;
+                uint64_t part = 0;
+                if (hi > lo) {
+                    // this chunk's host entries, deepened on the device as nq_count does
+                    DeviceFrontier cur;
+                    if ((rc = alloc_frontier(hi - lo, &cur)) != NQ_OK) return rc;
+                    NQ_HIP(hipMemcpyAsync(cur.cols, hc.data() + lo, (hi - lo) * 4,
+                                          hipMemcpyHostToDevice, s));
+                    NQ_HIP(hipMemcpyAsync(cur.ld, hl.data() + lo, (hi - lo) * 4,
+                                          hipMemcpyHostToDevice, s));
+                    NQ_HIP(hipMemcpyAsync(cur.rd, hr.data() + lo, (hi - lo) * 4,
+                                          hipMemcpyHostToDevice, s));
+                    NQ_HIP(hipMemcpyAsync(cur.w, hw.data() + lo, hi - lo, hipMemcpyHostToDevice, s));
+                    for (uint32_t have = pr.host_depth; have < depth;) {
+                        const uint32_t left = depth - have, steps = (left + 2) / 3;
+                        const uint32_t rows = (left + steps - 1) / steps;
+                        DeviceFrontier next;
+                        if ((rc = expand_frontier(n, cur, rows, s, &next, nullptr)) != NQ_OK)
+                            return rc;
+                        cur = std::move(next);
+                        have += rows;
+                    }
+                    if ((rc = launch_zero_u64(d_total, 1, s)) != NQ_OK) return rc;
+                    if ((rc = run_device(n, cur.cols, cur.ld, cur.rd, cur.w, cur.len, nullptr,
+                                         d_total, depth, &local, nullptr)) != NQ_OK)
+                        return rc;
+                    NQ_HIP(hipMemcpyAsync(&part, d_total, 8, hipMemcpyDeviceToHost, s));
+                    NQ_HIP(hipStreamSynchronize(s));
+                }
+                pr.total += part;
+                pr.done += 1;
+                if ((rc = progress_write(path, pr)) != NQ_OK) return rc;
+                ++ran;
+            }
+        }
+        *out_done = pr.done;
+        *out_total = pr.total;
+        return pr.done == pr.chunks ? NQ_OK : NQ_EAGAIN;
     } catch (const std::bad_alloc&) {
         return NQ_ENOMEM;
     } catch (...) {

@@ -133,3 +133,48 @@ def test_loop_form_setter_validates_and_restores():
         assert nq.set_loop_form(-1) == 1
     finally:
         nq.set_loop_form(prev)
+
+
+def _progress_record(n, depth, host_depth, chunks, done, total):
+    """The text of one nq_count_resumable progress record (its file format)."""
+    body = (f"nq-progress 1 n={n} depth={depth} host_depth={host_depth} chunks={chunks} "
+            f"done={done} total={total}")
+    h = 0xcbf29ce484222325
+    for ch in body.encode():
+        h = ((h ^ ch) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return f"{body} check={h:016x}\n"
+
+
+def test_resumable_count_file_handling_without_a_gpu(tmp_path):
+    """nq_count_resumable reads and checks its progress file before any device
+    work: bad arguments, a damaged file and the file of another count are
+    refused (the file is left as it was); a finished record is answered from
+    the file alone."""
+    path = str(tmp_path / "progress")
+    with pytest.raises(nq.NQError):
+        nq.count_resumable(0, path, depth=3)
+    with pytest.raises(nq.NQError):
+        nq.count_resumable(29, path, depth=3)
+    with pytest.raises(nq.NQError):
+        nq.count_resumable(12, "", depth=3)
+    for bad in ("garbage\n", "",
+                _progress_record(12, 4, 4, 8, 3, 100).replace("done=3", "done=4"),
+                _progress_record(12, 4, 4, 8, 9, 100)):
+        with open(path, "w") as f:
+            f.write(bad)
+        with pytest.raises(nq.NQError):
+            nq.count_resumable(12, path, chunks=8, depth=4)
+        with open(path) as f:
+            assert f.read() == bad
+    other = _progress_record(13, 4, 4, 8, 3, 100)
+    with open(path, "w") as f:
+        f.write(other)
+    with pytest.raises(nq.NQError):
+        nq.count_resumable(12, path, chunks=8, depth=4)
+    with pytest.raises(nq.NQError):
+        nq.count_resumable(13, path, chunks=16, depth=4)
+    with pytest.raises(nq.NQError):
+        nq.count_resumable(13, path, chunks=8, depth=5)
+    with open(path, "w") as f:
+        f.write(_progress_record(12, 4, 4, 8, 8, 14200))
+    assert nq.count_resumable(12, path, chunks=8, depth=4) == (14200, 8, True)
