@@ -17,6 +17,12 @@ prefix_masks(n, prefix)        -> (cols, ld, rd) attack masks on row len(prefix)
 frontier_masks(n, k)           -> (cols, ld, rd uint32[F], weights uint8[F])
 prefixes_masks(n, prefixes)    -> (cols, ld, rd uint32[m]) for many prefixes
 count_prefixes(n, prefixes, threads) -> (counts uint64[F], nodes uint64[F])
+
+The second search (n non-attacking kings, one per row and column; see the
+kings section of ``oracle.c``), with the same shapes:
+kings(n), kings_brute_count(n, prefix=()), kings_frontier(n, k),
+kings_frontier_size(n, k), kings_prefixes_masks(n, prefixes),
+kings_count_prefixes(n, prefixes, threads)
 """
 from __future__ import annotations
 
@@ -57,8 +63,17 @@ def _lib():
                                           u32p]
         lib.oq_count_prefixes.argtypes = [_ct.c_int, _ct.c_int, i32p, _ct.c_uint64, _ct.c_int,
                                           u64p, u64p]
+        lib.oqk_count_prefix.argtypes = [_ct.c_int, _ct.c_int, i32p, u64p, u64p]
+        lib.oqk_brute_count.argtypes = [_ct.c_int, _ct.c_int, i32p, u64p]
+        lib.oqk_frontier.argtypes = [_ct.c_int, _ct.c_int, i32p, u8p, _ct.c_uint64, u64p]
+        lib.oqk_prefixes_masks.argtypes = [_ct.c_int, _ct.c_int, i32p, _ct.c_uint64, u32p, u32p,
+                                           u32p]
+        lib.oqk_count_prefixes.argtypes = [_ct.c_int, _ct.c_int, i32p, _ct.c_uint64, _ct.c_int,
+                                           u64p, u64p]
         for f in (lib.oq_queens, lib.oq_count_prefix, lib.oq_brute_count, lib.oq_frontier,
-                  lib.oq_prefix_masks, lib.oq_prefixes_masks, lib.oq_count_prefixes):
+                  lib.oq_prefix_masks, lib.oq_prefixes_masks, lib.oq_count_prefixes,
+                  lib.oqk_count_prefix, lib.oqk_brute_count, lib.oqk_frontier,
+                  lib.oqk_prefixes_masks, lib.oqk_count_prefixes):
             f.restype = _ct.c_int
         _LIB = lib
     return _LIB
@@ -156,4 +171,70 @@ def count_prefixes(n: int, prefixes, threads: int = 1):
                                     counts.ctypes.data_as(_ct.POINTER(_ct.c_uint64)),
                                     nodes.ctypes.data_as(_ct.POINTER(_ct.c_uint64))),
            "oq_count_prefixes")
+    return counts[:m], nodes[:m]
+
+
+# ---- the second search: n non-attacking kings, one per row and column ----
+
+def kings(n: int):
+    """The number of king placements (permutations with no two adjacent rows in
+    adjacent columns) by plain backtracking, and its nodes from row 0."""
+    c, nd = _ct.c_uint64(), _ct.c_uint64()
+    _check(_lib().oqk_count_prefix(n, 0, None, _ct.byref(c), _ct.byref(nd)), "oqk_count_prefix")
+    return c.value, nd.value
+
+
+def kings_brute_count(n: int, prefix=()):
+    """Completions of a king prefix by enumerating permutations (n <= 11)."""
+    a, p = _iarr(list(prefix) if len(prefix) else [0])
+    c = _ct.c_uint64()
+    _check(_lib().oqk_brute_count(n, len(prefix), p, _ct.byref(c)), "oqk_brute_count")
+    return c.value
+
+
+def kings_frontier_size(n: int, k: int) -> int:
+    ln = _ct.c_uint64()
+    _check(_lib().oqk_frontier(n, k, None, None, 0, _ct.byref(ln)), "oqk_frontier(size)")
+    return ln.value
+
+
+def kings_frontier(n: int, k: int):
+    """Symmetry-reduced king prefixes (int32[F, k]) and weights (uint8[F])."""
+    size = kings_frontier_size(n, k)
+    pre = _np.zeros((max(size, 1), max(k, 1)), dtype=_np.int32)
+    w = _np.zeros(max(size, 1), dtype=_np.uint8)
+    ln = _ct.c_uint64()
+    _check(_lib().oqk_frontier(n, k, pre.ctypes.data_as(_ct.POINTER(_ct.c_int)),
+                               w.ctypes.data_as(_ct.POINTER(_ct.c_uint8)), size, _ct.byref(ln)),
+           "oqk_frontier")
+    return pre[:size, :k], w[:size]
+
+
+def kings_prefixes_masks(n: int, prefixes):
+    """(cols, ld, rd) uint32[m] that each king prefix casts on its next row."""
+    pre = _np.ascontiguousarray(_np.asarray(prefixes, dtype=_np.int32))
+    m, k = pre.shape
+    cols = _np.zeros(max(m, 1), dtype=_np.uint32)
+    ld = _np.zeros(max(m, 1), dtype=_np.uint32)
+    rd = _np.zeros(max(m, 1), dtype=_np.uint32)
+    buf = pre if pre.size else _np.zeros(1, dtype=_np.int32)
+    u32 = lambda a: a.ctypes.data_as(_ct.POINTER(_ct.c_uint32))  # noqa: E731
+    _check(_lib().oqk_prefixes_masks(n, k, buf.ctypes.data_as(_ct.POINTER(_ct.c_int)), m,
+                                     u32(cols), u32(ld), u32(rd)), "oqk_prefixes_masks")
+    return cols[:m], ld[:m], rd[:m]
+
+
+def kings_count_prefixes(n: int, prefixes, threads: int = 1):
+    """Completions and nodes (rows k..n-2) of each king prefix."""
+    pre = _np.ascontiguousarray(_np.asarray(prefixes, dtype=_np.int32))
+    if pre.ndim == 1:
+        pre = pre.reshape(-1, 0) if pre.size == 0 else pre.reshape(1, -1)
+    m, k = pre.shape
+    counts = _np.zeros(max(m, 1), dtype=_np.uint64)
+    nodes = _np.zeros(max(m, 1), dtype=_np.uint64)
+    buf = pre if pre.size else _np.zeros(1, dtype=_np.int32)
+    _check(_lib().oqk_count_prefixes(n, k, buf.ctypes.data_as(_ct.POINTER(_ct.c_int)), m,
+                                     threads, counts.ctypes.data_as(_ct.POINTER(_ct.c_uint64)),
+                                     nodes.ctypes.data_as(_ct.POINTER(_ct.c_uint64))),
+           "oqk_count_prefixes")
     return counts[:m], nodes[:m]

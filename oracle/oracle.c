@@ -318,3 +318,235 @@ int oq_count_prefixes(int n, int k, const int* prefixes, uint64_t m, int threads
     for (int t = 0; t < started; ++t) pthread_join(tid[t], NULL);
     return OQ_OK;
 }
+
+/* ============================================ second search: n kings ====== */
+/*
+ * Hertzsprung's problem: the number of ways to put n kings on an n x n board,
+ * one per row and one per column, no two attacking, i.e. the permutations s
+ * of 0..n-1 with |s(i) - s(i+1)| != 1 for every i.  It is the second depth-
+ * first search run on the same lane-stack machinery (the paper's conclusion:
+ * any DFS with many subproblems, an iterative stack form and frames of more
+ * than one word).  A king attacks only the adjacent row, so a board is the
+ * set of used columns plus the column of the last placed king.  Prefixes,
+ * weights, order and the node unit follow the queens oracle: row 0 in
+ * [0, n/2) with weight 2 (mirror symmetry s -> n-1-s); for odd n the centre
+ * column with row 1 in [0, n/2 - 2] (the centre and its neighbours are
+ * excluded by the rules) with weight 2, or alone with weight 1 when k = 1.
+ *
+ * Pins (tests/): permutation brute force (n <= 10), the recurrence that the
+ * counts obey (a(n) = (n+1)a(n-1) - (n-2)a(n-2) - (n-5)a(n-3) + (n-3)a(n-4)),
+ * and the weighted frontier totals against the unreduced counts.
+ */
+
+typedef struct {
+    int n;
+    unsigned char col[OQ_MAXN];    /* column j used                             */
+    int last;                      /* column of the king in the row above, or -1 */
+} kboard_t;
+
+static int kboard_free(const kboard_t* b, int c) {
+    if (b->col[c]) return 0;
+    if (b->last >= 0 && (c == b->last - 1 || c == b->last + 1)) return 0;
+    return 1;
+}
+
+/* Completions of rows row..n-1; placements in rows <= n-2 are nodes. */
+static uint64_t kboard_complete(kboard_t* b, int row, uint64_t* nodes) {
+    if (row == b->n) return 1;
+    uint64_t total = 0;
+    const int above = b->last;
+    for (int c = 0; c < b->n; ++c) {
+        if (!kboard_free(b, c)) continue;
+        if (row <= b->n - 2) ++*nodes;
+        b->col[c] = 1;
+        b->last = c;
+        total += kboard_complete(b, row + 1, nodes);
+        b->last = above;
+        b->col[c] = 0;
+    }
+    return total;
+}
+
+/* Place a prefix on an empty board; 0 if it breaks a rule. */
+static int kboard_place_prefix(kboard_t* b, int k, const int* prefix) {
+    for (int r = 0; r < k; ++r) {
+        int c = prefix[r];
+        if (c < 0 || c >= b->n || !kboard_free(b, c)) return 0;
+        b->col[c] = 1;
+        b->last = c;
+    }
+    return 1;
+}
+
+static void kboard_init(kboard_t* b, int n) {
+    memset(b, 0, sizeof(*b));
+    b->n = n;
+    b->last = -1;
+}
+
+int oqk_count_prefix(int n, int k, const int* prefix, uint64_t* count, uint64_t* nodes) {
+    if (!valid_nk(n, k) || !count || (k > 0 && !prefix)) return OQ_EINVAL;
+    kboard_t b;
+    kboard_init(&b, n);
+    uint64_t nd = 0;
+    *count = kboard_place_prefix(&b, k, prefix) ? kboard_complete(&b, k, &nd) : 0;
+    if (nodes) *nodes = nd;
+    return OQ_OK;
+}
+
+/* Every ordering of the free columns after the prefix, checked pairwise. */
+int oqk_brute_count(int n, int k, const int* prefix, uint64_t* count) {
+    if (!valid_nk(n, k) || n > 11 || !count || (k > 0 && !prefix)) return OQ_EINVAL;
+    int s[OQ_MAXN], used[OQ_MAXN] = {0};
+    for (int r = 0; r < k; ++r) {
+        if (prefix[r] < 0 || prefix[r] >= n || used[prefix[r]]) { *count = 0; return OQ_OK; }
+        used[prefix[r]] = 1;
+        s[r] = prefix[r];
+    }
+    int m = 0, rest[OQ_MAXN];
+    for (int c = 0; c < n; ++c)
+        if (!used[c]) rest[m++] = c;
+    uint64_t total = 0;
+    do {
+        for (int i = 0; i < m; ++i) s[k + i] = rest[i];
+        int ok = 1;
+        for (int i = 0; i + 1 < n && ok; ++i) {
+            int d = s[i] - s[i + 1];
+            if (d == 1 || d == -1) ok = 0;
+        }
+        total += (uint64_t)ok;
+    } while (next_perm(rest, m));
+    *count = total;
+    return OQ_OK;
+}
+
+typedef struct {
+    frontier_ctx f;
+    kboard_t b;
+} kfrontier_ctx;
+
+static void kextend(kfrontier_ctx* x, int row, int w) {
+    if (row == x->f.k) { emit(&x->f, w); return; }
+    const int above = x->b.last;
+    for (int c = 0; c < x->f.n; ++c) {
+        if (!kboard_free(&x->b, c)) continue;
+        x->f.cur[row] = c;
+        x->b.col[c] = 1;
+        x->b.last = c;
+        kextend(x, row + 1, w);
+        x->b.last = above;
+        x->b.col[c] = 0;
+    }
+}
+
+/* Symmetry-reduced king prefixes of length k, lexicographic (as oq_frontier). */
+int oqk_frontier(int n, int k, int* prefixes, uint8_t* weights, uint64_t cap, uint64_t* out_len) {
+    if (!valid_nk(n, k) || !out_len) return OQ_EINVAL;
+    kfrontier_ctx x;
+    memset(&x, 0, sizeof(x));
+    x.f.n = n; x.f.k = k; x.f.prefixes = prefixes; x.f.weights = weights;
+    x.f.cap = (prefixes || weights) ? cap : 0;
+    kboard_init(&x.b, n);
+    if (k == 0) {
+        emit(&x.f, 1);
+    } else {
+        const int half = n / 2;
+        for (int c0 = 0; c0 < half; ++c0) {
+            x.f.cur[0] = c0;
+            x.b.col[c0] = 1;
+            x.b.last = c0;
+            kextend(&x, 1, 2);
+            x.b.last = -1;
+            x.b.col[c0] = 0;
+        }
+        if (n % 2 == 1) {
+            const int m = half;
+            x.f.cur[0] = m;
+            x.b.col[m] = 1;
+            x.b.last = m;
+            if (k == 1) {
+                emit(&x.f, 1);
+            } else {
+                for (int c1 = 0; c1 <= m - 2; ++c1) {
+                    if (!kboard_free(&x.b, c1)) continue;
+                    x.f.cur[1] = c1;
+                    x.b.col[c1] = 1;
+                    x.b.last = c1;
+                    kextend(&x, 2, 2);
+                    x.b.last = m;
+                    x.b.col[c1] = 0;
+                }
+            }
+        }
+    }
+    *out_len = x.f.len;
+    if ((prefixes || weights) && x.f.len > cap) return OQ_ERANGE;
+    return OQ_OK;
+}
+
+/*
+ * The masks a king prefix casts on row k, by definition: every placed king
+ * blocks its column; the king of row k-1 also blocks (k, c+1) (in `ld`) and
+ * (k, c-1) (in `rd`), squares off the board dropped.  Bit j is column j.
+ */
+int oqk_prefixes_masks(int n, int k, const int* prefixes, uint64_t m, uint32_t* cols,
+                       uint32_t* ld, uint32_t* rd) {
+    if (!valid_nk(n, k) || !cols || !ld || !rd || (m > 0 && k > 0 && !prefixes)) return OQ_EINVAL;
+    for (uint64_t i = 0; i < m; ++i) {
+        const int* p = prefixes + i * (uint64_t)k;
+        uint32_t C = 0, L = 0, R = 0;
+        for (int r = 0; r < k; ++r) {
+            if (p[r] < 0 || p[r] >= n) return OQ_EINVAL;
+            C |= (uint32_t)1 << p[r];
+        }
+        if (k > 0) {
+            const int c = p[k - 1];
+            if (c + 1 < n) L = (uint32_t)1 << (c + 1);
+            if (c - 1 >= 0) R = (uint32_t)1 << (c - 1);
+        }
+        cols[i] = C; ld[i] = L; rd[i] = R;
+    }
+    return OQ_OK;
+}
+
+typedef struct {
+    int n, k;
+    const int* prefixes;
+    uint64_t m;
+    uint64_t* counts;
+    uint64_t* nodes;
+    uint64_t next;
+} kpool_ctx;
+
+static void* kpool_worker(void* arg) {
+    kpool_ctx* p = (kpool_ctx*)arg;
+    for (;;) {
+        uint64_t i = __atomic_fetch_add(&p->next, 1, __ATOMIC_RELAXED);
+        if (i >= p->m) break;
+        uint64_t c = 0, nd = 0;
+        oqk_count_prefix(p->n, p->k, p->prefixes + i * (uint64_t)p->k, &c, &nd);
+        p->counts[i] = c;
+        if (p->nodes) p->nodes[i] = nd;
+    }
+    return NULL;
+}
+
+/* Completions (and nodes) of m king prefixes; threads only spread prefixes. */
+int oqk_count_prefixes(int n, int k, const int* prefixes, uint64_t m, int threads,
+                       uint64_t* counts, uint64_t* nodes) {
+    if (!valid_nk(n, k) || !counts || (m > 0 && k > 0 && !prefixes)) return OQ_EINVAL;
+    kpool_ctx p = { n, k, prefixes, m, counts, nodes, 0 };
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    if (threads == 1 || m < 2) {
+        kpool_worker(&p);
+        return OQ_OK;
+    }
+    pthread_t tid[256];
+    int started = 0;
+    for (int t = 0; t < threads; ++t)
+        if (pthread_create(&tid[t], NULL, kpool_worker, &p) == 0) ++started;
+    if (started == 0) kpool_worker(&p);
+    for (int t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+    return OQ_OK;
+}
