@@ -82,6 +82,18 @@ int nq_frontier(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld, uint32
                 uint8_t* weight, uint64_t capacity, uint64_t* out_len);
 
 /*
+ * nq_kings_frontier -- nq_frontier for the kings search (NQ_FLAG_KINGS): every
+ * placement of one king per row in rows 0..depth-1, distinct columns, no two
+ * kings of adjacent rows in adjacent columns, under the same symmetry rule
+ * (mirror image s -> n-1-s; for odd n the centre column of row 0 with row 1 in
+ * [0, n/2 - 2], the centre's neighbours being excluded by the rule itself) and
+ * in the same order, weights and calling convention.  ld[i] / rd[i] hold the
+ * square right / left of the king of row depth-1 (masked to n bits).
+ */
+int nq_kings_frontier(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld, uint32_t* rd,
+                      uint8_t* weight, uint64_t capacity, uint64_t* out_len);
+
+/*
  * nq_frontier_runs -- where each row-0 column's entries start in the frontier.
  *
  * The frontier of (n, depth) is ordered by the row-0 column first, so the
@@ -128,9 +140,18 @@ enum nq_flags {
     /* Persistent mode hands entries out in frontier order instead of the
      * default reverse order (the last row-0 columns carry the largest subtrees,
      * Section 4.5, so reverse order starts the longest work first). */
-    NQ_FLAG_FORWARD_ORDER = 1u
+    NQ_FLAG_FORWARD_ORDER = 1u,
+    /* nq_count / nq_count_subproblems: count n non-attacking KINGS, one per row
+     * and column, instead of queens (the second depth-first search run on the
+     * same lane stack; the paper's conclusion names permutation searches as
+     * candidates for its method).  A king attacks only the adjacent row, so the
+     * Somers triple of an entry is (columns taken, the square right of the last
+     * king, the square left of it), as nq_kings_frontier writes it.  Only the
+     * default inner-loop form runs it; batches, servers and resumable counts
+     * refuse the flag (NQ_EINVAL). */
+    NQ_FLAG_KINGS = 2u
 };
-#define NQ_FLAGS_ALL 1u
+#define NQ_FLAGS_ALL 3u
 
 /*
  * Options shared by the counting entry points.  A NULL options pointer, or a

@@ -96,6 +96,8 @@ def lib():
         L.nq_last_hip_error.restype = ct.c_int
         L.nq_frontier.argtypes = [u32, u32, pu32, pu32, pu32, pu8, u64, pu64]
         L.nq_frontier.restype = ct.c_int
+        L.nq_kings_frontier.argtypes = [u32, u32, pu32, pu32, pu32, pu8, u64, pu64]
+        L.nq_kings_frontier.restype = ct.c_int
         L.nq_frontier_runs.argtypes = [u32, u32, pu64, u32, pu32]
         L.nq_frontier_runs.restype = ct.c_int
         L.nq_expand.argtypes = [u32, u32, vp, vp, vp, vp, u64, vp, vp, vp, vp, u64, pu64, vp]
@@ -144,6 +146,7 @@ def _check(rc: int, what: str):
 
 
 FLAG_FORWARD_ORDER = 1
+FLAG_KINGS = 2
 
 
 def _opts(depth=0, mode="persistent", wg_size=0, waves_per_cu=0, refill_every=0, stream=None,
@@ -183,18 +186,20 @@ def frontier_runs(n: int, depth: int):
     return [int(x) for x in off]
 
 
-def frontier(n: int, depth: int):
-    """(cols, ld, rd) uint32[F] and weight uint8[F] in canonical order (host arrays)."""
-    f = frontier_size(n, depth)
+def frontier(n: int, depth: int, kings: bool = False):
+    """(cols, ld, rd) uint32[F] and weight uint8[F] in canonical order (host arrays);
+    kings=True: the kings search's frontier (nq_kings_frontier)."""
+    fn = lib().nq_kings_frontier if kings else lib().nq_frontier
+    ln = ct.c_uint64()
+    _check(fn(n, depth, None, None, None, None, 0, ct.byref(ln)), "frontier size")
+    f = ln.value
     cols = np.zeros(max(f, 1), np.uint32)
     ld = np.zeros(max(f, 1), np.uint32)
     rd = np.zeros(max(f, 1), np.uint32)
     w = np.zeros(max(f, 1), np.uint8)
-    ln = ct.c_uint64()
     p32 = lambda a: a.ctypes.data_as(ct.POINTER(ct.c_uint32))  # noqa: E731
-    _check(lib().nq_frontier(n, depth, p32(cols), p32(ld), p32(rd),
-                             w.ctypes.data_as(ct.POINTER(ct.c_uint8)), f, ct.byref(ln)),
-           "nq_frontier")
+    _check(fn(n, depth, p32(cols), p32(ld), p32(rd), w.ctypes.data_as(ct.POINTER(ct.c_uint8)), f,
+              ct.byref(ln)), "nq_kings_frontier" if kings else "nq_frontier")
     return cols[:f], ld[:f], rd[:f], w[:f]
 
 
@@ -221,17 +226,21 @@ def expand(n: int, rows: int, cols, ld, rd, weight=None, stream=None):
 
 def count(n: int, depth: int = 0, mode="persistent", wg_size: int = 0, waves_per_cu: int = 0,
           refill_every: int = 0, counts: bool = False, timing: bool = False, stream=None,
-          forward: bool = False, claim: int = 0):
-    """Q(n).  With counts=True also the per-subproblem counts (numpy uint64, frontier
-    order); with timing=True also the DFS kernel time in ms.  Synchronous."""
+          forward: bool = False, claim: int = 0, kings: bool = False):
+    """Q(n) (kings=True: the number of ways to place n non-attacking kings, one
+    per row and column).  With counts=True also the per-subproblem counts (numpy
+    uint64, frontier order); with timing=True also the DFS kernel time in ms.
+    Synchronous."""
     o = _opts(depth, mode, wg_size, waves_per_cu, refill_every,
               stream if stream is None else _stream_handle(stream),
-              FLAG_FORWARD_ORDER if forward else 0, claim)
+              (FLAG_FORWARD_ORDER if forward else 0) | (FLAG_KINGS if kings else 0), claim)
     buf = None
+    size = (lambda: len(frontier(n, depth, kings=True)[0])) if kings else \
+        (lambda: frontier_size(n, depth))
     if counts:
         if depth == 0:
             raise ValueError("counts=True needs an explicit depth")
-        buf = np.zeros(max(frontier_size(n, depth), 1), np.uint64)
+        buf = np.zeros(max(size(), 1), np.uint64)
         o.counts_out = buf.ctypes.data_as(ct.POINTER(ct.c_uint64))
         o.counts_capacity = len(buf)
     ms = ct.c_double(0.0)
@@ -241,7 +250,7 @@ def count(n: int, depth: int = 0, mode="persistent", wg_size: int = 0, waves_per
     _check(lib().nq_count(n, ct.byref(o), ct.byref(total)), "nq_count")
     out = [total.value]
     if counts:
-        out.append(buf[:frontier_size(n, depth)])
+        out.append(buf[:size()])
     if timing:
         out.append(ms.value)
     return out[0] if len(out) == 1 else tuple(out)
@@ -250,7 +259,8 @@ def count(n: int, depth: int = 0, mode="persistent", wg_size: int = 0, waves_per
 def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None,
                       depth: int = 0, mode="persistent", wg_size: int = 0,
                       waves_per_cu: int = 0, refill_every: int = 0, stream=None,
-                      timing: bool = False, nodes=None, forward: bool = False, claim: int = 0):
+                      timing: bool = False, nodes=None, forward: bool = False, claim: int = 0,
+                      kings: bool = False):
     """Counts every subtree of device-resident triples (torch int32 CUDA tensors).
 
     ``counts`` (int64[F]) and ``total`` (int64[1], accumulated) are torch tensors
@@ -272,7 +282,7 @@ def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None
     if total is None:
         total = torch.zeros(1, dtype=torch.int64, device=cols.device)
     o = _opts(depth, mode, wg_size, waves_per_cu, refill_every, _stream_handle(stream),
-              FLAG_FORWARD_ORDER if forward else 0, claim)
+              (FLAG_FORWARD_ORDER if forward else 0) | (FLAG_KINGS if kings else 0), claim)
     if nodes is not None:
         if nodes.dtype != torch.int64 or nodes.numel() != length or not nodes.is_cuda:
             raise ValueError("nodes must be an int64 CUDA tensor of the same length")

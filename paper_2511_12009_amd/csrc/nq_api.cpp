@@ -107,6 +107,22 @@ uint32_t auto_depth(uint32_t n) {
     return std::max<uint32_t>(1, k);
 }
 
+// The kings search's automatic depth: the shallowest whose host frontier has
+// at least 2^22 entries (kept on the host, so at most 2^27), at most n - 2.
+uint32_t kings_auto_depth(uint32_t n) {
+    if (n <= 3) return n;
+    uint32_t best = 1;
+    for (uint32_t d = 1; d + 2 <= n; ++d) {
+        uint64_t F = 0;
+        if (frontier_fill(n, d, nullptr, nullptr, nullptr, nullptr, 0, &F, nullptr, true) != NQ_OK ||
+            F > (1ull << 27))
+            break;
+        best = d;
+        if (F >= (1ull << 22)) break;
+    }
+    return best;
+}
+
 uint32_t refill_default(const nq_opts* o) {
     return (o && o->refill_every) ? o->refill_every : 512u;
 }
@@ -129,8 +145,9 @@ static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
     const uint32_t frames = std::max<uint32_t>(1, frames_needed(n, min_placed));
     LaunchCfg cfg;
     uint64_t* d_nodes = opts ? opts->d_nodes : nullptr;
+    const bool kings = opts && (opts->flags & NQ_FLAG_KINGS);
     rc = plan_launch(dev, mode, opts ? opts->wg_size : 0, opts ? opts->waves_per_cu : 0, frames,
-                     len, d_nodes != nullptr, leafctr_ok(n, min_placed), &cfg);
+                     len, d_nodes != nullptr, leafctr_ok(n, min_placed), &cfg, false, kings);
     if (rc != NQ_OK) return rc;
     hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
     unsigned long long* head = nullptr;
@@ -174,14 +191,16 @@ int alloc_frontier(uint64_t len, DeviceFrontier* f) {
 }
 
 // The host frontier of depth `depth` (nq_frontier) uploaded to the device.
-int host_frontier(uint32_t n, uint32_t depth, hipStream_t s, DeviceFrontier* out) {
+int host_frontier(uint32_t n, uint32_t depth, hipStream_t s, DeviceFrontier* out,
+                  bool kings = false) {
     uint64_t F = 0;
     std::vector<uint64_t> first_row;
-    int rc = frontier_fill(n, depth, nullptr, nullptr, nullptr, nullptr, 0, &F, nullptr);
+    int rc = frontier_fill(n, depth, nullptr, nullptr, nullptr, nullptr, 0, &F, nullptr, kings);
     if (rc != NQ_OK) return rc;
     std::vector<uint32_t> hc(F), hl(F), hr(F);
     std::vector<uint8_t> hw(F);
-    rc = frontier_fill(n, depth, hc.data(), hl.data(), hr.data(), hw.data(), F, &F, &first_row);
+    rc = frontier_fill(n, depth, hc.data(), hl.data(), hr.data(), hw.data(), F, &F, &first_row,
+                       kings);
     if (rc != NQ_OK) return rc;
     if ((rc = alloc_frontier(F, out)) != NQ_OK) return rc;
     if (F) {
@@ -363,7 +382,8 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
     if (opts_in) local = *opts_in;
     local.d_nodes = nullptr;          // per-entry nodes are a nq_count_subproblems output
     const nq_opts* opts = &local;
-    if (local.depth == 0) {
+    const bool kings = (local.flags & NQ_FLAG_KINGS) != 0;
+    if (local.depth == 0 && !kings) {
         nq_tuned t;
         if (tune_lookup(n, &t) == NQ_OK) {
             local.depth = t.depth;
@@ -372,12 +392,14 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
             if (!local.claim) local.claim = t.claim;
         }
     }
-    const uint32_t depth = local.depth ? local.depth : auto_depth(n);
+    const uint32_t depth = local.depth ? local.depth : kings ? kings_auto_depth(n) : auto_depth(n);
     if (depth > n) return NQ_EINVAL;
     try {
         hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
         DeviceFrontier fr;
-        int rc = build_device_frontier(n, depth, s, &fr);
+        // the kings frontier is built on the host only (nq_expand follows the
+        // queens' recurrence)
+        int rc = kings ? host_frontier(n, depth, s, &fr, true) : build_device_frontier(n, depth, s, &fr);
         if (rc != NQ_OK) return rc;
         const uint64_t F = fr.len;
         const std::vector<uint64_t>& first_row = fr.first_row;
@@ -506,6 +528,7 @@ extern "C" int nq_count_resumable(uint32_t n, const nq_opts* opts_in, const char
     if (n < 1 || n > NQ_MAX_N || !path || !*path || !out_total || !out_done) return NQ_EINVAL;
     if (opts_in && (opts_in->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
     if (opts_in && (opts_in->counts_out || opts_in->d_nodes)) return NQ_EINVAL;
+    if (opts_in && (opts_in->flags & NQ_FLAG_KINGS)) return NQ_EINVAL;
     nq_opts local{};
     if (opts_in) local = *opts_in;
     local.kernel_ms_out = nullptr;

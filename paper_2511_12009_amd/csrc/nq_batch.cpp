@@ -62,6 +62,7 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
                  nq_batch** out) {
     if (!out || ninst == 0 || !ns) return NQ_EINVAL;
     if (opts && (opts->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
+    if (opts && (opts->flags & NQ_FLAG_KINGS)) return NQ_EINVAL;   // queens only
     for (uint32_t i = 0; i < ninst; ++i) {
         if (ns[i] < 1 || ns[i] > NQ_MAX_N) return NQ_EINVAL;
         if (depths && (depths[i] < 1 || depths[i] > ns[i])) return NQ_EINVAL;

@@ -258,9 +258,13 @@ __device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, u
 // launcher adds to P.frames (kFormExtraFrames).  SERVE
 // (persistent launches of the serving loop, P.remaining set) compiles in the
 // per-request retirement; it is a template flag so that the scheduler visit
-// of every other launch carries none of its code.
-template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP, bool SERVE>
+// of every other launch carries none of its code.  KINGS runs the second
+// search (n kings, one per row and column): the same stack, scheduler and
+// leaf test, with the next row's attacked squares taken from the placed king
+// alone (no diagonals carried down); it exists for the default form only.
+template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP, bool SERVE, bool KINGS = false>
 __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
+    static_assert(!KINGS || LOOP == 1, "the kings search runs in the default form only");
     extern __shared__ uint4 lds_stack[];
     const int32_t lds = (int32_t)(uint32_t)(uintptr_t)(lds_frame*)lds_stack;
     const uint32_t lane = threadIdx.x & 63u;
@@ -458,8 +462,8 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 uint32_t p, rest = st.w;
                 isa_take_lowest(rest, p);
                 const uint32_t nc = LEAFCTR ? st.x + p + step_k : (st.x | p);
-                const uint32_t nl = (st.y + p) << 1;
-                const uint32_t nr = (st.z + p) >> 1;
+                const uint32_t nl = KINGS ? (p << 1) : (st.y + p) << 1;
+                const uint32_t nr = KINGS ? (p >> 1) : (st.z + p) >> 1;
                 const uint32_t a = last & ~(nc | nl | nr);
                 if (STATS) steps32 += (p != 0u);
                 const uint64_t leafm = __builtin_amdgcn_ballot_w64(
@@ -614,9 +618,27 @@ __global__ void nq_fill_u32_kernel(uint32_t* dst, uint32_t value, uint64_t count
     if (i < count) dst[i] = value;
 }
 
-template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP, bool SERVE = false>
+template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP, bool SERVE = false,
+          bool KINGS = false>
 static const void* kernel_ptr() {
-    return reinterpret_cast<const void*>(&nq_dfs_kernel<PERSISTENT, STATS, LEAFCTR, LOOP, SERVE>);
+    return reinterpret_cast<const void*>(
+        &nq_dfs_kernel<PERSISTENT, STATS, LEAFCTR, LOOP, SERVE, KINGS>);
+}
+
+// The kings search: default form, no serving.
+static const void* select_kings_kernel(uint32_t mode, bool stats, bool leafctr) {
+    if (mode == NQ_MODE_PERSISTENT) {
+        if (stats)
+            return leafctr ? kernel_ptr<true, true, true, 1, false, true>()
+                           : kernel_ptr<true, true, false, 1, false, true>();
+        return leafctr ? kernel_ptr<true, false, true, 1, false, true>()
+                       : kernel_ptr<true, false, false, 1, false, true>();
+    }
+    if (stats)
+        return leafctr ? kernel_ptr<false, true, true, 1, false, true>()
+                       : kernel_ptr<false, true, false, 1, false, true>();
+    return leafctr ? kernel_ptr<false, false, true, 1, false, true>()
+                   : kernel_ptr<false, false, false, 1, false, true>();
 }
 
 // The kernel for a launch shape; serving launches exist only as persistent,
@@ -687,7 +709,9 @@ uint32_t default_idle_min() {
     return v;
 }
 
-static const void* select_kernel(int form, uint32_t mode, bool stats, bool leafctr, bool serve) {
+static const void* select_kernel(int form, uint32_t mode, bool stats, bool leafctr, bool serve,
+                                 bool kings) {
+    if (kings) return (form == 1 && !serve) ? select_kings_kernel(mode, stats, leafctr) : nullptr;
     switch (form) {
         case 0: return select_kernel_loop<0>(mode, stats, leafctr, serve);
         case 1: return select_kernel_loop<1>(mode, stats, leafctr, serve);
@@ -730,7 +754,7 @@ int device_info(DeviceInfo* out) {
 
 int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t waves_per_cu,
                 uint32_t frames, uint64_t len, bool stats, bool leafctr, LaunchCfg* cfg,
-                bool serve) {
+                bool serve, bool kings) {
     if (mode != NQ_MODE_PLAIN && mode != NQ_MODE_PERSISTENT) return NQ_EINVAL;
     const int form = loop_form();
     frames += kFormExtraFrames[form];
@@ -752,7 +776,8 @@ int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t
     cfg->leafctr = leafctr;
     cfg->serve = serve;
     cfg->form = form;
-    const void* fn = select_kernel(form, mode, stats, leafctr, serve);
+    cfg->kings = kings;
+    const void* fn = select_kernel(form, mode, stats, leafctr, serve, kings);
     if (!fn) return NQ_EINVAL;
     if (mode == NQ_MODE_PLAIN) {
         const uint64_t g = (len + wg_size - 1) / wg_size;
@@ -814,7 +839,8 @@ int launch_dfs(const LaunchCfg& cfg, const DfsParams& P, void* stream) {
     // and the LDS planned must hold the stacks of the form it was planned for.
     if (cfg.serve != (P.remaining != nullptr)) return NQ_EINVAL;
     if (cfg.form < 0 || cfg.form >= kLoopForms) return NQ_EINVAL;
-    const void* fn = select_kernel(cfg.form, cfg.mode, cfg.stats, cfg.leafctr, cfg.serve);
+    const void* fn = select_kernel(cfg.form, cfg.mode, cfg.stats, cfg.leafctr, cfg.serve,
+                                   cfg.kings);
     if (!fn) return NQ_EINVAL;
     DfsParams Q = P;
     Q.frames += kFormExtraFrames[cfg.form];

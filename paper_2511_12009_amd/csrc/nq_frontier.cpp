@@ -25,7 +25,17 @@ struct Sink {
     uint64_t pos;
     uint32_t last;
     uint8_t w;
+    bool kings;
 };
+
+// The triple below (c, l, r) after placing p: queens carry both diagonals down
+// (Somers' recurrence); a king attacks only the next row's neighbours of p.
+inline void child(bool kings, uint32_t c, uint32_t l, uint32_t r, uint32_t p, uint32_t& nc,
+                  uint32_t& nl, uint32_t& nr) {
+    nc = c | p;
+    nl = kings ? (p << 1) : ((l | p) << 1);
+    nr = kings ? (p >> 1) : ((r | p) >> 1);
+}
 
 // Placements of `rows_left` more rows below (c, l, r), lowest column first.
 void expand_fill(Sink& s, int rows_left, uint32_t c, uint32_t l, uint32_t r) {
@@ -39,21 +49,24 @@ void expand_fill(Sink& s, int rows_left, uint32_t c, uint32_t l, uint32_t r) {
     }
     uint32_t v = s.last & ~(c | l | r);
     while (v) {
-        uint32_t p = v & (0u - v);
+        uint32_t p = v & (0u - v), nc, nl, nr;
         v ^= p;
-        expand_fill(s, rows_left - 1, c | p, (l | p) << 1, (r | p) >> 1);
+        child(s.kings, c, l, r, p, nc, nl, nr);
+        expand_fill(s, rows_left - 1, nc, nl, nr);
     }
 }
 
-uint64_t expand_count(uint32_t last, int rows_left, uint32_t c, uint32_t l, uint32_t r) {
+uint64_t expand_count(uint32_t last, bool kings, int rows_left, uint32_t c, uint32_t l,
+                      uint32_t r) {
     if (rows_left == 0) return 1;
     uint32_t v = last & ~(c | l | r);
     if (rows_left == 1) return (uint64_t)__builtin_popcount(v);
     uint64_t total = 0;
     while (v) {
-        uint32_t p = v & (0u - v);
+        uint32_t p = v & (0u - v), nc, nl, nr;
         v ^= p;
-        total += expand_count(last, rows_left - 1, c | p, (l | p) << 1, (r | p) >> 1);
+        child(kings, c, l, r, p, nc, nl, nr);
+        total += expand_count(last, kings, rows_left - 1, nc, nl, nr);
     }
     return total;
 }
@@ -62,11 +75,11 @@ uint64_t expand_count(uint32_t last, int rows_left, uint32_t c, uint32_t l, uint
 
 // Roots in canonical order.  Every root sits at row `row` with `rows_left`
 // rows still to place before the frontier depth.
-std::vector<Root> frontier_roots(uint32_t n, uint32_t depth) {
+std::vector<Root> frontier_roots(uint32_t n, uint32_t depth, bool kings) {
     std::vector<Root> roots;
     const uint32_t last = (n >= 32) ? 0xffffffffu : ((1u << n) - 1u);
     if (depth == 0) {
-        roots.push_back({0, 0, 0, 0, 0, 1, 0});
+        roots.push_back({0, 0, 0, 0, 0, 1, 0, kings});
         return roots;
     }
     const uint32_t half = n / 2;
@@ -78,12 +91,13 @@ std::vector<Root> frontier_roots(uint32_t n, uint32_t depth) {
         if (depth >= 3) {
             uint32_t v = last & ~(c | l | r);
             while (v) {
-                uint32_t q = v & (0u - v);
+                uint32_t q = v & (0u - v), nc, nl, nr;
                 v ^= q;
-                roots.push_back({c | q, (l | q) << 1, (r | q) >> 1, 2, (int)depth - 2, 2, c0});
+                child(kings, c, l, r, q, nc, nl, nr);
+                roots.push_back({nc, nl, nr, 2, (int)depth - 2, 2, c0, kings});
             }
         } else {
-            roots.push_back({c, l, r, 1, (int)depth - 1, 2, c0});
+            roots.push_back({c, l, r, 1, (int)depth - 1, 2, c0, kings});
         }
     }
     if (n % 2 == 1) {
@@ -91,15 +105,16 @@ std::vector<Root> frontier_roots(uint32_t n, uint32_t depth) {
         uint32_t p = 1u << m;
         uint32_t c = p, l = p << 1, r = p >> 1;
         if (depth == 1) {
-            roots.push_back({c, l, r, 1, 0, 1, m});
+            roots.push_back({c, l, r, 1, 0, 1, m, kings});
         } else {
             // Row 1 restricted to columns 0..m-2: the mirror images of the
             // columns right of the centre (Section 1 and its footnote).
             uint32_t v = last & ~(c | l | r) & ((m >= 2) ? ((1u << (m - 1)) - 1u) : 0u);
             while (v) {
-                uint32_t q = v & (0u - v);
+                uint32_t q = v & (0u - v), nc, nl, nr;
                 v ^= q;
-                roots.push_back({c | q, (l | q) << 1, (r | q) >> 1, 2, (int)depth - 2, 2, m});
+                child(kings, c, l, r, q, nc, nl, nr);
+                roots.push_back({nc, nl, nr, 2, (int)depth - 2, 2, m, kings});
             }
         }
     }
@@ -108,12 +123,12 @@ std::vector<Root> frontier_roots(uint32_t n, uint32_t depth) {
 
 uint64_t root_size(uint32_t n, const Root& rt) {
     const uint32_t last = (1u << n) - 1u;
-    return expand_count(last, rt.rows_left, rt.cols, rt.ld, rt.rd);
+    return expand_count(last, rt.kings, rt.rows_left, rt.cols, rt.ld, rt.rd);
 }
 
 void root_fill(uint32_t n, const Root& rt, uint32_t* cols, uint32_t* ld, uint32_t* rd,
                uint8_t* weight) {
-    Sink s{cols, ld, rd, weight, 0, (1u << n) - 1u, rt.weight};
+    Sink s{cols, ld, rd, weight, 0, (1u << n) - 1u, rt.weight, rt.kings};
     expand_fill(s, rt.rows_left, rt.cols, rt.ld, rt.rd);
 }
 
@@ -149,9 +164,9 @@ std::vector<uint64_t> root_offsets(uint32_t n, const std::vector<Root>& roots) {
 
 int frontier_fill(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld, uint32_t* rd,
                   uint8_t* weight, uint64_t capacity, uint64_t* out_len,
-                  std::vector<uint64_t>* first_row_offsets) {
+                  std::vector<uint64_t>* first_row_offsets, bool kings) {
     if (n < 1 || n > NQ_MAX_N || depth > n || !out_len) return NQ_EINVAL;
-    std::vector<Root> roots = frontier_roots(n, depth);
+    std::vector<Root> roots = frontier_roots(n, depth, kings);
     std::vector<uint64_t> off = root_offsets(n, roots);
     const uint64_t total = off.back();
     *out_len = total;
@@ -218,6 +233,17 @@ extern "C" int nq_frontier(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t*
                            uint64_t* out_len) {
     try {
         return nqi::frontier_fill(n, depth, cols, ld, rd, weight, capacity, out_len, nullptr);
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
+}
+
+extern "C" int nq_kings_frontier(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld,
+                                 uint32_t* rd, uint8_t* weight, uint64_t capacity,
+                                 uint64_t* out_len) {
+    try {
+        return nqi::frontier_fill(n, depth, cols, ld, rd, weight, capacity, out_len, nullptr,
+                                  true);
     } catch (...) {
         return NQ_ENOMEM;
     }

@@ -10,16 +10,18 @@ namespace nqi {
 
 // One starting point of the frontier enumeration: the Somers triple after the
 // first `row` rows, the rows still to place before the frontier depth, the
-// weight every entry below it carries, and its row-0 column.
+// weight every entry below it carries, its row-0 column, and the search (the
+// kings search keeps only the last king's neighbours in ld / rd).
 struct Root {
     uint32_t cols, ld, rd;
     int row;
     int rows_left;
     uint8_t weight;
     uint32_t first_col;
+    bool kings;
 };
 
-std::vector<Root> frontier_roots(uint32_t n, uint32_t depth);
+std::vector<Root> frontier_roots(uint32_t n, uint32_t depth, bool kings = false);
 uint64_t root_size(uint32_t n, const Root& rt);
 std::vector<uint64_t> root_offsets(uint32_t n, const std::vector<Root>& roots);
 
@@ -27,7 +29,7 @@ std::vector<uint64_t> root_offsets(uint32_t n, const std::vector<Root>& roots);
 // each row-0 column's run of entries followed by the total.
 int frontier_fill(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld, uint32_t* rd,
                   uint8_t* weight, uint64_t capacity, uint64_t* out_len,
-                  std::vector<uint64_t>* first_row_offsets);
+                  std::vector<uint64_t>* first_row_offsets, bool kings = false);
 
 // Arguments of the DFS kernels (passed by value).
 struct DfsParams {
@@ -88,6 +90,7 @@ struct LaunchCfg {
     bool leafctr;           // row counter in the high bits of cols (see the kernel)
     bool serve;             // serving epoch: per-request retirement (P.remaining set)
     int form;               // inner-loop form the launch was planned for
+    bool kings;             // the kings search (NQ_FLAG_KINGS)
 };
 
 // Sets the inner-loop form of the DFS launches planned from now on (-1 = the
@@ -116,10 +119,11 @@ struct DeviceInfo {
 int device_info(DeviceInfo* out);
 
 // Fills `cfg` for `len` entries needing `frames` frames per lane; `serve`
-// plans a serving epoch (persistent, leafctr, no statistics only).
+// plans a serving epoch (persistent, leafctr, no statistics only), `kings` a
+// launch of the kings search (default inner-loop form only).
 int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t waves_per_cu,
                 uint32_t frames, uint64_t len, bool stats, bool leafctr, LaunchCfg* cfg,
-                bool serve = false);
+                bool serve = false, bool kings = false);
 
 // Enqueues the DFS kernel (and, for the persistent mode, the zeroing of
 // *P.head) on `stream`.  Returns NQ_OK or NQ_EDEVICE.

@@ -178,3 +178,34 @@ def test_resumable_count_file_handling_without_a_gpu(tmp_path):
     with open(path, "w") as f:
         f.write(_progress_record(12, 4, 4, 8, 8, 14200))
     assert nq.count_resumable(12, path, chunks=8, depth=4) == (14200, 8, True)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 11, 13, 16])
+def test_kings_frontier_matches_oracle(n):
+    """nq_kings_frontier (bitmask enumeration) against the kings oracle (board
+    arrays): the same prefixes in the same order, masks by definition, weights."""
+    for k in sorted({1, 2, 3, min(n, 5)} | ({n} if n <= 8 else set())):
+        if k > n:
+            continue
+        c, l, r, w = nq.frontier(n, k, kings=True)
+        pre, pw = oracle.kings_frontier(n, k)
+        assert len(c) == len(pre), (n, k)
+        if len(pre):
+            oc, ol, orr = oracle.kings_prefixes_masks(n, pre)
+            np.testing.assert_array_equal(c, oc)
+            np.testing.assert_array_equal(l, ol)
+            np.testing.assert_array_equal(r, orr)
+            np.testing.assert_array_equal(w, pw)
+
+
+def test_kings_flag_refused_where_unsupported(tmp_path):
+    """Resumable counts refuse the kings search before touching any file or device."""
+    with pytest.raises(nq.NQError):
+        nq._native.lib()
+        o = nq._native._opts(3, "persistent", 0, 0, 0, None, nq._native.FLAG_KINGS, 0)
+        import ctypes as c_
+        t, d = c_.c_uint64(), c_.c_uint32()
+        rc = nq._native.lib().nq_count_resumable(12, c_.byref(o), str(tmp_path / "p").encode(), 4,
+                                                  0, c_.byref(t), c_.byref(d))
+        nq._native._check(rc, "nq_count_resumable")
+    assert not (tmp_path / "p").exists()
