@@ -15,7 +15,8 @@ unless --depth is given.  Frontiers deeper than 8 rows are built on the host at
 depth k-2 and expanded on the device (nq_expand) before the timed region.  Printed: one JSON line with the metric, the "plain"
 form (one launch per row-0 column over the same frontier), the end-to-end
 nq_count wall time, the int-ALU roofline of the DFS kernel, the ragged
-256-instance batch (one graph replay), one GPU's share of an N=21 count
+256-instance batch (one graph replay), the kings search (a second DFS on the
+same engine, n = 16), one GPU's share of an N=21 count
 dealt round-robin over 8 GPUs (all 8 shares run in turn; their totals must add
 up to Q(21)), the serving loop at a few request rates (p50/p99 latency,
 throughput) and the oracle timed on the host cores.
@@ -152,6 +153,29 @@ def bench_shards(nq, torch, known, shares=8, n=21, k=6, deepen=3):
     return {"n": n, "frontier_depth": k, "shares": shares, "search_depth": k + deepen,
             "split": "round-robin over the frontier", "share_ms": ms, "share_subproblems": entries,
             "max_over_mean": max(ms) / (sum(ms) / len(ms)), "sum_exact": True}
+
+
+def kings_count(n):
+    """The king-placement count a(n) from a(0..3) = 1, 1, 0, 0 by its recurrence
+    (pinned against the kings oracle in tests/test_oracle_kings.py)."""
+    a = [1, 1, 0, 0]
+    for m in range(4, n + 1):
+        a.append((m + 1) * a[m - 1] - (m - 2) * a[m - 2] - (m - 5) * a[m - 3] + (m - 3) * a[m - 4])
+    return a[n]
+
+
+def bench_kings(nq, n=16):
+    """The second search on the same engine: n non-attacking kings, one per row
+    and column, automatic depth (host frontier), one persistent launch."""
+    want = kings_count(n)
+    best = None
+    for _ in range(2):
+        got, ms = nq.count(n, kings=True, timing=True)
+        if got != want:
+            raise SystemExit(f"bench.py: kings({n}) = {got}, not {want}")
+        best = ms if best is None else min(best, ms)
+    return {"n": n, "solutions": want, "kernel_ms": best, "solutions_per_s": want / (best / 1e3),
+            "exact": True, "form": "kings search on the queens lane-stack engine (NQ_FLAG_KINGS)"}
 
 
 def bench_serving(nq, known, rates, seconds):
@@ -477,6 +501,8 @@ def main():
     if not args.no_batch:
         print("[bench] ragged batch (256 instances)", file=sys.stderr, flush=True)
         out["batch"] = bench_batch(nq, known)
+    print("[bench] kings search (second DFS workload)", file=sys.stderr, flush=True)
+    out["kings"] = bench_kings(nq)
     if not args.no_shards:
         print("[bench] one GPU's share of N=21 over 8 GPUs", file=sys.stderr, flush=True)
         out["shard"] = bench_shards(nq, torch, known)
