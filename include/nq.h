@@ -190,7 +190,10 @@ typedef struct nq_opts {
  * frontier order (NQ_ERANGE if counts_capacity < F).  n in [1, 28].
  * opts->depth == 0 selects the depth nq_autotune found for n in this process,
  * else the shallowest depth whose frontier has at least 2^29 entries (at most
- * n - 4, and under 2^32 entries).
+ * n - 4, and under 2^32 entries).  With NQ_FLAG_KINGS the kings frontier
+ * (nq_kings_frontier) is built on the host only, at opts->depth or by default
+ * the shallowest depth with at least 2^22 entries (at most n - 2 and 2^27
+ * entries).
  */
 int nq_count(uint32_t n, const nq_opts* opts, uint64_t* out_total);
 
