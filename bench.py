@@ -74,9 +74,9 @@ def kernel_digest():
     return h.hexdigest()
 
 
-def profiled_traffic(n, k):
-    """HBM bytes per launch of the default persistent DFS kernel at (n, k) from
-    the committed counter summary (profiles/), or None when there is none, when
+def profiled_counters(n, k):
+    """The counter record of the default persistent DFS kernel at (n, k) from the
+    committed summary (profiles/), as a dict, or None when there is none, when
     the kernel's source, header or build flags have changed since the counters
     were taken (the summary records their kernel_digest), or when an environment
     override selects another kernel form or scheduler setting."""
@@ -90,9 +90,31 @@ def profiled_traffic(n, k):
                 if not line.startswith("counters:"):
                     continue
                 kv = dict(x.split("=", 1) for x in line.split()[1:] if "=" in x)
-                if (kv.get("kernel_sha256") == digest and int(kv.get("n", -1)) == n and int(kv.get("depth", -1)) == k):
-                    return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+                if (kv.get("kernel_sha256") == digest and int(kv.get("n", -1)) == n and
+                        int(kv.get("depth", -1)) == k):
+                    kv["source"] = os.path.relpath(path, ROOT)
+                    return kv
     return None
+
+
+def profiled_traffic(n, k):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the
+    committed counters, or None (see profiled_counters)."""
+    kv = profiled_counters(n, k)
+    return int(kv["fetch_bytes"]) + int(kv["write_bytes"]) if kv else None
+
+
+def profiled_executed(n, k):
+    """VALU lane-operations the kernel executed per second under the counters
+    (SQ_THREAD_CYCLES_VALU, the active lanes summed over its VALU instructions,
+    over the duration of the same profiled dispatch), against the same int32
+    peak, or None.  Beside `achieved` (the algorithmic operations) it shows how
+    much of the issued work is overhead."""
+    kv = profiled_counters(n, k)
+    if not kv or "valu_lane_ops" not in kv:
+        return None
+    rate = int(kv["valu_lane_ops"]) / (int(kv["kernel_ns"]) / 1e9)
+    return {"lane_ops_per_s": rate, "frac": rate / INT_PEAK, "source": kv["source"]}
 
 
 def known_counts():
@@ -491,6 +513,7 @@ def main():
         out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK / 1e12,
                            "unit": "Tint32op/s", "frac": achieved / INT_PEAK,
                            "traffic": profiled_traffic(N, k),
+                           "executed": profiled_executed(N, k),
                            "ops_per_node": OPS_PER_NODE, "kernel_ms": kern_ms}
     out["launch"] = {"waves_per_cu": args.waves_per_cu, "refill_every": args.refill,
                      "claim": args.claim,
