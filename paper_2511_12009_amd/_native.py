@@ -170,9 +170,11 @@ def _stream_handle(stream):
     return getattr(stream, "cuda_stream", stream)
 
 
-def frontier_size(n: int, depth: int) -> int:
+def frontier_size(n: int, depth: int, kings: bool = False) -> int:
+    """F of the (n, depth) frontier (kings=True: of the kings search)."""
+    fn = lib().nq_kings_frontier if kings else lib().nq_frontier
     ln = ct.c_uint64()
-    _check(lib().nq_frontier(n, depth, None, None, None, None, 0, ct.byref(ln)), "nq_frontier")
+    _check(fn(n, depth, None, None, None, None, 0, ct.byref(ln)), "frontier size")
     return ln.value
 
 
@@ -190,9 +192,8 @@ def frontier(n: int, depth: int, kings: bool = False):
     """(cols, ld, rd) uint32[F] and weight uint8[F] in canonical order (host arrays);
     kings=True: the kings search's frontier (nq_kings_frontier)."""
     fn = lib().nq_kings_frontier if kings else lib().nq_frontier
+    f = frontier_size(n, depth, kings)
     ln = ct.c_uint64()
-    _check(fn(n, depth, None, None, None, None, 0, ct.byref(ln)), "frontier size")
-    f = ln.value
     cols = np.zeros(max(f, 1), np.uint32)
     ld = np.zeros(max(f, 1), np.uint32)
     rd = np.zeros(max(f, 1), np.uint32)
@@ -235,12 +236,10 @@ def count(n: int, depth: int = 0, mode="persistent", wg_size: int = 0, waves_per
               stream if stream is None else _stream_handle(stream),
               (FLAG_FORWARD_ORDER if forward else 0) | (FLAG_KINGS if kings else 0), claim)
     buf = None
-    size = (lambda: len(frontier(n, depth, kings=True)[0])) if kings else \
-        (lambda: frontier_size(n, depth))
     if counts:
         if depth == 0:
             raise ValueError("counts=True needs an explicit depth")
-        buf = np.zeros(max(size(), 1), np.uint64)
+        buf = np.zeros(max(frontier_size(n, depth, kings), 1), np.uint64)
         o.counts_out = buf.ctypes.data_as(ct.POINTER(ct.c_uint64))
         o.counts_capacity = len(buf)
     ms = ct.c_double(0.0)
@@ -250,7 +249,7 @@ def count(n: int, depth: int = 0, mode="persistent", wg_size: int = 0, waves_per
     _check(lib().nq_count(n, ct.byref(o), ct.byref(total)), "nq_count")
     out = [total.value]
     if counts:
-        out.append(buf[:size()])
+        out.append(buf[:frontier_size(n, depth, kings)])
     if timing:
         out.append(ms.value)
     return out[0] if len(out) == 1 else tuple(out)

@@ -1,6 +1,7 @@
 // C-ABI entry points: status text, nq_count, nq_count_subproblems, nq_count_batch,
 // nq_count_resumable.
 #include <hip/hip_runtime.h>
+#include <fcntl.h>
 #include <unistd.h>
 
 #include <algorithm>
@@ -517,6 +518,16 @@ int progress_write(const char* path, const Progress& p) {
               fsync(fileno(f)) == 0;
     ok = (std::fclose(f) == 0) && ok;
     if (!ok || std::rename(tmp.c_str(), path) != 0) return NQ_EINVAL;
+    // make the rename itself durable: flush the directory that holds the file
+    const std::string full(path);
+    const size_t slash = full.find_last_of('/');
+    const std::string dir =
+        slash == std::string::npos ? "." : (slash == 0 ? "/" : full.substr(0, slash));
+    const int dfd = open(dir.c_str(), O_RDONLY | O_DIRECTORY);
+    if (dfd >= 0) {
+        (void)fsync(dfd);
+        close(dfd);
+    }
     return NQ_OK;
 }
 
