@@ -108,6 +108,11 @@ uint32_t auto_depth(uint32_t n) {
     return std::max<uint32_t>(1, k);
 }
 
+// Boards whose automatic count runs in chunks (measured: N = 22 in 79.9 s at
+// depth 11 in 64 chunks against 86.4 s for the whole depth-9 frontier; N = 23
+// in 753 s at depth 11, which beat depths 9 and 10 on the same chunk).
+constexpr uint32_t kChunkedFirst = 22, kChunkedLast = 23, kChunkedDepth = 11, kChunkedChunks = 64;
+
 // The kings search's automatic depth: the shallowest whose host frontier has
 // at least 2^22 entries (kept on the host, so at most 2^27), at most n - 2.
 uint32_t kings_auto_depth(uint32_t n) {
@@ -312,6 +317,62 @@ int build_device_frontier_at(uint32_t n, uint32_t host_depth, uint32_t rows, voi
     return NQ_OK;
 }
 
+// Counts chunks first.. of the (n, depth) count: chunk i is the range
+// [F*i/chunks, F*(i+1)/chunks) of the host frontier of host_depth, deepened
+// on the device in equal steps of up to three rows and searched by one
+// launch.  At most max_run chunks (0 = all the rest); after each one
+// on_chunk(chunks done, its weighted count) is called, and a status other
+// than NQ_OK from it stops the loop.  kernel_ms (nullable) accumulates the
+// DFS kernel time.
+template <class OnChunk>
+int count_chunks(uint32_t n, const nq_opts& local, uint32_t depth, uint32_t host_depth,
+                 uint32_t chunks, uint32_t first, uint32_t max_run, double* kernel_ms,
+                 OnChunk&& on_chunk) {
+    uint64_t Fh = 0;
+    int rc = frontier_fill(n, host_depth, nullptr, nullptr, nullptr, nullptr, 0, &Fh, nullptr);
+    if (rc != NQ_OK) return rc;
+    std::vector<uint32_t> hc(Fh), hl(Fh), hr(Fh);
+    std::vector<uint8_t> hw(Fh);
+    if ((rc = frontier_fill(n, host_depth, hc.data(), hl.data(), hr.data(), hw.data(), Fh, &Fh,
+                            nullptr)) != NQ_OK)
+        return rc;
+    hipStream_t s = (hipStream_t)local.stream;
+    DevBuf tot;
+    if ((rc = tot.alloc(8)) != NQ_OK) return rc;
+    auto* d_total = tot.as<unsigned long long>();
+    uint32_t ran = 0;
+    for (uint32_t i = first; i < chunks && (max_run == 0 || ran < max_run); ++i, ++ran) {
+        const uint64_t lo = Fh * i / chunks, hi = Fh * (i + 1) / chunks;
+        uint64_t part = 0;
+        if (hi > lo) {
+            DeviceFrontier cur;
+            if ((rc = alloc_frontier(hi - lo, &cur)) != NQ_OK) return rc;
+            NQ_HIP(hipMemcpyAsync(cur.cols, hc.data() + lo, (hi - lo) * 4, hipMemcpyHostToDevice, s));
+            NQ_HIP(hipMemcpyAsync(cur.ld, hl.data() + lo, (hi - lo) * 4, hipMemcpyHostToDevice, s));
+            NQ_HIP(hipMemcpyAsync(cur.rd, hr.data() + lo, (hi - lo) * 4, hipMemcpyHostToDevice, s));
+            NQ_HIP(hipMemcpyAsync(cur.w, hw.data() + lo, hi - lo, hipMemcpyHostToDevice, s));
+            for (uint32_t have = host_depth; have < depth;) {
+                const uint32_t left = depth - have, steps = (left + 2) / 3;
+                const uint32_t rows = (left + steps - 1) / steps;
+                DeviceFrontier next;
+                if ((rc = expand_frontier(n, cur, rows, s, &next, nullptr)) != NQ_OK) return rc;
+                cur = std::move(next);
+                have += rows;
+            }
+            double ms = 0.0;
+            if ((rc = launch_zero_u64(d_total, 1, s)) != NQ_OK) return rc;
+            if ((rc = run_device(n, cur.cols, cur.ld, cur.rd, cur.w, cur.len, nullptr, d_total,
+                                 depth, &local, kernel_ms ? &ms : nullptr)) != NQ_OK)
+                return rc;
+            NQ_HIP(hipMemcpyAsync(&part, d_total, 8, hipMemcpyDeviceToHost, s));
+            NQ_HIP(hipStreamSynchronize(s));
+            if (kernel_ms) *kernel_ms += ms;
+        }
+        if ((rc = on_chunk(i + 1, part)) != NQ_OK) return rc;
+    }
+    return NQ_OK;
+}
+
 }  // namespace nqi
 
 using namespace nqi;
@@ -393,8 +454,32 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
             if (!local.claim) local.claim = t.claim;
         }
     }
+    const bool auto_pick = local.depth == 0;          // neither the caller nor the tuner chose
     const uint32_t depth = local.depth ? local.depth : kings ? kings_auto_depth(n) : auto_depth(n);
     if (depth > n) return NQ_EINVAL;
+    if (auto_pick && !kings && kChunkedFirst <= n && n <= kChunkedLast && !local.counts_out &&
+        opt_mode(opts) == NQ_MODE_PERSISTENT) {
+        // A whole frontier deep enough for these boards does not fit in device
+        // memory; chunks of the depth-5 frontier deepened to kChunkedDepth do
+        // (as nq_count_resumable, without a progress file).
+        try {
+            uint64_t total = 0;
+            double ms = 0.0;
+            local.depth = kChunkedDepth;
+            int rc = count_chunks(n, local, kChunkedDepth, 5, kChunkedChunks, 0, 0,
+                                  opts_in && opts_in->kernel_ms_out ? &ms : nullptr,
+                                  [&](uint32_t, uint64_t part) {
+                                      total += part;
+                                      return (int)NQ_OK;
+                                  });
+            if (rc != NQ_OK) return rc;
+            if (opts_in && opts_in->kernel_ms_out) *opts_in->kernel_ms_out = ms;
+            *out_total = total;
+            return NQ_OK;
+        } catch (const std::bad_alloc&) {
+            return NQ_ENOMEM;
+        }
+    }
     try {
         hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
         DeviceFrontier fr;
@@ -572,55 +657,13 @@ extern "C" int nq_count_resumable(uint32_t n, const nq_opts* opts_in, const char
             pr = old;
         }
         if (pr.done < pr.chunks) {
-            uint64_t Fh = 0;
-            if ((rc = frontier_fill(n, pr.host_depth, nullptr, nullptr, nullptr, nullptr, 0, &Fh,
-                                    nullptr)) != NQ_OK)
-                return rc;
-            std::vector<uint32_t> hc(Fh), hl(Fh), hr(Fh);
-            std::vector<uint8_t> hw(Fh);
-            if ((rc = frontier_fill(n, pr.host_depth, hc.data(), hl.data(), hr.data(), hw.data(),
-                                    Fh, &Fh, nullptr)) != NQ_OK)
-                return rc;
-            hipStream_t s = (hipStream_t)local.stream;
-            DevBuf tot;
-            if ((rc = tot.alloc(8)) != NQ_OK) return rc;
-            auto* d_total = tot.as<unsigned long long>();
-            uint32_t ran = 0;
-            while (pr.done < pr.chunks && (max_chunks == 0 || ran < max_chunks)) {
-                const uint64_t lo = Fh * pr.done / pr.chunks, hi = Fh * (pr.done + 1) / pr.chunks;
-                uint64_t part = 0;
-                if (hi > lo) {
-                    // this chunk's host entries, deepened on the device as nq_count does
-                    DeviceFrontier cur;
-                    if ((rc = alloc_frontier(hi - lo, &cur)) != NQ_OK) return rc;
-                    NQ_HIP(hipMemcpyAsync(cur.cols, hc.data() + lo, (hi - lo) * 4,
-                                          hipMemcpyHostToDevice, s));
-                    NQ_HIP(hipMemcpyAsync(cur.ld, hl.data() + lo, (hi - lo) * 4,
-                                          hipMemcpyHostToDevice, s));
-                    NQ_HIP(hipMemcpyAsync(cur.rd, hr.data() + lo, (hi - lo) * 4,
-                                          hipMemcpyHostToDevice, s));
-                    NQ_HIP(hipMemcpyAsync(cur.w, hw.data() + lo, hi - lo, hipMemcpyHostToDevice, s));
-                    for (uint32_t have = pr.host_depth; have < depth;) {
-                        const uint32_t left = depth - have, steps = (left + 2) / 3;
-                        const uint32_t rows = (left + steps - 1) / steps;
-                        DeviceFrontier next;
-                        if ((rc = expand_frontier(n, cur, rows, s, &next, nullptr)) != NQ_OK)
-                            return rc;
-                        cur = std::move(next);
-                        have += rows;
-                    }
-                    if ((rc = launch_zero_u64(d_total, 1, s)) != NQ_OK) return rc;
-                    if ((rc = run_device(n, cur.cols, cur.ld, cur.rd, cur.w, cur.len, nullptr,
-                                         d_total, depth, &local, nullptr)) != NQ_OK)
-                        return rc;
-                    NQ_HIP(hipMemcpyAsync(&part, d_total, 8, hipMemcpyDeviceToHost, s));
-                    NQ_HIP(hipStreamSynchronize(s));
-                }
-                pr.total += part;
-                pr.done += 1;
-                if ((rc = progress_write(path, pr)) != NQ_OK) return rc;
-                ++ran;
-            }
+            rc = count_chunks(n, local, depth, pr.host_depth, pr.chunks, pr.done, max_chunks,
+                              nullptr, [&](uint32_t done, uint64_t part) {
+                                  pr.total += part;
+                                  pr.done = done;
+                                  return progress_write(path, pr);
+                              });
+            if (rc != NQ_OK) return rc;
         }
         *out_done = pr.done;
         *out_total = pr.total;
