@@ -478,6 +478,8 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
             return NQ_OK;
         } catch (const std::bad_alloc&) {
             return NQ_ENOMEM;
+        } catch (...) {
+            return NQ_EINVAL;
         }
     }
     try {
