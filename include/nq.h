@@ -190,10 +190,12 @@ typedef struct nq_opts {
  * frontier order (NQ_ERANGE if counts_capacity < F).  n in [1, 28].
  * opts->depth == 0 selects the depth nq_autotune found for n in this process,
  * else the shallowest depth whose frontier has at least 2^29 entries (at most
- * n - 4, and under 2^32 entries); for n = 22 and 23, whose best depth has a
- * frontier too large for device memory, the automatic count runs as 64 chunks
- * of the depth-5 frontier deepened to depth 11 (as nq_count_resumable, without
- * a file; persistent mode, no per-entry counts).  With NQ_FLAG_KINGS the kings frontier
+ * n - 4, and under 2^32 entries); for n = 21, 22 and 23, whose best depth
+ * has a frontier too large (or not worth building whole), the automatic count
+ * runs in chunks of the depth-5 frontier deepened on the device (n = 21: 16
+ * chunks to depth 10; 22 and 23: 64 chunks to depth 11), as
+ * nq_count_resumable does without a file (persistent mode, no per-entry
+ * counts).  With NQ_FLAG_KINGS the kings frontier
  * (nq_kings_frontier) is built on the host only, at opts->depth or by default
  * the shallowest depth with at least 2^22 entries (at most n - 2 and 2^27
  * entries).

@@ -108,10 +108,19 @@ uint32_t auto_depth(uint32_t n) {
     return std::max<uint32_t>(1, k);
 }
 
-// Boards whose automatic count runs in chunks (measured: N = 22 in 79.9 s at
-// depth 11 in 64 chunks against 86.4 s for the whole depth-9 frontier; N = 23
-// in 753 s at depth 11, which beat depths 9 and 10 on the same chunk).
-constexpr uint32_t kChunkedFirst = 22, kChunkedLast = 23, kChunkedDepth = 11, kChunkedChunks = 64;
+// Boards whose automatic count runs in chunks, with the depth and chunk count
+// measured best: N = 21 at depth 10 in 16 chunks (8.86 s against 9.0 s for the
+// whole depth-9 frontier), N = 22 at depth 11 in 64 chunks (79.9 s against
+// 86.4 s), N = 23 at depth 11 in 64 chunks (753 s; depth 11 beat 9 and 10 on
+// the same chunk).
+struct ChunkPlan { uint32_t n, depth, chunks; };
+constexpr ChunkPlan kChunkPlans[] = {{21, 10, 16}, {22, 11, 64}, {23, 11, 64}};
+
+const ChunkPlan* chunk_plan(uint32_t n) {
+    for (const ChunkPlan& p : kChunkPlans)
+        if (p.n == n) return &p;
+    return nullptr;
+}
 
 // The kings search's automatic depth: the shallowest whose host frontier has
 // at least 2^22 entries (kept on the host, so at most 2^27), at most n - 2.
@@ -457,16 +466,16 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
     const bool auto_pick = local.depth == 0;          // neither the caller nor the tuner chose
     const uint32_t depth = local.depth ? local.depth : kings ? kings_auto_depth(n) : auto_depth(n);
     if (depth > n) return NQ_EINVAL;
-    if (auto_pick && !kings && kChunkedFirst <= n && n <= kChunkedLast && !local.counts_out &&
-        opt_mode(opts) == NQ_MODE_PERSISTENT) {
+    const ChunkPlan* plan = chunk_plan(n);
+    if (auto_pick && !kings && plan && !local.counts_out && opt_mode(opts) == NQ_MODE_PERSISTENT) {
         // A whole frontier deep enough for these boards does not fit in device
-        // memory; chunks of the depth-5 frontier deepened to kChunkedDepth do
+        // memory; chunks of the depth-5 frontier deepened to plan->depth do
         // (as nq_count_resumable, without a progress file).
         try {
             uint64_t total = 0;
             double ms = 0.0;
-            local.depth = kChunkedDepth;
-            int rc = count_chunks(n, local, kChunkedDepth, 5, kChunkedChunks, 0, 0,
+            local.depth = plan->depth;
+            int rc = count_chunks(n, local, plan->depth, 5, plan->chunks, 0, 0,
                                   opts_in && opts_in->kernel_ms_out ? &ms : nullptr,
                                   [&](uint32_t, uint64_t part) {
                                       total += part;
