@@ -372,7 +372,7 @@ def main():
     ap.add_argument("--depth", type=int, default=0, help="0 = autotune over 6..10")
     ap.add_argument("--tune-ms", type=float, default=40000.0)
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--serve-rates", default="25,100", help="COUNT requests/s, comma list")
+    ap.add_argument("--serve-rates", default="25,100,200", help="COUNT requests/s, comma list")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
