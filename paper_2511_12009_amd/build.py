@@ -15,6 +15,8 @@ LIB = os.path.join(HERE, "libnq.so")
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# Marker ranges (nq_trace.h) come from the profiler SDK's roctx library.
+ROCM_LIB = "/opt/rocm/lib"
 # Packed FP32 instructions are kept out of every code object.  Loops start on
 # a 64-byte instruction-cache line: the DFS step loop is 192 bytes, three lines
 # when aligned; where it started 4 bytes before a line boundary the N = 20
@@ -47,8 +49,8 @@ def build(verbose: bool = False, asm_dir: str = None) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile_one(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread"] + objs + ["-o", tmp],
-         verbose)
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread"] + objs +
+         ["-L", ROCM_LIB, f"-Wl,-rpath,{ROCM_LIB}", "-lrocprofiler-sdk-roctx", "-o", tmp], verbose)
     os.replace(tmp, LIB)
     if asm_dir:
         os.makedirs(asm_dir, exist_ok=True)

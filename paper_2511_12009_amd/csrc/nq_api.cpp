@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "nq_internal.h"
+#include "nq_trace.h"
 
 namespace nqi {
 
@@ -234,6 +235,7 @@ int host_frontier(uint32_t n, uint32_t depth, hipStream_t s, DeviceFrontier* out
 // of every entry of `in` (offsets[in.len] = out->len).
 int expand_frontier(uint32_t n, const DeviceFrontier& in, uint32_t rows, hipStream_t s,
                     DeviceFrontier* out, std::vector<uint64_t>* offsets) {
+    TraceRange t("expand");
     if (in.len == 0) {                            // nothing to expand
         if (offsets) offsets->assign(1, 0);
         out->first_row.assign(in.first_row.size(), 0);
@@ -353,6 +355,7 @@ int count_chunks(uint32_t n, const nq_opts& local, uint32_t depth, uint32_t host
     for (uint32_t i = first; i < chunks && (max_run == 0 || ran < max_run); ++i, ++ran) {
         const uint64_t lo = Fh * i / chunks, hi = Fh * (i + 1) / chunks;
         uint64_t part = 0;
+        TraceRange chunk_range("chunk");
         if (hi > lo) {
             DeviceFrontier cur;
             if ((rc = alloc_frontier(hi - lo, &cur)) != NQ_OK) return rc;
@@ -492,11 +495,16 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
         }
     }
     try {
+        TraceRange whole("nq_count");
         hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
         DeviceFrontier fr;
         // the kings frontier is built on the host only (nq_expand follows the
         // queens' recurrence)
-        int rc = kings ? host_frontier(n, depth, s, &fr, true) : build_device_frontier(n, depth, s, &fr);
+        int rc;
+        {
+            TraceRange t("frontier");
+            rc = kings ? host_frontier(n, depth, s, &fr, true) : build_device_frontier(n, depth, s, &fr);
+        }
         if (rc != NQ_OK) return rc;
         const uint64_t F = fr.len;
         const std::vector<uint64_t>& first_row = fr.first_row;
@@ -512,6 +520,7 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
         if ((rc = launch_zero_u64(d_total, 1, s)) != NQ_OK) return rc;
         const uint32_t mode = opt_mode(opts);
         double ms = 0.0, ms_part = 0.0;
+        TraceRange dfs_range("dfs");
         if (mode == NQ_MODE_PLAIN) {
             // One launch per row-0 column (the form the paper's host driver uses
             // per GPU slice), each over its contiguous run of the frontier.
@@ -529,6 +538,7 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
             if (rc != NQ_OK) return rc;
         }
         uint64_t total = 0;
+        TraceRange result_range("result");
         NQ_HIP(hipMemcpyAsync(&total, d_total, 8, hipMemcpyDeviceToHost, s));
         if (want_counts && F)
             NQ_HIP(hipMemcpyAsync(opts->counts_out, d_counts, F * 8, hipMemcpyDeviceToHost, s));

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "nq_internal.h"
+#include "nq_trace.h"
 
 struct nq_batch {
     uint32_t ninst = 0;
@@ -76,6 +77,7 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
         release(b);
         return code;
     };
+    TraceRange trace("batch_create");
     try {
         if ((e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess) {
             set_hip_error(e);
@@ -197,6 +199,7 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
 }
 
 int batch_run(nq_batch* b, uint64_t* out_totals, double* ms) {
+    TraceRange t("batch_run");
     if (!b || (b->ninst && !out_totals)) return NQ_EINVAL;
     hipError_t e;
     hipEvent_t ea = nullptr, eb = nullptr;

@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "nq_internal.h"
+#include "nq_trace.h"
 
 namespace {
 
@@ -239,6 +240,7 @@ void collect(nq_server* s) {
 // HIP calls are made with it held too (they only enqueue work).
 int admit_and_launch(nq_server* s) {
     if (s->pending.empty() || s->free_slots.empty()) return NQ_OK;
+    TraceRange t("epoch");
     Epoch ep;
     const uint64_t epoch_start = s->ring_tail;
     std::vector<uint64_t> taken;
