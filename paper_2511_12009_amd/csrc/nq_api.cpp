@@ -340,13 +340,18 @@ int count_chunks(uint32_t n, const nq_opts& local, uint32_t depth, uint32_t host
                  uint32_t chunks, uint32_t first, uint32_t max_run, double* kernel_ms,
                  OnChunk&& on_chunk) {
     uint64_t Fh = 0;
-    int rc = frontier_fill(n, host_depth, nullptr, nullptr, nullptr, nullptr, 0, &Fh, nullptr);
-    if (rc != NQ_OK) return rc;
-    std::vector<uint32_t> hc(Fh), hl(Fh), hr(Fh);
-    std::vector<uint8_t> hw(Fh);
-    if ((rc = frontier_fill(n, host_depth, hc.data(), hl.data(), hr.data(), hw.data(), Fh, &Fh,
-                            nullptr)) != NQ_OK)
-        return rc;
+    std::vector<uint32_t> hc, hl, hr;
+    std::vector<uint8_t> hw;
+    {
+        TraceRange t("frontier");
+        int rc = frontier_fill(n, host_depth, nullptr, nullptr, nullptr, nullptr, 0, &Fh, nullptr);
+        if (rc != NQ_OK) return rc;
+        hc.resize(Fh); hl.resize(Fh); hr.resize(Fh); hw.resize(Fh);
+        if ((rc = frontier_fill(n, host_depth, hc.data(), hl.data(), hr.data(), hw.data(), Fh,
+                                &Fh, nullptr)) != NQ_OK)
+            return rc;
+    }
+    int rc = NQ_OK;
     hipStream_t s = (hipStream_t)local.stream;
     DevBuf tot;
     if ((rc = tot.alloc(8)) != NQ_OK) return rc;
@@ -475,6 +480,7 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
         // memory; chunks of the depth-5 frontier deepened to plan->depth do
         // (as nq_count_resumable, without a progress file).
         try {
+            TraceRange whole("nq_count (chunked)");
             uint64_t total = 0;
             double ms = 0.0;
             local.depth = plan->depth;
@@ -520,7 +526,7 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
         if ((rc = launch_zero_u64(d_total, 1, s)) != NQ_OK) return rc;
         const uint32_t mode = opt_mode(opts);
         double ms = 0.0, ms_part = 0.0;
-        TraceRange dfs_range("dfs");
+        roctxRangePushA("dfs launch");     // enqueue only: the launches are asynchronous
         if (mode == NQ_MODE_PLAIN) {
             // One launch per row-0 column (the form the paper's host driver uses
             // per GPU slice), each over its contiguous run of the frontier.
@@ -529,16 +535,17 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
                 rc = run_device(n, fr.cols + lo, fr.ld + lo, fr.rd + lo, fr.w + lo, hi - lo,
                                 d_counts ? d_counts + lo : nullptr, d_total, depth, opts,
                                 opts && opts->kernel_ms_out ? &ms_part : nullptr);
-                if (rc != NQ_OK) return rc;
+                if (rc != NQ_OK) break;
                 ms += ms_part;
             }
         } else {
             rc = run_device(n, fr.cols, fr.ld, fr.rd, fr.w, F, d_counts, d_total, depth, opts,
                             opts && opts->kernel_ms_out ? &ms : nullptr);
-            if (rc != NQ_OK) return rc;
         }
+        roctxRangePop();
+        if (rc != NQ_OK) return rc;
         uint64_t total = 0;
-        TraceRange result_range("result");
+        TraceRange result_range("dfs wait and result");
         NQ_HIP(hipMemcpyAsync(&total, d_total, 8, hipMemcpyDeviceToHost, s));
         if (want_counts && F)
             NQ_HIP(hipMemcpyAsync(opts->counts_out, d_counts, F * 8, hipMemcpyDeviceToHost, s));
