@@ -117,3 +117,20 @@ def test_many_tiny_slices_share_waves():
             assert r["status"] == 0
             assert r["entries"] == ln
             assert r["count"] == int(wref[a:a + ln].sum()), (a, ln)
+
+
+def test_requests_beyond_a_small_budget_fail_alone(known_counts):
+    """A server with an 8 MiB budget: a request whose subproblems cannot fit its
+    ring or resident space completes with NQ_ENOMEM in its result, while the
+    small requests around it are still answered exactly."""
+    nq = _nq()
+    with nq.Server(hbm_budget=8 << 20) as srv:
+        _say("small budget")
+        small = [srv.submit_count(n) for n in (8, 10, 11)]
+        big = srv.submit_count(18)
+        more = [srv.submit_count(n) for n in (9, 12)]
+        r = srv.wait(big, timeout_s=60)
+        assert r["status"] == -3                     # NQ_ENOMEM
+        for n, t in zip((8, 10, 11, 9, 12), small + more):
+            r = srv.wait(t, timeout_s=60)
+            assert r["status"] == 0 and r["count"] == known_counts[n], n
