@@ -412,12 +412,15 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         // The frame is kept as one 4-vector so that push and pop move it with
         // a single ds_write_b128 / ds_read_b128 and no register shuffling.
         u32x4 st = {c, l, r, v};
-        // Steps run in chunks of 32 (forms 1 and 2).  After a chunk a wave
-        // returns to the scheduler early when all its lanes have finished
-        // (avail == 0 after a step) or, in persistent mode, once `idle_min` of
-        // them have, so a finished lane waits for at most one chunk instead of
-        // `refill_every` steps.  The trip counts are wave-uniform;
-        // readfirstlane keeps them in SGPRs.
+        // Steps run in chunks (64 steps in form 1, 32 in form 2).  After a
+        // chunk a wave returns to the scheduler early when all its lanes have
+        // finished (avail == 0 after a step) or, in persistent mode, once
+        // `idle_min` of them have, so a finished lane waits for at most one
+        // chunk instead of `refill_every` steps; a chunk's end check costs two
+        // ballots, which 64-step chunks pay half as often as 32-step ones
+        // (N = 20 at k = 9: 995 against 1004 ms; 16 steps: 1021, 128: 995,
+        // 256: 1005).  The trip counts are wave-uniform; readfirstlane keeps
+        // them in SGPRs.
         auto chunk_done = [&](uint32_t avail) {
             const uint32_t idle = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(avail == 0u));
             const uint32_t lanes = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(true));
@@ -454,9 +457,9 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         } else if (LOOP == 1) {
         // The lane masks live in SGPR pairs; the push, the selects, the pop
         // and the leaf count use them directly.
-        uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 31u) / 32u);
+        uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 63u) / 64u);
         for (;;) {
-            uint32_t trips = 32u;
+            uint32_t trips = 64u;
             do {
                 // p = lowest untried column; the untried set keeps its register.
                 uint32_t p, rest = st.w;
