@@ -380,7 +380,7 @@ def main():
     ap.add_argument("--claim", type=int, default=0, help="entries per work-head claim (0 = auto)")
     ap.add_argument("--forward", action="store_true", help="claim entries in frontier order")
     ap.add_argument("--plain-steps", type=int, default=1)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-shards", action="store_true")
     ap.add_argument("--ablation", action="store_true",
