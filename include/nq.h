@@ -20,7 +20,8 @@
  * Conventions for every entry point:
  *   - Return value: NQ_OK (0) or a negative NQ_E* status.  Nothing throws, aborts
  *     or exits.  Outputs are written through pointers and only on NQ_OK, except
- *     where a function says otherwise (nq_frontier with NQ_ERANGE).
+ *     where a function says otherwise (nq_frontier with NQ_ERANGE,
+ *     nq_count_resumable with NQ_EAGAIN).
  *   - Bit j of a mask stands for column j.  Valid board sizes: 1 <= n <= 28
  *     (NQ_MAX_N); larger n is NQ_EINVAL.
  *   - Counts are exact uint64.  Per-subproblem counts are UNWEIGHTED; totals are
@@ -49,7 +50,8 @@ enum nq_status {
     NQ_ERANGE = -2,   /* output buffer too small; *out_len holds the needed size  */
     NQ_ENOMEM = -3,   /* host or device allocation failed, or over a memory cap   */
     NQ_EDEVICE = -4,  /* a HIP call failed; see nq_last_hip_error()              */
-    NQ_EAGAIN = -5,   /* nq_serve_poll: the request is not finished yet           */
+    NQ_EAGAIN = -5,   /* nq_serve_poll: not finished yet; nq_count_resumable:
+                         chunks remain (call again)                               */
     NQ_EFULL = -6,    /* nq_serve_submit: admission refused, retry later          */
     NQ_ENOENT = -7    /* unknown ticket                                           */
 };
