@@ -218,7 +218,10 @@ int nq_count(uint32_t n, const nq_opts* opts, uint64_t* out_total);
  * many queens placed; it sizes the LDS stack (n - 2 - depth frames per lane).
  * A triple with fewer queens is not searched: its d_counts entry is set to
  * UINT64_MAX and it adds nothing to d_total.  Asynchronous on opts->stream
- * (unless kernel_ms_out is set); len == 0 launches nothing.
+ * (unless kernel_ms_out is set); len == 0 launches nothing.  With
+ * NQ_FLAG_KINGS the triples are kings-search triples (nq_kings_frontier: ld /
+ * rd hold only the squares beside the last king) and the counts are king
+ * placements; the same rules for full, last-row and dead entries apply.
  */
 int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
                          const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len,
