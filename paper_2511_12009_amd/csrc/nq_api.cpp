@@ -176,10 +176,10 @@ static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
     P.claim = (opts && opts->claim) ? opts->claim : default_claim(len, cfg);
     P.reverse = (opts && (opts->flags & NQ_FLAG_FORWARD_ORDER)) ? 0u : 1u;
     EventTimer t;
-    if (kernel_ms && (rc = t.start(s)) != NQ_OK) return rc;
-    rc = launch_dfs(cfg, P, s);
+    if (kernel_ms) rc = t.start(s);
+    if (rc == NQ_OK) rc = launch_dfs(cfg, P, s);
     if (rc == NQ_OK && kernel_ms) rc = t.stop(s, kernel_ms);
-    if (head) {
+    if (head) {                                   // freed on every path past its allocation
         hipError_t e = hipFreeAsync(head, s);
         if (e != hipSuccess && rc == NQ_OK) { set_hip_error((int)e); rc = NQ_EDEVICE; }
     }
