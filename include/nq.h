@@ -372,8 +372,12 @@ int nq_batch_destroy(nq_batch* batch);
  * NQ_ENOENT (unknown or already collected ticket).  nq_serve_wait: the same,
  * blocking up to timeout_ns.  Timestamps are CLOCK_MONOTONIC nanoseconds:
  * submit, admission (subproblems enqueued), completion seen by the scheduler.
- * nq_serve_destroy: drops requests not yet admitted, waits for admitted ones,
- * frees everything.  All calls on one server are thread-safe.
+ * After a HIP failure in the server (an epoch that cannot be enqueued or that
+ * ends in a device error) every unfinished request reports that status
+ * (NQ_EDEVICE) instead of NQ_EAGAIN, and submit returns it too.
+ * nq_serve_destroy: drops requests not yet admitted, waits for admitted ones
+ * (not after such a failure), frees everything, and returns the failure's
+ * status or NQ_OK.  All calls on one server are thread-safe.
  */
 enum nq_request_kind { NQ_REQ_COUNT = 1, NQ_REQ_SLICE = 2 };
 typedef struct nq_request {

@@ -228,8 +228,16 @@ void collect(nq_server* s) {
         s->admitted.pop_front();
     }
     if (s->admitted.empty()) s->ring_head = s->ring_tail;
-    // Retire finished epochs' staging buffers.
-    while (!s->epochs.empty() && hipEventQuery(s->epochs.front().done) == hipSuccess) {
+    // Retire finished epochs' staging buffers.  An epoch whose event reports a
+    // device error is retired too, and the error becomes the server's fatal
+    // status: its requests will never publish.
+    while (!s->epochs.empty()) {
+        const hipError_t q = hipEventQuery(s->epochs.front().done);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess && s->fatal == NQ_OK) {
+            set_hip_error(q);
+            s->fatal = NQ_EDEVICE;
+        }
         (void)hipEventDestroy(s->epochs.front().done);
         s->epochs.pop_front();
     }
@@ -375,7 +383,9 @@ void worker_main(nq_server* s) {
             int rc = admit_and_launch(s);
             if (rc != NQ_OK) s->fatal = rc;
         }
-        const bool busy = !s->admitted.empty() || !s->epochs.empty();
+        // After a fatal error nothing admitted is waited for: its results
+        // will not come, and pollers see the error instead.
+        const bool busy = s->fatal == NQ_OK && (!s->admitted.empty() || !s->epochs.empty());
         if (s->stop && !busy) break;
         if (busy) {
             lk.unlock();
@@ -530,9 +540,11 @@ int serve_poll(nq_server* s, uint64_t ticket, nq_result* out, uint64_t wait_ns) 
     if (it->second.state != ReqState::Done && wait_ns) {
         const auto deadline = std::chrono::steady_clock::now() + std::chrono::nanoseconds(wait_ns);
         s->cv.wait_until(lk, deadline, [&] {
-            return s->fatal != NQ_OK || s->reqs.at(ticket).state == ReqState::Done;
+            const auto j = s->reqs.find(ticket);   // another poller may take it
+            return s->fatal != NQ_OK || j == s->reqs.end() || j->second.state == ReqState::Done;
         });
         it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return NQ_ENOENT;
     }
     const Req& r = it->second;
     if (r.state != ReqState::Done) return s->fatal != NQ_OK ? s->fatal : NQ_EAGAIN;
