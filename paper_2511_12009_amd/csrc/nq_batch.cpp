@@ -231,11 +231,19 @@ int batch_run(nq_batch* b, uint64_t* out_totals, double* ms) {
 
 extern "C" int nq_batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths,
                                const nq_opts* opts, nq_batch** out) {
-    return nqi::batch_create(ninst, ns, depths, opts, out);
+    try {
+        return nqi::batch_create(ninst, ns, depths, opts, out);
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
 }
 
 extern "C" int nq_batch_run(nq_batch* b, uint64_t* out_totals, double* kernel_ms) {
-    return nqi::batch_run(b, out_totals, kernel_ms);
+    try {
+        return nqi::batch_run(b, out_totals, kernel_ms);
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
 }
 
 extern "C" uint64_t nq_batch_entries(const nq_batch* b) { return b ? b->entries : 0; }
@@ -251,11 +259,16 @@ extern "C" int nq_count_batch(uint32_t ninst, const uint32_t* ns, const uint32_t
     if (ninst == 0) return NQ_OK;
     if (!ns || !out_totals) return NQ_EINVAL;
     nq_batch* b = nullptr;
-    int rc = nqi::batch_create(ninst, ns, depths, opts, &b);
-    if (rc != NQ_OK) return rc;
-    double ms = 0.0;
-    rc = nqi::batch_run(b, out_totals, opts && opts->kernel_ms_out ? &ms : nullptr);
-    if (rc == NQ_OK && opts && opts->kernel_ms_out) *opts->kernel_ms_out = ms;
-    nqi::release(b);
+    int rc = NQ_OK;
+    try {
+        rc = nqi::batch_create(ninst, ns, depths, opts, &b);
+        if (rc != NQ_OK) return rc;
+        double ms = 0.0;
+        rc = nqi::batch_run(b, out_totals, opts && opts->kernel_ms_out ? &ms : nullptr);
+        if (rc == NQ_OK && opts && opts->kernel_ms_out) *opts->kernel_ms_out = ms;
+    } catch (...) {
+        rc = NQ_ENOMEM;
+    }
+    if (b) nqi::release(b);
     return rc;
 }

@@ -594,11 +594,25 @@ extern "C" int nq_serve_submit(nq_server* s, const nq_request* req, uint64_t* ou
 }
 
 extern "C" int nq_serve_poll(nq_server* s, uint64_t ticket, nq_result* out) {
-    return nqi::serve_poll(s, ticket, out, 0);
+    try {
+        return nqi::serve_poll(s, ticket, out, 0);
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
 }
 
 extern "C" int nq_serve_wait(nq_server* s, uint64_t ticket, nq_result* out, uint64_t timeout_ns) {
-    return nqi::serve_poll(s, ticket, out, timeout_ns ? timeout_ns : 1);
+    try {
+        return nqi::serve_poll(s, ticket, out, timeout_ns ? timeout_ns : 1);
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
 }
 
-extern "C" int nq_serve_destroy(nq_server* s) { return nqi::serve_destroy(s); }
+extern "C" int nq_serve_destroy(nq_server* s) {
+    try {
+        return nqi::serve_destroy(s);
+    } catch (...) {
+        return NQ_EDEVICE;            // the worker thread could not be joined
+    }
+}

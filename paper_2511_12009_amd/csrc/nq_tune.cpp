@@ -204,5 +204,9 @@ int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
 
 extern "C" int nq_autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
                            nq_tuned* out) {
-    return nqi::autotune(n, depth_lo, depth_hi, budget_ms, out);
+    try {
+        return nqi::autotune(n, depth_lo, depth_hi, budget_ms, out);
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
 }
