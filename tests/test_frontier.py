@@ -110,6 +110,42 @@ def test_count_entry_points_validate_before_touching_the_gpu():
     assert lib.nq_count_subproblems(8, None, None, None, None, 0, None, None, None) == 0
 
 
+def test_batch_serve_tune_entry_points_validate_before_touching_the_gpu():
+    """Malformed calls of the batch, serving and autotune entry points return
+    NQ_EINVAL (or their documented no-op result) before any HIP call."""
+    lib = nq.lib()
+    u32a = lambda *v: (ct.c_uint32 * len(v))(*v)
+    handle = ct.c_void_p()
+    totals = (ct.c_uint64 * 4)()
+    # ragged batches
+    assert lib.nq_count_batch(0, None, None, None, None) == 0       # nothing to count
+    assert lib.nq_count_batch(3, None, None, None, totals) == -1
+    assert lib.nq_count_batch(2, u32a(8, 29), None, None, totals) == -1
+    assert lib.nq_count_batch(2, u32a(8, 9), u32a(3, 10), None, totals) == -1
+    assert lib.nq_batch_create(0, u32a(8), None, None, ct.byref(handle)) == -1
+    assert lib.nq_batch_create(1, u32a(0), None, None, ct.byref(handle)) == -1
+    assert lib.nq_batch_create(1, u32a(8), None, None, None) == -1
+    assert lib.nq_batch_run(None, totals, None) == -1
+    assert lib.nq_batch_entries(None) == 0
+    assert lib.nq_batch_destroy(None) == -1
+    # serving: no server, no request, no output
+    res = nq._native.NqResult()
+    req = nq._native.NqRequest()
+    tk = ct.c_uint64()
+    assert lib.nq_serve_create(None, 0, None) == -1
+    assert lib.nq_serve_submit(None, ct.byref(req), ct.byref(tk)) == -1
+    assert lib.nq_serve_poll(None, 0, ct.byref(res)) == -1
+    assert lib.nq_serve_wait(None, 0, ct.byref(res), 1000) == -1
+    assert lib.nq_serve_destroy(None) == -1
+    # autotune: board too small or too large, no output, empty depth range
+    tuned = nq._native.NqTuned()
+    assert lib.nq_autotune(3, 0, 0, 0.0, ct.byref(tuned)) == -1
+    assert lib.nq_autotune(29, 0, 0, 0.0, ct.byref(tuned)) == -1
+    assert lib.nq_autotune(20, 0, 0, 0.0, None) == -1
+    assert lib.nq_autotune(20, 9, 6, 0.0, ct.byref(tuned)) == -1
+    assert lib.nq_autotune(20, 6, 21, 0.0, ct.byref(tuned)) == -1
+
+
 def test_frontier_runs_cover_row0_columns():
     for n, k in [(20, 6), (17, 5), (9, 3)]:
         runs = nq.frontier_runs(n, k)
