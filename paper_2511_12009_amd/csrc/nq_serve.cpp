@@ -132,6 +132,7 @@ struct nq_server {
     std::deque<Epoch> epochs;
     bool stop = false;
     int fatal = NQ_OK;
+    int fatal_hip = 0;            // hipError_t behind `fatal`, handed to the caller's thread
     std::thread worker;
 };
 
@@ -235,7 +236,7 @@ void collect(nq_server* s) {
         const hipError_t q = hipEventQuery(s->epochs.front().done);
         if (q == hipErrorNotReady) break;
         if (q != hipSuccess && s->fatal == NQ_OK) {
-            set_hip_error(q);
+            s->fatal_hip = (int)q;
             s->fatal = NQ_EDEVICE;
         }
         (void)hipEventDestroy(s->epochs.front().done);
@@ -381,7 +382,10 @@ void worker_main(nq_server* s) {
         collect(s);
         if (s->fatal == NQ_OK) {
             int rc = admit_and_launch(s);
-            if (rc != NQ_OK) s->fatal = rc;
+            if (rc != NQ_OK) {
+                s->fatal = rc;
+                s->fatal_hip = nq_last_hip_error();   // set on this (the worker) thread
+            }
         }
         // After a fatal error nothing admitted is waited for: its results
         // will not come, and pollers see the error instead.
@@ -503,6 +507,13 @@ int serve_create(const nq_opts* opts, uint64_t hbm_budget, nq_server** out) {
     return NQ_OK;
 }
 
+// The server's fatal status, with its HIP error made visible to
+// nq_last_hip_error() on the calling thread (the worker thread met it).
+int fatal_status(const nq_server* s) {
+    set_hip_error(s->fatal_hip);
+    return s->fatal;
+}
+
 int serve_submit(nq_server* s, const nq_request* rq, uint64_t* ticket) {
     if (!s || !rq || !ticket) return NQ_EINVAL;
     if (rq->n < 1 || rq->n > NQ_MAX_N || rq->reserved != 0) return NQ_EINVAL;
@@ -522,7 +533,7 @@ int serve_submit(nq_server* s, const nq_request* rq, uint64_t* ticket) {
     if (!leafctr_ok(rq->n, r.depth)) return NQ_EINVAL;                   // row counter range
     r.t_submit = now_ns();
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->fatal != NQ_OK) return s->fatal;
+    if (s->fatal != NQ_OK) return fatal_status(s);
     if (s->pending.size() >= 65536) return NQ_EFULL;
     const uint64_t t = s->next_ticket++;
     s->reqs.emplace(t, r);
@@ -547,7 +558,7 @@ int serve_poll(nq_server* s, uint64_t ticket, nq_result* out, uint64_t wait_ns) 
         if (it == s->reqs.end()) return NQ_ENOENT;
     }
     const Req& r = it->second;
-    if (r.state != ReqState::Done) return s->fatal != NQ_OK ? s->fatal : NQ_EAGAIN;
+    if (r.state != ReqState::Done) return s->fatal != NQ_OK ? fatal_status(s) : NQ_EAGAIN;
     out->status = r.status;
     out->reserved = 0;
     out->count = r.count;
@@ -570,7 +581,7 @@ int serve_destroy(nq_server* s) {
         s->cv.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
-    const int fatal = s->fatal;
+    const int fatal = s->fatal != NQ_OK ? fatal_status(s) : NQ_OK;
     destroy_all(s);
     return fatal;
 }
