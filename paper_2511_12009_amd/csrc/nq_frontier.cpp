@@ -145,11 +145,16 @@ static void parallel_for(size_t count, unsigned threads, F&& fn) {
         return;
     }
     std::atomic<size_t> next{0};
+    auto work = [&] {
+        for (size_t i; (i = next.fetch_add(1)) < count;) fn(i);
+    };
     std::vector<std::thread> pool;
-    for (unsigned t = 0; t < threads; ++t)
-        pool.emplace_back([&] {
-            for (size_t i; (i = next.fetch_add(1)) < count;) fn(i);
-        });
+    try {
+        for (unsigned t = 1; t < threads; ++t) pool.emplace_back(work);
+    } catch (...) {
+        // A thread that cannot be started leaves its share to the others.
+    }
+    work();                                       // the calling thread is one worker
     for (auto& th : pool) th.join();
 }
 
