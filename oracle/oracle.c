@@ -313,7 +313,7 @@ int oq_count_prefixes(int n, int k, const int* prefixes, uint64_t m, int threads
     pthread_t tid[256];
     int started = 0;
     for (int t = 0; t < threads; ++t)
-        if (pthread_create(&tid[t], NULL, pool_worker, &p) == 0) ++started;
+        if (pthread_create(&tid[started], NULL, pool_worker, &p) == 0) ++started;
     if (started == 0) pool_worker(&p);
     for (int t = 0; t < started; ++t) pthread_join(tid[t], NULL);
     return OQ_OK;
@@ -545,7 +545,7 @@ int oqk_count_prefixes(int n, int k, const int* prefixes, uint64_t m, int thread
     pthread_t tid[256];
     int started = 0;
     for (int t = 0; t < threads; ++t)
-        if (pthread_create(&tid[t], NULL, kpool_worker, &p) == 0) ++started;
+        if (pthread_create(&tid[started], NULL, kpool_worker, &p) == 0) ++started;
     if (started == 0) kpool_worker(&p);
     for (int t = 0; t < started; ++t) pthread_join(tid[t], NULL);
     return OQ_OK;
