@@ -372,11 +372,12 @@ int nq_batch_destroy(nq_batch* batch);
  * NQ_ENOENT (unknown or already collected ticket).  nq_serve_wait: the same,
  * blocking up to timeout_ns.  Timestamps are CLOCK_MONOTONIC nanoseconds:
  * submit, admission (subproblems enqueued), completion seen by the scheduler.
- * After a HIP failure in the server (an epoch that cannot be enqueued or that
- * ends in a device error) every unfinished request reports that status
- * (NQ_EDEVICE) instead of NQ_EAGAIN, and submit returns it too; the server's
- * own thread met the error, and nq_last_hip_error() on the thread that gets
- * the status returns it.
+ * After a failure in the server (an epoch that cannot be enqueued or that
+ * ends in a device error: NQ_EDEVICE; a host allocation of its thread:
+ * NQ_ENOMEM) every unfinished request reports that status instead of
+ * NQ_EAGAIN, and submit returns it too; the server's own thread met the
+ * error, and nq_last_hip_error() on the thread that gets the status returns
+ * its hipError_t.
  * nq_serve_destroy: drops requests not yet admitted, waits for admitted ones
  * (not after such a failure), frees everything, and returns the failure's
  * status or NQ_OK.  All calls on one server are thread-safe.

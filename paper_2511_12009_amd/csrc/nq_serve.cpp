@@ -379,13 +379,21 @@ int admit_and_launch(nq_server* s) {
 void worker_main(nq_server* s) {
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        collect(s);
-        if (s->fatal == NQ_OK) {
-            int rc = admit_and_launch(s);
-            if (rc != NQ_OK) {
-                s->fatal = rc;
-                s->fatal_hip = nq_last_hip_error();   // set on this (the worker) thread
+        try {
+            collect(s);
+            if (s->fatal == NQ_OK) {
+                int rc = admit_and_launch(s);
+                if (rc != NQ_OK) {
+                    s->fatal = rc;
+                    s->fatal_hip = nq_last_hip_error();   // set on this (the worker) thread
+                }
             }
+        } catch (...) {                 // a host allocation failed: stop admitting
+            if (s->fatal == NQ_OK) {
+                s->fatal = NQ_ENOMEM;
+                s->fatal_hip = 0;
+            }
+            s->cv.notify_all();
         }
         // After a fatal error nothing admitted is waited for: its results
         // will not come, and pollers see the error instead.
@@ -396,8 +404,10 @@ void worker_main(nq_server* s) {
             std::this_thread::sleep_for(std::chrono::microseconds(20));
             lk.lock();
         } else {
-            s->cv.wait_for(lk, std::chrono::milliseconds(2),
-                           [&] { return s->stop || !s->pending.empty(); });
+            // (after a fatal error pending requests are never admitted)
+            s->cv.wait_for(lk, std::chrono::milliseconds(2), [&] {
+                return s->stop || (s->fatal == NQ_OK && !s->pending.empty());
+            });
         }
     }
 }
