@@ -10,12 +10,13 @@
  *   Q(N) = number of ways to put N queens on an N x N board, one per row, with
  *   no two on a common column or diagonal.  A prefix pi = (c_0..c_{k-1}) fixes
  *   the queen of row i in column c_i; Q_pi(N) counts the completions of pi.  The
- *   method pre-places k rows (Section 1, "pre-placing queens in the first few
- *   rows"; Section 2, subproblem generation), keeps only the first half of row 0
- *   by mirror symmetry, and for odd N adds the centre column of row 0 with the
- *   row-1 queen restricted to the first N/2 - 1 columns (Section 1 and its
- *   footnote).  Every kept prefix stands for itself and its mirror image
- *   (weight 2); the total is sum(w_pi * Q_pi(N)) = Q(N).
+ *   method pre-places k rows (Section 1, which splits the search into
+ *   independent subtrees this way; Section 2, subproblem generation), keeps
+ *   only the first half of row 0 by mirror symmetry, and for odd N adds the
+ *   centre column of row 0 with the row-1 queen restricted to the first
+ *   N/2 - 1 columns (Section 1 and its footnote).  Every kept prefix stands
+ *   for itself and its mirror image (weight 2); the total is
+ *   sum(w_pi * Q_pi(N)) = Q(N).
  *
  * Readings where the paper is silent (each one is pinned by the tests):
  *   - k = 1 with odd N: the centre prefix has no mirror partner and gets w = 1.
