@@ -27,6 +27,20 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_every_declared_function_is_documented():
+    """Each entry point of the C-ABI header carries its own documentation: its
+    name appears in a comment, or a comment ends right above its declaration."""
+    with open(os.path.join(ROOT, "include", "nq.h")) as f:
+        text = f.read()
+    comments = " ".join(re.findall(r"/\*.*?\*/", text, flags=re.S))
+    for name in _declared_functions():
+        if name in comments:
+            continue
+        decl = re.search(r"^[^\n]*\b" + name + r"\s*\(", text, flags=re.M)
+        before = text[:decl.start()].rstrip()
+        assert before.endswith("*/"), f"{name} has no documentation"
+
+
 def test_strerror_covers_every_status():
     lib = nq.lib()
     for st in range(0, -8, -1):
