@@ -36,7 +36,11 @@
 #include <string.h>
 #include <pthread.h>
 
-#define OQ_MAXN 28
+/* Boards up to 31 columns: the widest whose attack masks (oq_prefix_masks)
+ * fit in 32 bits.  Whole-board counts stop at 28, the last size whose count
+ * fits in 64 bits (Section 4.5). */
+#define OQ_MAXN 31
+#define OQ_MAXN_COUNT 28
 
 enum { OQ_OK = 0, OQ_EINVAL = -1, OQ_ERANGE = -2, OQ_ENOMEM = -3 };
 
@@ -94,7 +98,7 @@ static int valid_nk(int n, int k) { return n >= 1 && n <= OQ_MAXN && k >= 0 && k
 
 /* Q(n) with no symmetry at all: every column of every row (the definition). */
 int oq_queens(int n, uint64_t* count, uint64_t* nodes) {
-    if (!valid_nk(n, 0) || !count) return OQ_EINVAL;
+    if (!valid_nk(n, 0) || n > OQ_MAXN_COUNT || !count) return OQ_EINVAL;
     board_t b;
     board_init(&b, n);
     uint64_t nd = 0;

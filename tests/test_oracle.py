@@ -148,11 +148,28 @@ def test_edge_sizes():
     assert oracle.frontier_size(3, 3) == 0
     assert oracle.frontier_size(4, 0) == 1
     with pytest.raises(oracle.OracleError):
-        oracle.frontier_size(29, 3)
+        oracle.frontier_size(32, 3)
+    with pytest.raises(oracle.OracleError):
+        oracle.queens(29)                     # Q(29) does not fit in 64 bits
     with pytest.raises(oracle.OracleError):
         oracle.frontier_size(8, 9)
     with pytest.raises(oracle.OracleError):
         oracle.queens(0)
+
+
+@pytest.mark.parametrize("n", [4, 5, 12, 13, 28, 29, 30, 31])
+def test_frontier_sizes_closed_form_at_depth_one_and_two(n):
+    """Depths 1 and 2 counted by hand from the symmetry rule (Section 1 and its
+    footnote), also for the boards of 29..31 that only the 128-bit totals
+    reach: row 0 takes the first n//2 columns, plus the centre for odd n; a
+    row-0 queen in column c attacks c-1, c, c+1 of row 1 (two of them at the
+    edge), and the centre's row-1 queen takes columns 0..n//2-2, none of which
+    it attacks."""
+    h = n // 2
+    odd = n % 2
+    assert oracle.frontier_size(n, 1) == h + odd
+    row1 = sum(n - (2 if c == 0 else 3) for c in range(h))
+    assert oracle.frontier_size(n, 2) == row1 + odd * (h - 1)
 
 
 # ------------------------------------------------------------ mask definition
