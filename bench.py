@@ -3,8 +3,9 @@
 One step = the whole device path over the resident N=20 frontier (pre-placement
 depth k, built before the timed region): zero the total, one persistent DFS
 launch over every subproblem (weighted total; per-subproblem counts are not
-requested), and the copy of the 8-byte total back to the host, which is checked
-against Q(20) = 39,029,188,884 every step.
+requested), and the copy of the 8-byte total into that step's own slot of a
+pinned host array; after the timed loop every slot is checked against
+Q(20) = 39,029,188,884.
 
 value = DFS nodes per second = nodes(20, k) / step time, where nodes(20, k) is
 the oracle's node count (queens placed in rows k..18 below every pre-placed
@@ -118,7 +119,10 @@ def profiled_executed(n, k):
 
 
 def known_counts():
-    """Published counts (tests/golden/known_counts.txt)."""
+    """Expected Q(n): the oracle's weighted total where tests/golden/oracle_runs.txt
+    holds an oracle run of n (written by tests/golden/make_golden.py), else the
+    published count (tests/golden/known_counts.txt).  The two agree wherever
+    both exist (tests/test_oracle.py)."""
     out = {}
     with open(os.path.join(ROOT, "tests", "golden", "known_counts.txt")) as f:
         for line in f:
@@ -126,7 +130,18 @@ def known_counts():
             if line:
                 n, c = line.split()[:2]
                 out[int(n)] = int(c)
+    with open(os.path.join(ROOT, "tests", "golden", "oracle_runs.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                r = line.split()
+                out[int(r[0])] = int(r[3])
     return out
+
+
+def oracle_checked():
+    """Board sizes whose expected count comes from an oracle run (see known_counts)."""
+    with open(os.path.join(ROOT, "tests", "golden", "oracle_runs.txt")) as f:
+        return sorted({int(ln.split()[0]) for ln in f if ln.strip() and not ln.startswith("#")})
 
 
 def bench_batch(nq, known):
@@ -141,9 +156,12 @@ def bench_batch(nq, known):
         entries = b.entries
     ok = got == [known[n] for n in ns]
     if not ok:
-        raise SystemExit("bench.py: ragged batch totals differ from the published counts")
+        raise SystemExit("bench.py: ragged batch totals differ from the expected counts")
+    by_oracle = oracle_checked()
     return {"instances": len(ns), "subproblems": entries, "replay_ms": ms,
             "build_ms": build_ms, "exact": ok,
+            "checked_by_oracle_runs": sum(1 for n in ns if n in by_oracle),
+            "oracle_sizes": [n for n in sorted(set(ns)) if n in by_oracle],
             "form": "one persistent launch over every instance's frontier, HIP graph replay"}
 
 
@@ -200,14 +218,61 @@ def bench_kings(nq, n=16):
             "exact": True, "form": "kings search on the queens lane-stack engine (NQ_FLAG_KINGS)"}
 
 
-def bench_serving(nq, known, rates, seconds):
+def _serve_count_work(nq, torch, n, entries):
+    """DFS nodes of a COUNT request of board n that the server searched as
+    `entries` subproblems: the frontier depth with that many entries, searched
+    by nq_count_subproblems with per-entry node counts (the node-counting
+    kernel is checked against the oracle's nodes in the parity tests)."""
+    dev = torch.device("cuda:0")
+    for d in range(1, n + 1):
+        if nq.frontier_size(n, d) == entries:
+            cols, ld, rd, w = nq.frontier(n, d)
+            t = [torch.from_numpy(x.view(np.int32)).to(dev) for x in (cols, ld, rd)]
+            nodes = torch.zeros(len(cols), dtype=torch.int64, device=dev)
+            nq.count_subproblems(n, *t, weight=torch.from_numpy(w).to(dev), counts=False,
+                                 depth=d, nodes=nodes)
+            return int(nodes.sum())
+    raise SystemExit(f"bench.py: no frontier depth of N={n} has {entries} entries")
+
+
+def _slice_check(nq, torch, n, k, cols, ld, rd, w, start, length):
+    """A second path for one slice: its entries expanded two rows (as the server
+    does), searched by nq_count_subproblems with node counts; returns
+    (weighted total, entries searched, DFS nodes)."""
+    dev = torch.device("cuda:0")
+    sl = slice(start, start + length)
+    t = [torch.from_numpy(np.ascontiguousarray(x[sl]).view(np.int32)).to(dev)
+         for x in (cols, ld, rd)]
+    tw = torch.from_numpy(np.ascontiguousarray(w[sl])).to(dev)
+    c, l, r, ww = nq.expand(n, 2, t[0], t[1], t[2], tw)
+    nodes = torch.zeros(c.numel(), dtype=torch.int64, device=dev)
+    _, tot = nq.count_subproblems(n, c, l, r, weight=ww, counts=False, depth=k + 2, nodes=nodes)
+    return int(tot.item()), c.numel(), int(nodes.sum())
+
+
+def bench_serving(nq, torch, known, rates, seconds):
     """Poisson COUNT(N in 10..18) requests with N=21 depth-6 4096-entry slices
-    interleaved; per rate: p50/p99 latency and throughput."""
+    interleaved; per rate: p50/p99 latency (all COUNTs, per N, slices),
+    throughput in requests/s and in served DFS nodes/s.  Every COUNT result is
+    checked against the published count; every slice against a second device
+    path over the same entries (nq_expand + nq_count_subproblems), whose node
+    counts also give the served nodes.  Solo latency per N (one request on an
+    idle server) is measured first."""
     import seeded_inputs
-    F21 = nq.frontier_size(21, 6)
-    res = []
+    n21, k21, slen = 21, 6, 4096
+    F21 = nq.frontier_size(n21, k21)
+    c21, l21, r21, w21 = nq.frontier(n21, k21)
+    res = {"solo_count_ms": {}, "rates": []}
+    count_nodes, slice_ref = {}, {}
     with nq.Server(hbm_budget=16 << 30) as srv:
-        srv.wait(srv.submit_slice(21, 6, 0, 1))          # builds the resident frontier
+        srv.wait(srv.submit_slice(n21, k21, 0, 1))          # builds the resident frontier
+        for n in range(10, 19):
+            srv.wait(srv.submit_count(n))                     # builds this N's frontier
+            r = srv.wait(srv.submit_count(n))
+            if r["status"] != 0 or r["count"] != known[n]:
+                raise SystemExit(f"bench.py: serving result wrong (solo N={n})")
+            res["solo_count_ms"][n] = (r["t_done_ns"] - r["t_submit_ns"]) / 1e6
+            count_nodes[n] = (r["entries"], _serve_count_work(nq, torch, n, r["entries"]))
         for rate in rates:
             n_req = max(1, int(rate * seconds))
             arr = seeded_inputs.poisson_arrivals(n_req, rate)
@@ -226,25 +291,53 @@ def bench_serving(nq, known, rates, seconds):
                 if kind == "count":
                     tickets.append(("count", ns[i], srv.submit_count(ns[i])))
                 else:
-                    start = (i * 4096) % F21
-                    tickets.append(("slice", None, srv.submit_slice(21, 6, start,
-                                                                    min(4096, F21 - start))))
+                    start = (i * slen) % F21
+                    ln = min(slen, F21 - start)
+                    tickets.append(("slice", (start, ln), srv.submit_slice(n21, k21, start, ln)))
             lat = {"count": [], "slice": []}
-            for kind, n, tk in tickets:
+            per_n = {}
+            served_nodes = 0
+            results = []
+            for kind, arg, tk in tickets:
                 r = srv.wait(tk, timeout_s=300)
-                if r["status"] != 0 or (kind == "count" and r["count"] != known[n]):
-                    raise SystemExit(f"bench.py: serving result wrong ({kind}, N={n})")
-                lat[kind].append((r["t_done_ns"] - r["t_submit_ns"]) / 1e6)
+                results.append((kind, arg, r))
             wall = time.perf_counter() - t0
+            for kind, arg, r in results:
+                if r["status"] != 0:
+                    raise SystemExit(f"bench.py: serving request failed ({kind}, {arg})")
+                ms = (r["t_done_ns"] - r["t_submit_ns"]) / 1e6
+                lat[kind].append(ms)
+                if kind == "count":
+                    if r["count"] != known[arg] or r["entries"] != count_nodes[arg][0]:
+                        raise SystemExit(f"bench.py: serving result wrong (count, N={arg})")
+                    per_n.setdefault(arg, []).append(ms)
+                    served_nodes += count_nodes[arg][1]
+                else:
+                    if arg not in slice_ref:
+                        slice_ref[arg] = _slice_check(nq, torch, n21, k21, c21, l21, r21, w21,
+                                                      *arg)
+                    want, entries, nd = slice_ref[arg]
+                    if r["count"] != want or r["entries"] != entries:
+                        raise SystemExit(f"bench.py: serving slice {arg} = {r['count']}, "
+                                         f"second path {want}")
+                    served_nodes += nd
             row = {"rate_count_per_s": rate, "rate_slice_per_s": s_rate,
                    "requests": len(tickets), "wall_s": wall,
-                   "throughput_req_per_s": len(tickets) / wall}
+                   "throughput_req_per_s": len(tickets) / wall,
+                   "served_nodes": served_nodes, "nodes_per_s": served_nodes / wall}
             for kind in ("count", "slice"):
                 if lat[kind]:
                     row[f"{kind}_p50_ms"] = float(np.percentile(lat[kind], 50))
                     row[f"{kind}_p99_ms"] = float(np.percentile(lat[kind], 99))
-            res.append(row)
+            row["count_by_n"] = {
+                n: {"requests": len(v), "p50_ms": float(np.percentile(v, 50)),
+                    "p99_ms": float(np.percentile(v, 99)),
+                    "p50_over_solo": float(np.percentile(v, 50)) / res["solo_count_ms"][n]}
+                for n, v in sorted(per_n.items())}
+            res["rates"].append(row)
             print(f"[bench] serving {json.dumps(row)}", file=sys.stderr, flush=True)
+    res["checked"] = ("every COUNT against the published count; every slice against nq_expand + "
+                      "nq_count_subproblems over the same entries")
     return res
 
 
@@ -340,9 +433,10 @@ def run_ablation(nq, torch):
 
 def cpu_baseline(k, budget_s):
     """The oracle on a seeded sample of the N=20 frontier (depth min(k, 8), so
-    that the prefix list stays small), all host cores."""
+    that the prefix list stays small), one thread per host core this process
+    may run on."""
     import oracle
-    cores = min(os.cpu_count() or 1, 16)
+    cores = len(os.sched_getaffinity(0))
     k = min(k, 8)
     pre, _ = oracle.frontier(N, k)
     rng = np.random.default_rng(20251112)
@@ -359,7 +453,7 @@ def cpu_baseline(k, budget_s):
     _, nd = oracle.count_prefixes(N, sample, threads=cores)
     dt = time.perf_counter() - t
     return {"value": float(nd.sum()) / dt, "unit": "DFS nodes/s", "cores": cores,
-            "kind": "oracle",
+            "host_cpus": os.cpu_count(), "kind": "oracle",
             "sample": f"{m} seeded subproblems of the N=20 depth-{k} frontier "
                       f"({int(nd.sum())} nodes, {dt:.1f} s)"}
 
@@ -379,7 +473,7 @@ def main():
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--claim", type=int, default=0, help="entries per work-head claim (0 = auto)")
     ap.add_argument("--forward", action="store_true", help="claim entries in frontier order")
-    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-shards", action="store_true")
@@ -426,14 +520,15 @@ def main():
     t_cols, t_ld, t_rd, t_w = device_frontier(nq, torch, dev, k)
     F = t_cols.numel()
     total = torch.zeros(1, dtype=torch.int64, device=dev)
-    host_total = torch.zeros(1, dtype=torch.int64).pin_memory()
+    # one pinned slot per timed step: each step's total is checked after the loop
+    host_totals = torch.zeros(max(args.steps, args.plain_steps, 1), dtype=torch.int64).pin_memory()
     stream = torch.cuda.current_stream()
     kw = dict(depth=k, wg_size=args.wg, waves_per_cu=args.waves_per_cu,
               refill_every=args.refill, forward=args.forward, claim=args.claim)
 
     runs = nq.frontier_runs(N, k)
 
-    def step(mode):
+    def step(mode, slot):
         total.zero_()
         if mode == "plain":
             # one launch per row-0 column, each over its run of the frontier
@@ -444,23 +539,30 @@ def main():
         else:
             nq.count_subproblems(N, t_cols, t_ld, t_rd, weight=t_w, counts=False, total=total,
                                  mode=mode, stream=stream, **kw)
-        host_total.copy_(total, non_blocking=True)
+        host_totals[slot:slot + 1].copy_(total, non_blocking=True)
 
     def timed(mode, steps, warmup):
+        host_totals.zero_()
         for _ in range(warmup):
-            step(mode)
+            step(mode, 0)
         torch.cuda.synchronize()
+        bad = [int(x) for x in host_totals[:min(warmup, 1)] if int(x) != EXPECT]
+        if bad:
+            raise SystemExit(f"bench.py: {mode} warm-up total {bad[0]} != {EXPECT}")
+        host_totals.zero_()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(steps)]
         t0 = time.perf_counter()
-        for a, b in evs:
+        for i, (a, b) in enumerate(evs):
             a.record(stream)
-            step(mode)
+            step(mode, i)
             b.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        if int(host_total.item()) != EXPECT:
-            raise SystemExit(f"bench.py: {mode} total {int(host_total.item())} != {EXPECT}")
+        got = [int(x) for x in host_totals[:steps]]
+        wrong = [(i, g) for i, g in enumerate(got) if g != EXPECT]
+        if wrong:
+            raise SystemExit(f"bench.py: {mode} step {wrong[0][0]} total {wrong[0][1]} != {EXPECT}")
         ev_ms = [a.elapsed_time(b) for a, b in evs]
         return wall, ev_ms
 
@@ -470,9 +572,10 @@ def main():
     ms_step = wall / args.steps * 1e3
     print(f"[bench] persistent {ms_step:.1f} ms/step (events {np.mean(ev_ms):.1f} ms)",
           file=sys.stderr, flush=True)
-    plain_wall, plain_ev = timed("plain", args.plain_steps, 0)
+    plain_wall, plain_ev = timed("plain", args.plain_steps, 1)
     plain_ms = plain_wall / args.plain_steps * 1e3
-    print(f"[bench] plain {plain_ms:.1f} ms/step", file=sys.stderr, flush=True)
+    print(f"[bench] plain {plain_ms:.1f} ms/step over {args.plain_steps} steps (events "
+          f"{min(plain_ev):.1f}..{max(plain_ev):.1f} ms)", file=sys.stderr, flush=True)
 
     t = time.perf_counter()
     e2e_total = nq.count(N, depth=k, mode="persistent")
@@ -501,7 +604,8 @@ def main():
                                "resident in HBM, one persistent launch",
                    "n": N, "depth": k, "subproblems": F, "solutions": EXPECT,
                    "nodes": nodes, "nodes_source": src},
-        "plain": {"ms_per_step": plain_ms,
+        "plain": {"ms_per_step": plain_ms, "steps": args.plain_steps, "warmup": 1,
+                  "event_ms": plain_ev,
                   "value": (nodes / (plain_ms / 1e3)) if nodes else None,
                   "form": "one launch per row-0 column over the same resident frontier"},
         "batched_over_plain": plain_ms / ms_step,
@@ -532,7 +636,7 @@ def main():
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
     if rates:
         print("[bench] serving", file=sys.stderr, flush=True)
-        out["serving"] = bench_serving(nq, known, rates, args.serve_seconds)
+        out["serving"] = bench_serving(nq, torch, known, rates, args.serve_seconds)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(k, args.cpu_seconds)

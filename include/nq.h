@@ -15,7 +15,8 @@
  *   - Section 2, Algorithm 2, and Section 3.2.3 / Algorithm 3: each subtree is
  *     searched by an iterative DFS with an explicit stack of (cols, ld, rd,
  *     avail) frames; the last row is never pushed, its free squares are counted.
- *   - Section 4.5: N = 28 is the last size whose count fits in 64 bits.
+ *   - Section 4.5: N = 28 is the last size whose count fits in 64 bits; larger
+ *     boards need wider totals.
  *
  * Conventions for every entry point:
  *   - Return value: NQ_OK (0) or a negative NQ_E* status.  Nothing throws, aborts
@@ -23,7 +24,10 @@
  *     where a function says otherwise (nq_frontier with NQ_ERANGE,
  *     nq_count_resumable with NQ_EAGAIN).
  *   - Bit j of a mask stands for column j.  Valid board sizes: 1 <= n <= 28
- *     (NQ_MAX_N); larger n is NQ_EINVAL.
+ *     (NQ_MAX_N); larger n is NQ_EINVAL, except where a function accepts boards
+ *     up to NQ_MAX_N_WIDE (31, the widest board whose masks fit in 32 bits):
+ *     nq_frontier, nq_kings_frontier, nq_frontier_runs, nq_expand,
+ *     nq_count_subproblems (with 128-bit totals) and nq_count_resumable_wide.
  *   - Counts are exact uint64.  Per-subproblem counts are UNWEIGHTED; totals are
  *     weighted by the symmetry weights.
  *   - Host buffers are owned by the caller.  Device buffers passed in are owned
@@ -43,6 +47,7 @@ extern "C" {
 #endif
 
 #define NQ_MAX_N 28
+#define NQ_MAX_N_WIDE 31
 
 enum nq_status {
     NQ_OK = 0,
@@ -74,7 +79,7 @@ int nq_last_hip_error(void);
  *   depth == 0 (the empty board) and for the odd-n centre entry when depth == 1.
  * Entries whose row `depth` has no free square are kept (their count is 0).
  *
- * n in [1, 28], depth in [0, n].  Size query: if cols, ld or rd is NULL, or
+ * n in [1, 31], depth in [0, n].  Size query: if cols, ld or rd is NULL, or
  * capacity == 0, only *out_len = F is written and NQ_OK returned.  Otherwise
  * the arrays (length >= capacity; weight may be NULL) are filled; if
  * capacity < F the first `capacity` entries are written, *out_len = F and
@@ -102,7 +107,7 @@ int nq_kings_frontier(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld, 
  * entries of each row-0 column (and, for odd n, of the centre column) form one
  * contiguous run.  Writes the start offset of every run followed by F, i.e.
  * runs + 1 values, into offsets (capacity >= runs + 1) and *out_runs = runs.
- * With offsets == NULL only *out_runs is written.  n in [1, 28], depth in
+ * With offsets == NULL only *out_runs is written.  n in [1, 31], depth in
  * [1, n]; host only.
  */
 int nq_frontier_runs(uint32_t n, uint32_t depth, uint64_t* offsets, uint32_t capacity,
@@ -122,7 +127,7 @@ int nq_frontier_runs(uint32_t n, uint32_t depth, uint64_t* offsets, uint32_t cap
  * keep weight 1, which gives the same weighted count as the deeper frontier,
  * whose centre entries restrict row 1 and carry weight 2.)  With d_ocols, d_old or d_ord NULL only
  * *out_len (the number of children) is computed; capacity < *out_len is
- * NQ_ERANGE.  The call allocates scratch device memory and waits on `stream`
+ * NQ_ERANGE.  n in [1, 31].  The call allocates scratch device memory and waits on `stream`
  * (hipStream_t or NULL) for the size and, when writing, for the result.
  */
 int nq_expand(uint32_t n, uint32_t rows, const uint32_t* d_cols, const uint32_t* d_ld,
@@ -148,12 +153,16 @@ enum nq_flags {
      * same lane stack; the paper's conclusion names permutation searches as
      * candidates for its method).  A king attacks only the adjacent row, so the
      * Somers triple of an entry is (columns taken, the square right of the last
-     * king, the square left of it), as nq_kings_frontier writes it.  Only the
-     * default inner-loop form runs it; batches, servers and resumable counts
-     * refuse the flag (NQ_EINVAL). */
-    NQ_FLAG_KINGS = 2u
+     * king, the square left of it), as nq_kings_frontier writes it.  It runs
+     * inner-loop form 1 whatever form nq_set_loop_form selects; batches,
+     * servers and resumable counts refuse the flag (NQ_EINVAL). */
+    NQ_FLAG_KINGS = 2u,
+    /* nq_count_subproblems: d_total is uint64[2], a 128-bit total (low word
+     * first) increased with carry.  Required when n > 28 and d_total is set:
+     * Q(29) already exceeds 2^64 (Section 4.5). */
+    NQ_FLAG_WIDE_TOTAL = 4u
 };
-#define NQ_FLAGS_ALL 3u
+#define NQ_FLAGS_ALL 7u
 
 /*
  * Options shared by the counting entry points.  A NULL options pointer, or a
@@ -200,7 +209,8 @@ typedef struct nq_opts {
  * counts).  With NQ_FLAG_KINGS the kings frontier
  * (nq_kings_frontier) is built on the host only, at opts->depth or by default
  * the shallowest depth with at least 2^22 entries (at most n - 2 and 2^27
- * entries).
+ * entries); the number of king placements passes 2^64 at n = 22, so with
+ * that flag n > 21 is NQ_EINVAL.  NQ_FLAG_WIDE_TOTAL is NQ_EINVAL here.
  */
 int nq_count(uint32_t n, const nq_opts* opts, uint64_t* out_total);
 
@@ -218,7 +228,10 @@ int nq_count(uint32_t n, const nq_opts* opts, uint64_t* out_total);
  * many queens placed; it sizes the LDS stack (n - 2 - depth frames per lane).
  * A triple with fewer queens is not searched: its d_counts entry is set to
  * UINT64_MAX and it adds nothing to d_total.  Asynchronous on opts->stream
- * (unless kernel_ms_out is set); len == 0 launches nothing.  With
+ * (unless kernel_ms_out is set); len == 0 launches nothing.  n may be up to
+ * NQ_MAX_N_WIDE (31); for n > 28 opts->depth must be at least n - 20 (at most
+ * 20 rows below every prefix, so a per-subproblem count stays below 20! <
+ * 2^62) and a non-NULL d_total needs NQ_FLAG_WIDE_TOTAL.  With
  * NQ_FLAG_KINGS the triples are kings-search triples (nq_kings_frontier: ld /
  * rd hold only the squares beside the last king) and the counts are king
  * placements; the same rules for full, last-row and dead entries apply.
@@ -262,10 +275,31 @@ int nq_count_batch(uint32_t ninst, const uint32_t* ns, const uint32_t* depths,
  * *out_total = Q(n) when every range is done, NQ_EAGAIN with the partial total
  * while ranges remain; *out_done = ranges done.  opts->counts_out and
  * opts->d_nodes must be NULL.  NQ_EINVAL also when the file cannot be written.
+ * With opts->depth == 0 the depth is that of an existing record of the same n
+ * and chunk count, else the one nq_count's automatic chunked count uses for n,
+ * else nq_count's frontier-size rule; never a tuning result, so that every
+ * process that continues a file picks the same depth.  n in [1, 28]; a total
+ * of 2^64 or more (possible only for files written by nq_count_resumable_wide)
+ * is NQ_ERANGE, with *out_done written and *out_total untouched.
  * Synchronous; one call at a time per file.
  */
 int nq_count_resumable(uint32_t n, const nq_opts* opts, const char* path, uint32_t chunks,
                        uint32_t max_chunks, uint64_t* out_total, uint32_t* out_done);
+
+/*
+ * nq_count_resumable_wide -- nq_count_resumable with a 128-bit total, for
+ * boards beyond the 64-bit limit of Section 4.5 (N = 28 is the last count
+ * that fits in int64).  n in [1, 31] (NQ_MAX_N_WIDE); for n > 28 the depth
+ * (opts->depth, or the automatic one) must be at least n - 20, which keeps
+ * every per-subproblem count below 2^62.  Each range is counted with a
+ * 128-bit device total (NQ_FLAG_WIDE_TOTAL), the ranges are added in 128 bits
+ * on the host (the automatic depth of a board beyond 28 is n - 20), and the
+ * record's total= field holds the 128-bit decimal value.
+ * out_total[0] receives the low and out_total[1] the high 64 bits.  Everything
+ * else is as nq_count_resumable, and both read and write the same records.
+ */
+int nq_count_resumable_wide(uint32_t n, const nq_opts* opts, const char* path, uint32_t chunks,
+                            uint32_t max_chunks, uint64_t* out_total, uint32_t* out_done);
 
 /*
  * nq_autotune -- measure the best pre-placement depth and launch shape for n.
@@ -295,14 +329,17 @@ int nq_autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_
 /*
  * nq_set_loop_form -- choose the DFS inner-loop form of the launches planned
  * from now on, to measure the forms against each other; all give the same
- * counts.  form: -1 = the default (1, or NQ_DFS_LOOP from the environment),
- * 0 = compiler-scheduled C++ step, 1 = hand-placed exec masks (default),
- * 2 = form 1 with the untried set negated, 4 = the frame being expanded read
- * from the LDS stack at every step with its untried set written back
- * (Algorithm 2 as printed in Section 2, with the last-row step of Algorithm 3,
- * Section 3.2.3), 5 = form 0 without the last-row step (Algorithm 2 alone).
- * Forms 4 and 5 need one LDS frame more per lane.  *previous (nullable)
- * receives the form in use.  NQ_EINVAL for any other form (3 included).
+ * counts.  form: -1 = the default (NQ_DFS_LOOP from the environment, else
+ * the library's default form), 0 = compiler-scheduled C++ step, 1 = hand-placed
+ * exec masks, 2 = form 1 with the untried set negated, 3 = a step without
+ * selects (the frame being expanded is pushed while it has untried columns,
+ * the child is computed into a second register frame, and a child that is not
+ * searched is replaced by a pop), 4 = the frame being expanded read from the
+ * LDS stack at every step with its untried set written back (Algorithm 2 as
+ * printed in Section 2, with the last-row step of Algorithm 3, Section
+ * 3.2.3), 5 = form 0 without the last-row step (Algorithm 2 alone).  Forms 3,
+ * 4 and 5 need one LDS frame more per lane.  *previous (nullable) receives the
+ * form in use.  NQ_EINVAL for any other form.
  * Process-wide; a launch keeps the form it was planned with (a server's epochs
  * or a batch plan made before the call keep theirs), so set it while no other
  * thread plans launches.  Touches no device.

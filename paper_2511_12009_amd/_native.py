@@ -130,6 +130,9 @@ def lib():
         L.nq_batch_destroy.restype = ct.c_int
         L.nq_count_resumable.argtypes = [u32, ct.POINTER(NqOpts), ct.c_char_p, u32, u32, pu64, pu32]
         L.nq_count_resumable.restype = ct.c_int
+        L.nq_count_resumable_wide.argtypes = [u32, ct.POINTER(NqOpts), ct.c_char_p, u32, u32, pu64,
+                                              pu32]
+        L.nq_count_resumable_wide.restype = ct.c_int
         L.nq_set_loop_form.argtypes = [ct.c_int, ct.POINTER(ct.c_int)]
         L.nq_set_loop_form.restype = ct.c_int
         _LIB = L
@@ -147,6 +150,7 @@ def _check(rc: int, what: str):
 
 FLAG_FORWARD_ORDER = 1
 FLAG_KINGS = 2
+FLAG_WIDE_TOTAL = 4
 
 
 def _opts(depth=0, mode="persistent", wg_size=0, waves_per_cu=0, refill_every=0, stream=None,
@@ -259,8 +263,11 @@ def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None
                       depth: int = 0, mode="persistent", wg_size: int = 0,
                       waves_per_cu: int = 0, refill_every: int = 0, stream=None,
                       timing: bool = False, nodes=None, forward: bool = False, claim: int = 0,
-                      kings: bool = False):
+                      kings: bool = False, wide: bool = False):
     """Counts every subtree of device-resident triples (torch int32 CUDA tensors).
+
+    ``wide=True`` (NQ_FLAG_WIDE_TOTAL; needed for n > 28): ``total`` is int64[2],
+    a 128-bit total (low word first) increased with carry.
 
     ``counts`` (int64[F]) and ``total`` (int64[1], accumulated) are torch tensors
     allocated here when not given; ``counts=False`` requests no per-entry counts.  ``depth`` promises that every triple has at
@@ -279,9 +286,12 @@ def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None
     if counts is None:
         counts = torch.empty(length, dtype=torch.int64, device=cols.device)
     if total is None:
-        total = torch.zeros(1, dtype=torch.int64, device=cols.device)
+        total = torch.zeros(2 if wide else 1, dtype=torch.int64, device=cols.device)
+    if total is not False and total.numel() < (2 if wide else 1):
+        raise ValueError("total needs two int64 words with wide=True")
     o = _opts(depth, mode, wg_size, waves_per_cu, refill_every, _stream_handle(stream),
-              (FLAG_FORWARD_ORDER if forward else 0) | (FLAG_KINGS if kings else 0), claim)
+              (FLAG_FORWARD_ORDER if forward else 0) | (FLAG_KINGS if kings else 0) |
+              (FLAG_WIDE_TOTAL if wide else 0), claim)
     if nodes is not None:
         if nodes.dtype != torch.int64 or nodes.numel() != length or not nodes.is_cuda:
             raise ValueError("nodes must be an int64 CUDA tensor of the same length")
@@ -292,26 +302,29 @@ def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None
     _check(lib().nq_count_subproblems(
         n, cols.data_ptr(), ld.data_ptr(), rd.data_ptr(),
         None if weight is None else weight.data_ptr(), length,
-        None if counts is False else counts.data_ptr(), total.data_ptr(), ct.byref(o)),
+        None if counts is False else counts.data_ptr(),
+        None if total is False else total.data_ptr(), ct.byref(o)),
         "nq_count_subproblems")
     return (counts, total, ms.value) if timing else (counts, total)
 
 
 def count_resumable(n: int, path: str, chunks: int = 0, max_chunks: int = 0, depth: int = 0,
                     mode="persistent", waves_per_cu: int = 0, refill_every: int = 0,
-                    claim: int = 0):
+                    claim: int = 0, wide: bool = False):
     """nq_count_resumable: Q(n) in chunks whose progress is kept in the file
     `path`; returns (total, chunks_done, finished).  While not finished, total
-    is the weighted count of the chunks done so far; call again to go on."""
+    is the weighted count of the chunks done so far; call again to go on.
+    wide=True calls nq_count_resumable_wide (boards up to 31, 128-bit total)."""
     o = _opts(depth, mode, 0, waves_per_cu, refill_every, None, 0, claim)
-    total = ct.c_uint64()
+    words = (ct.c_uint64 * 2)()
     done = ct.c_uint32()
-    rc = lib().nq_count_resumable(n, ct.byref(o), os.fsencode(path), chunks, max_chunks,
-                                  ct.byref(total), ct.byref(done))
+    fn = lib().nq_count_resumable_wide if wide else lib().nq_count_resumable
+    rc = fn(n, ct.byref(o), os.fsencode(path), chunks, max_chunks, words, ct.byref(done))
+    total = int(words[0]) | (int(words[1]) << 64)
     if rc == NQ_EAGAIN:
-        return total.value, done.value, False
-    _check(rc, "nq_count_resumable")
-    return total.value, done.value, True
+        return total, done.value, False
+    _check(rc, "nq_count_resumable_wide" if wide else "nq_count_resumable")
+    return total, done.value, True
 
 
 def set_loop_form(form: int) -> int:

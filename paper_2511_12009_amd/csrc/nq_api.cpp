@@ -19,6 +19,14 @@ namespace nqi {
 
 static thread_local int g_last_hip_error = 0;
 
+// Boards beyond 28 (128-bit totals): at most this many rows below a prefix,
+// so that a per-subproblem count (at most 20! < 2^62 placements) and its
+// weighted value stay within 64 bits.
+constexpr uint32_t kMaxRowsBelowWide = 20;
+
+// Largest kings board whose total fits in 64 bits.
+constexpr uint32_t kMaxKingsN = 21;
+
 void set_hip_error(int err) { g_last_hip_error = err; }
 
 namespace {
@@ -163,7 +171,7 @@ static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
     uint64_t* d_nodes = opts ? opts->d_nodes : nullptr;
     const bool kings = opts && (opts->flags & NQ_FLAG_KINGS);
     rc = plan_launch(dev, mode, opts ? opts->wg_size : 0, opts ? opts->waves_per_cu : 0, frames,
-                     len, d_nodes != nullptr, leafctr_ok(n, min_placed), &cfg, false, kings);
+                     len, d_nodes != nullptr, leafctr_ok(n, min_placed), &cfg, false, kings, n);
     if (rc != NQ_OK) return rc;
     hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
     unsigned long long* head = nullptr;
@@ -175,6 +183,7 @@ static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
     P.idle_min = default_idle_min();
     P.claim = (opts && opts->claim) ? opts->claim : default_claim(len, cfg);
     P.reverse = (opts && (opts->flags & NQ_FLAG_FORWARD_ORDER)) ? 0u : 1u;
+    P.wide = (opts && (opts->flags & NQ_FLAG_WIDE_TOTAL)) ? 1u : 0u;
     EventTimer t;
     if (kernel_ms) rc = t.start(s);
     if (rc == NQ_OK) rc = launch_dfs(cfg, P, s);
@@ -331,10 +340,10 @@ int build_device_frontier_at(uint32_t n, uint32_t host_depth, uint32_t rows, voi
 // Counts chunks first.. of the (n, depth) count: chunk i is the range
 // [F*i/chunks, F*(i+1)/chunks) of the host frontier of host_depth, deepened
 // on the device in equal steps of up to three rows and searched by one
-// launch.  At most max_run chunks (0 = all the rest); after each one
-// on_chunk(chunks done, its weighted count) is called, and a status other
-// than NQ_OK from it stops the loop.  kernel_ms (nullable) accumulates the
-// DFS kernel time.
+// launch into a 128-bit device total.  At most max_run chunks (0 = all the
+// rest); after each one on_chunk(chunks done, its weighted count as an
+// unsigned __int128) is called, and a status other than NQ_OK from it stops
+// the loop.  kernel_ms (nullable) accumulates the DFS kernel time.
 template <class OnChunk>
 int count_chunks(uint32_t n, const nq_opts& local, uint32_t depth, uint32_t host_depth,
                  uint32_t chunks, uint32_t first, uint32_t max_run, double* kernel_ms,
@@ -354,12 +363,14 @@ int count_chunks(uint32_t n, const nq_opts& local, uint32_t depth, uint32_t host
     int rc = NQ_OK;
     hipStream_t s = (hipStream_t)local.stream;
     DevBuf tot;
-    if ((rc = tot.alloc(8)) != NQ_OK) return rc;
-    auto* d_total = tot.as<unsigned long long>();
+    if ((rc = tot.alloc(16)) != NQ_OK) return rc;
+    auto* d_total = tot.as<unsigned long long>();   // low word, high word
+    nq_opts wide = local;
+    wide.flags |= NQ_FLAG_WIDE_TOTAL;
     uint32_t ran = 0;
     for (uint32_t i = first; i < chunks && (max_run == 0 || ran < max_run); ++i, ++ran) {
         const uint64_t lo = Fh * i / chunks, hi = Fh * (i + 1) / chunks;
-        uint64_t part = 0;
+        unsigned __int128 part = 0;
         TraceRange chunk_range("chunk");
         if (hi > lo) {
             DeviceFrontier cur;
@@ -377,12 +388,14 @@ int count_chunks(uint32_t n, const nq_opts& local, uint32_t depth, uint32_t host
                 have += rows;
             }
             double ms = 0.0;
-            if ((rc = launch_zero_u64(d_total, 1, s)) != NQ_OK) return rc;
+            if ((rc = launch_zero_u64(d_total, 2, s)) != NQ_OK) return rc;
             if ((rc = run_device(n, cur.cols, cur.ld, cur.rd, cur.w, cur.len, nullptr, d_total,
-                                 depth, &local, kernel_ms ? &ms : nullptr)) != NQ_OK)
+                                 depth, &wide, kernel_ms ? &ms : nullptr)) != NQ_OK)
                 return rc;
-            NQ_HIP(hipMemcpyAsync(&part, d_total, 8, hipMemcpyDeviceToHost, s));
+            uint64_t words[2] = {0, 0};
+            NQ_HIP(hipMemcpyAsync(words, d_total, 16, hipMemcpyDeviceToHost, s));
             NQ_HIP(hipStreamSynchronize(s));
+            part = ((unsigned __int128)words[1] << 64) | words[0];
             if (kernel_ms) *kernel_ms += ms;
         }
         if ((rc = on_chunk(i + 1, part)) != NQ_OK) return rc;
@@ -416,7 +429,7 @@ extern "C" int nq_expand(uint32_t n, uint32_t rows, const uint32_t* d_cols, cons
                          const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len,
                          uint32_t* d_ocols, uint32_t* d_old, uint32_t* d_ord, uint8_t* d_oweight,
                          uint64_t capacity, uint64_t* out_len, void* stream) {
-    if (n < 1 || n > NQ_MAX_N || rows < 1 || rows > 3 || !out_len) return NQ_EINVAL;
+    if (n < 1 || n > NQ_MAX_N_WIDE || rows < 1 || rows > 3 || !out_len) return NQ_EINVAL;
     if (len && (!d_cols || !d_ld || !d_rd)) return NQ_EINVAL;
     try {
         DevBuf scratch;
@@ -438,11 +451,17 @@ extern "C" int nq_expand(uint32_t n, uint32_t rows, const uint32_t* d_cols, cons
 extern "C" int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
                                     const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len,
                                     uint64_t* d_counts, uint64_t* d_total, const nq_opts* opts) {
-    if (n < 1 || n > NQ_MAX_N) return NQ_EINVAL;
+    if (n < 1 || n > NQ_MAX_N_WIDE) return NQ_EINVAL;
     if (opts && (opts->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
+    const uint32_t min_placed = opts ? std::min(opts->depth, n) : 0u;
+    if (n > NQ_MAX_N) {
+        // beyond 64-bit totals: a 128-bit d_total, and at most 20 rows below
+        // every prefix so that each per-subproblem count stays below 20! < 2^62
+        const bool wide = opts && (opts->flags & NQ_FLAG_WIDE_TOTAL);
+        if ((d_total && !wide) || min_placed + kMaxRowsBelowWide < n) return NQ_EINVAL;
+    }
     if (len == 0) return NQ_OK;
     if (!d_cols || !d_ld || !d_rd) return NQ_EINVAL;
-    const uint32_t min_placed = opts ? std::min(opts->depth, n) : 0u;
     try {
         return run_device(n, d_cols, d_ld, d_rd, d_weight, len, d_counts,
                           reinterpret_cast<unsigned long long*>(d_total), min_placed, opts,
@@ -455,6 +474,7 @@ extern "C" int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const ui
 extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total) {
     if (n < 1 || n > NQ_MAX_N || !out_total) return NQ_EINVAL;
     if (opts_in && (opts_in->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
+    if (opts_in && (opts_in->flags & NQ_FLAG_WIDE_TOTAL)) return NQ_EINVAL;  // no device total
     // Automatic depth: the autotuner's choice for this n if it ran, else the
     // frontier-size rule.  A tuned launch shape fills fields left at 0.
     nq_opts local{};
@@ -462,6 +482,8 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
     local.d_nodes = nullptr;          // per-entry nodes are a nq_count_subproblems output
     const nq_opts* opts = &local;
     const bool kings = (local.flags & NQ_FLAG_KINGS) != 0;
+    // the number of king placements passes 2^64 at n = 22 (about n! / e^2)
+    if (kings && n > kMaxKingsN) return NQ_EINVAL;
     if (local.depth == 0 && !kings) {
         nq_tuned t;
         if (tune_lookup(n, &t) == NQ_OK) {
@@ -486,8 +508,8 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
             local.depth = plan->depth;
             int rc = count_chunks(n, local, plan->depth, 5, plan->chunks, 0, 0,
                                   opts_in && opts_in->kernel_ms_out ? &ms : nullptr,
-                                  [&](uint32_t, uint64_t part) {
-                                      total += part;
+                                  [&](uint32_t, unsigned __int128 part) {
+                                      total += (uint64_t)part;    // Q(n <= 23) < 2^64
                                       return (int)NQ_OK;
                                   });
             if (rc != NQ_OK) return rc;
@@ -572,8 +594,35 @@ constexpr uint32_t kResumeChunks = 64;
 
 struct Progress {
     uint32_t n = 0, depth = 0, host_depth = 0, chunks = 0, done = 0;
-    uint64_t total = 0;
+    unsigned __int128 total = 0;
 };
+
+// Decimal text of a 128-bit count.
+std::string u128_text(unsigned __int128 v) {
+    char buf[48];
+    int i = sizeof buf - 1;
+    buf[i] = 0;
+    do {
+        buf[--i] = (char)('0' + (int)(v % 10));
+        v /= 10;
+    } while (v != 0);
+    return std::string(buf + i);
+}
+
+// Parses 1..39 decimal digits into *v; false on anything else or overflow.
+bool u128_parse(const char* s, size_t len, unsigned __int128* v) {
+    if (len == 0 || len > 39) return false;
+    const unsigned __int128 max = ~(unsigned __int128)0;
+    unsigned __int128 x = 0;
+    for (size_t i = 0; i < len; ++i) {
+        if (s[i] < '0' || s[i] > '9') return false;
+        const unsigned d = (unsigned)(s[i] - '0');
+        if (x > (max - d) / 10) return false;
+        x = x * 10 + d;
+    }
+    *v = x;
+    return true;
+}
 
 // FNV-1a (64-bit) of the record text: catches a torn or edited file.
 uint64_t fnv1a64(const std::string& s) {
@@ -586,11 +635,10 @@ uint64_t fnv1a64(const std::string& s) {
 }
 
 std::string progress_body(const Progress& p) {
-    char buf[192];
-    std::snprintf(buf, sizeof buf,
-                  "nq-progress 1 n=%u depth=%u host_depth=%u chunks=%u done=%u total=%llu", p.n,
-                  p.depth, p.host_depth, p.chunks, p.done, (unsigned long long)p.total);
-    return buf;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "nq-progress 1 n=%u depth=%u host_depth=%u chunks=%u done=%u total=",
+                  p.n, p.depth, p.host_depth, p.chunks, p.done);
+    return buf + u128_text(p.total);
 }
 
 // NQ_OK with *exists = false when there is no file; NQ_EINVAL when the file
@@ -604,14 +652,18 @@ int progress_read(const char* path, Progress* p, bool* exists) {
     std::fclose(f);
     if (!got) return NQ_EINVAL;
     unsigned n, depth, hd, chunks, done;
-    unsigned long long total, check;
+    unsigned long long check;
+    int t0 = -1, t1 = -1;
+    // the total is up to 128 bits: its digits are located by %n and parsed apart
     if (std::sscanf(line,
-                    "nq-progress 1 n=%u depth=%u host_depth=%u chunks=%u done=%u total=%llu "
+                    "nq-progress 1 n=%u depth=%u host_depth=%u chunks=%u done=%u total=%n%*[0-9]%n "
                     "check=%llx",
-                    &n, &depth, &hd, &chunks, &done, &total, &check) != 7)
+                    &n, &depth, &hd, &chunks, &done, &t0, &t1, &check) != 6 ||
+        t0 < 0 || t1 <= t0)
         return NQ_EINVAL;
     Progress q;
-    q.n = n; q.depth = depth; q.host_depth = hd; q.chunks = chunks; q.done = done; q.total = total;
+    q.n = n; q.depth = depth; q.host_depth = hd; q.chunks = chunks; q.done = done;
+    if (!u128_parse(line + t0, (size_t)(t1 - t0), &q.total)) return NQ_EINVAL;
     if (fnv1a64(progress_body(q)) != check || q.done > q.chunks) return NQ_EINVAL;
     *p = q;
     *exists = true;
@@ -646,38 +698,46 @@ int progress_write(const char* path, const Progress& p) {
 
 }  // namespace
 
-extern "C" int nq_count_resumable(uint32_t n, const nq_opts* opts_in, const char* path,
-                                  uint32_t chunks, uint32_t max_chunks, uint64_t* out_total,
-                                  uint32_t* out_done) {
-    if (n < 1 || n > NQ_MAX_N || !path || !*path || !out_total || !out_done) return NQ_EINVAL;
+// Both resumable entry points: n up to max_n, the total in 128 bits.
+static int count_resumable(uint32_t n, const nq_opts* opts_in, const char* path, uint32_t chunks,
+                           uint32_t max_chunks, uint32_t max_n, unsigned __int128* out_total,
+                           uint32_t* out_done) {
+    if (n < 1 || n > max_n || !path || !*path || !out_total || !out_done) return NQ_EINVAL;
     if (opts_in && (opts_in->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
     if (opts_in && (opts_in->counts_out || opts_in->d_nodes)) return NQ_EINVAL;
     if (opts_in && (opts_in->flags & NQ_FLAG_KINGS)) return NQ_EINVAL;
     nq_opts local{};
     if (opts_in) local = *opts_in;
     local.kernel_ms_out = nullptr;
-    if (local.depth == 0) {
-        nq_tuned t;
-        if (tune_lookup(n, &t) == NQ_OK) {
-            local.depth = t.depth;
-            if (!local.waves_per_cu) local.waves_per_cu = t.waves_per_cu;
-            if (!local.refill_every) local.refill_every = t.refill_every;
-            if (!local.claim) local.claim = t.claim;
-        }
-    }
-    const uint32_t depth = local.depth ? local.depth : auto_depth(n);
-    if (depth > n) return NQ_EINVAL;
-    local.depth = depth;
     try {
-        Progress pr;
-        pr.n = n;
-        pr.depth = depth;
-        pr.host_depth = std::min(depth, kResumeHostDepth);
-        pr.chunks = chunks ? chunks : kResumeChunks;
         Progress old;
         bool exists = false;
         int rc = progress_read(path, &old, &exists);
         if (rc != NQ_OK) return rc;
+        const uint32_t nchunks = chunks ? chunks : kResumeChunks;
+        // The automatic depth must be the same in every process that works on
+        // one file, so it never comes from this process's tuning results: the
+        // depth of a record of the same count, else the chunk plan of n, else
+        // the frontier-size rule (for boards beyond 28 at least n - 20 rows).
+        uint32_t depth = local.depth;
+        if (depth == 0) {
+            if (exists && old.n == n && old.chunks == nchunks) {
+                depth = old.depth;
+            } else if (n > NQ_MAX_N) {
+                depth = n - kMaxRowsBelowWide;            // 9..11 for 29..31
+            } else {
+                const ChunkPlan* plan = chunk_plan(n);
+                depth = plan ? plan->depth : auto_depth(n);
+            }
+        }
+        if (depth > n) return NQ_EINVAL;
+        if (n > NQ_MAX_N && depth + kMaxRowsBelowWide < n) return NQ_EINVAL;
+        local.depth = depth;
+        Progress pr;
+        pr.n = n;
+        pr.depth = depth;
+        pr.host_depth = std::min(depth, kResumeHostDepth);
+        pr.chunks = nchunks;
         if (exists) {
             if (old.n != pr.n || old.depth != pr.depth || old.host_depth != pr.host_depth ||
                 old.chunks != pr.chunks)
@@ -686,7 +746,7 @@ extern "C" int nq_count_resumable(uint32_t n, const nq_opts* opts_in, const char
         }
         if (pr.done < pr.chunks) {
             rc = count_chunks(n, local, depth, pr.host_depth, pr.chunks, pr.done, max_chunks,
-                              nullptr, [&](uint32_t done, uint64_t part) {
+                              nullptr, [&](uint32_t done, unsigned __int128 part) {
                                   pr.total += part;
                                   pr.done = done;
                                   return progress_write(path, pr);
@@ -701,4 +761,29 @@ extern "C" int nq_count_resumable(uint32_t n, const nq_opts* opts_in, const char
     } catch (...) {
         return NQ_EINVAL;
     }
+}
+
+extern "C" int nq_count_resumable(uint32_t n, const nq_opts* opts, const char* path,
+                                  uint32_t chunks, uint32_t max_chunks, uint64_t* out_total,
+                                  uint32_t* out_done) {
+    if (!out_total) return NQ_EINVAL;
+    unsigned __int128 total = 0;
+    const int rc = count_resumable(n, opts, path, chunks, max_chunks, NQ_MAX_N, &total, out_done);
+    if (rc != NQ_OK && rc != NQ_EAGAIN) return rc;
+    if ((total >> 64) != 0) return NQ_ERANGE;           // a wide record: *out_done is written
+    *out_total = (uint64_t)total;
+    return rc;
+}
+
+extern "C" int nq_count_resumable_wide(uint32_t n, const nq_opts* opts, const char* path,
+                                       uint32_t chunks, uint32_t max_chunks, uint64_t* out_total,
+                                       uint32_t* out_done) {
+    if (!out_total) return NQ_EINVAL;
+    unsigned __int128 total = 0;
+    const int rc =
+        count_resumable(n, opts, path, chunks, max_chunks, NQ_MAX_N_WIDE, &total, out_done);
+    if (rc != NQ_OK && rc != NQ_EAGAIN) return rc;
+    out_total[0] = (uint64_t)total;
+    out_total[1] = (uint64_t)(total >> 64);
+    return rc;
 }

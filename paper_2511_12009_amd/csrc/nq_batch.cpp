@@ -63,7 +63,8 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
                  nq_batch** out) {
     if (!out || ninst == 0 || !ns) return NQ_EINVAL;
     if (opts && (opts->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
-    if (opts && (opts->flags & NQ_FLAG_KINGS)) return NQ_EINVAL;   // queens only
+    // queens only; per-instance totals are 64-bit (every board <= 28)
+    if (opts && (opts->flags & (NQ_FLAG_KINGS | NQ_FLAG_WIDE_TOTAL))) return NQ_EINVAL;
     for (uint32_t i = 0; i < ninst; ++i) {
         if (ns[i] < 1 || ns[i] > NQ_MAX_N) return NQ_EINVAL;
         if (depths && (depths[i] < 1 || depths[i] > ns[i])) return NQ_EINVAL;
@@ -88,7 +89,7 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
         std::vector<uint32_t> k(ninst);
         std::vector<uint64_t> off(ninst + 1, 0);
         std::vector<DeviceFrontier> fr(ninst);
-        uint32_t frames = 1;
+        uint32_t frames = 1, max_n = 1;
         bool leafctr = true;
         for (uint32_t i = 0; i < ninst; ++i) {
             k[i] = depths ? depths[i] : batch_default_depth(ns[i], opts ? opts->depth : 0);
@@ -97,6 +98,7 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
             off[i + 1] = off[i] + fr[i].len;
             frames = std::max(frames, frames_needed(ns[i], k[i]));
             leafctr = leafctr && leafctr_ok(ns[i], k[i]);
+            max_n = std::max(max_n, ns[i]);
         }
         const uint64_t total = off[ninst];
         b->entries = total;
@@ -166,7 +168,7 @@ int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, con
         if ((rc = device_info(&dev)) != NQ_OK) return fail(rc);
         if ((rc = plan_launch(dev, NQ_MODE_PERSISTENT, opts ? opts->wg_size : 0,
                               opts ? opts->waves_per_cu : 0, frames, total, false, leafctr,
-                              &b->cfg)) != NQ_OK)
+                              &b->cfg, false, false, max_n)) != NQ_OK)
             return fail(rc);
         P.claim = (opts && opts->claim) ? opts->claim : default_claim(total, b->cfg);
         // Capture: zero totals, zero head + DFS, totals to pinned host memory.

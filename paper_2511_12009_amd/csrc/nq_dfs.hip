@@ -41,9 +41,9 @@ namespace nqi {
 
 // Default inner-loop form of the DFS kernels (see nq_dfs_kernel).
 constexpr int kDefaultLoop = 1;
-constexpr int kLoopForms = 6;          // forms 0..5 (3 is not used)
+constexpr int kLoopForms = 6;          // forms 0..5
 // LDS frames per lane that a form needs beyond N - 2 - placed.
-constexpr uint32_t kFormExtraFrames[kLoopForms] = {0, 0, 0, 0, 1, 1};
+constexpr uint32_t kFormExtraFrames[kLoopForms] = {0, 0, 0, 1, 1, 1};
 
 namespace {
 
@@ -216,6 +216,33 @@ __device__ __forceinline__ uint32_t isa_neg_any(uint32_t a, uint64_t& am) {
     return n;
 }
 
+// Form 3's first instructions: p = lowest untried column of w, w loses it (in
+// place), and alive = lanes whose w was not empty (the borrow of 0 - w), read
+// by SALU code only.
+__device__ __forceinline__ void isa_take_alive(uint32_t& w, uint32_t& p, uint64_t& alive) {
+    uint32_t neg;
+    asm("v_sub_co_u32 %[n], %[al], 0, %[w]\n\t"
+        "v_and_b32 %[p], %[w], %[n]\n\t"
+        "v_xor_b32 %[w], %[w], %[p]"
+        : [w] "+v"(w), [p] "=&v"(p), [n] "=&v"(neg), [al] "=&s"(alive));
+}
+
+// Form 3's pop: frame <- [top], top -= 1024 for the lanes in `m`, with no
+// clamp (a lane pops only while it has work, so it pops its sentinel at most
+// once); the loaded frame is waited for before the block ends.
+__device__ __forceinline__ void isa_pop_free(u32x4& st, int32_t& top, uint64_t m) {
+    uint64_t sv;
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[m]\n\t"
+        "ds_read_b128 %[st], %[top]\n\t"
+        "v_add_u32 %[top], 0xfffffc00, %[top]\n\t"
+        "s_mov_b64 exec, %[sv]\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [st] "+v"(st), [top] "+v"(top), [sv] "=&s"(sv)
+        : [m] "s"(m)
+        : "memory", "scc");
+}
+
 // One step's stack and frame update for form 2: lanes in `pm` store the frame
 // at [top + 1024] and advance top, lanes in `dm` take the child frame `ch`
 // (four v_cndmask), lanes in `qm` reload the frame at [top] and step top back.
@@ -248,8 +275,9 @@ __device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, u
 }
 
 // LOOP selects the inner-loop form: 0 = plain C++ (the compiler places the
-// exec masks), 1 = hand-placed exec masks (the default), 2 = as 1 with the
-// untried set kept negated so that two lane masks come from carries.  Two
+// exec masks), 1 = hand-placed exec masks, 2 = as 1 with the untried set kept
+// negated so that two lane masks come from carries, 3 = the step without
+// selects (see below).  Two
 // more forms exist to measure the paper's own design choices: 4 keeps the
 // frame being expanded in the LDS stack too (read every step, its untried set
 // written back: Algorithm 2 as the paper prints it, with the last-row step of
@@ -274,10 +302,12 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     *frame_at(floor) = u32x4{kParked, 0u, 0u, 0u};
 
     uint32_t c = kParked, l = 0, r = 0, v = 0, last = 0, nm1 = 0, step_k = 0;
+    uint32_t leaf_lim = 0;                // form 3 with LEAFCTR: rd below this = leaf
     uint64_t idx = 0;
     uint32_t sum32 = 0, steps32 = 0;
     uint64_t sum64 = 0, steps64 = 0;
     uint64_t wtotal = 0;                  // weighted total, single-instance launches
+    uint64_t wtotal_hi = 0;               // its carries (128-bit totals, P.wide)
     uint32_t acc_s = 0u;                  // batches: instance of the lane's pending sum
     uint64_t acc_v = 0;                   // batches: weighted sum not yet added
     bool has_task = false;                // holds an entry not yet retired
@@ -314,16 +344,29 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         const uint32_t avail = last & ~(c | l | r);
         step_k = LEAFCTR ? (1u << n) : 0u;
         *frame_at(floor) = u32x4{kParked, 0u, 0u, 0u};
-        if (bad_inst || n < 1u || n > NQ_MAX_N) {
+        if (bad_inst || n < 1u || n > NQ_MAX_N_WIDE) {
             sum64 = kCountInvalid;        // instance id or board size out of range
         } else if (placed >= nm1) {
             sum32 = (placed == n) ? 1u : __popc(avail);
         } else if (n - 2u - placed > P.frames - kFormExtraFrames[LOOP] ||
-                   (LEAFCTR && nm1 - placed > (1u << (31u - n)))) {
+                   (LEAFCTR && LOOP != 3 && nm1 - placed > (1u << (31u - n))) ||
+                   (LEAFCTR && LOOP == 3 && 2u * n - 1u - placed > 31u)) {
             sum64 = kCountInvalid;        // does not fit this launch's stack or counter
         } else if (avail != 0u) {
             v = avail;
-            if (LEAFCTR) c |= ((1u << (31u - n)) - (nm1 - placed)) << n;
+            if (LOOP == 3) {
+                // form 3: the columns off the board count as taken, so the free
+                // squares of the next row are one 3-input NOR; with LEAFCTR a
+                // marker bit rides in rd, one place lower per row, and reaches
+                // bit n exactly in the frames of the last row
+                c |= ~last;
+                if (LEAFCTR) {
+                    r |= 1u << (2u * n - 1u - placed);
+                    leaf_lim = 2u << n;
+                }
+            } else if (LEAFCTR) {
+                c |= ((1u << (31u - n)) - (nm1 - placed)) << n;
+            }
         }
         if (v == 0u) c = kParked;         // nothing to search: park like a finished lane
     };
@@ -349,7 +392,9 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
             if (P.totals && ok && sum64 != 0) {
                 const uint64_t w = P.weight ? (uint64_t)P.weight[idx] : 1u;
                 if (!P.inst) {
-                    wtotal += w * sum64;
+                    const uint64_t add = w * sum64;
+                    wtotal += add;
+                    wtotal_hi += (wtotal < add) ? 1u : 0u;
                 } else if (SERVE) {
                     req_val = w * sum64;          // serving: added per wave below
                 } else {
@@ -489,6 +534,48 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
             chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
             if (chunks == 0u || chunk_done(st.w)) break;
         }
+        } else if (LOOP == 3) {
+        // Form 3: no selects.  Each step pushes the frame being expanded when
+        // it still has an untried column, computes the child into the other
+        // register frame, and pops when the child is not searched (no free
+        // square, or a leaf): a descent leaves the child in place, and a dead
+        // child or a leaf is replaced by the frame just pushed (or, when that
+        // had nothing left, by the nearest ancestor with work).  Lanes pop
+        // only while they had an untried column, so the stack pointer needs no
+        // clamp.  The frame at row N-2 is pushed before its leaf children are
+        // counted: one LDS frame more than form 1.  Two register frames
+        // alternate (two steps per trip), so the child is written without
+        // moves and can be computed while the parent is being pushed.
+        auto step3 = [&](u32x4& A, u32x4& B) {
+            uint32_t p, rest = A.w;
+            uint64_t alive;
+            isa_take_alive(rest, p, alive);           // the untried rest keeps A.w's register
+            A.w = rest;
+            const uint64_t restm = __builtin_amdgcn_ballot_w64(A.w != 0u);
+            B.x = A.x + p;                            // p is free: + is |
+            B.y = (A.y + p) << 1;
+            B.z = (A.z + p) >> 1;
+            B.w = ~(B.x | B.y | B.z);                 // off-board columns are set in B.x
+            const uint64_t leafm = __builtin_amdgcn_ballot_w64(
+                LEAFCTR ? B.z < leaf_lim : __popc(B.x) == 31u);
+            const uint64_t anym = __builtin_amdgcn_ballot_w64(B.w != 0u);
+            if (STATS) isa_count(steps32, alive);
+            isa_count(sum32, anym & leafm);
+            isa_push(A, top, restm);
+            isa_pop_free(B, top, alive & ~(anym & ~leafm));
+        };
+        uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 63u) / 64u);
+        u32x4 other;
+        for (;;) {
+            uint32_t trips = 32u;
+            do {
+                step3(st, other);
+                step3(other, st);
+                trips = __builtin_amdgcn_readfirstlane(trips - 1u);
+            } while (trips != 0u);
+            chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
+            if (chunks == 0u || chunk_done(st.w)) break;
+        }
         } else if (LOOP == 4) {
         // The paper's loop as printed: the frame being expanded is the top
         // of the LDS stack, read at every step, with its untried set written
@@ -593,8 +680,22 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     if (!SERVE && P.totals && P.inst && acc_v)
         atomicAdd(&P.totals[acc_s], (unsigned long long)acc_v);
     if (P.totals && !P.inst) {
-        for (int off = 32; off > 0; off >>= 1) wtotal += shfl_xor_u64(wtotal, off);
-        if (lane == 0 && wtotal != 0) atomicAdd(&P.totals[0], (unsigned long long)wtotal);
+        // 128-bit wave sum (the high word holds the carries; it stays 0 unless
+        // one wave's share exceeds 2^64, possible only for boards beyond 28)
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t lo = shfl_xor_u64(wtotal, off);
+            wtotal_hi += shfl_xor_u64(wtotal_hi, off);
+            wtotal += lo;
+            wtotal_hi += (wtotal < lo) ? 1u : 0u;
+        }
+        if (lane == 0 && (wtotal | wtotal_hi) != 0) {
+            const unsigned long long before =
+                atomicAdd(&P.totals[0], (unsigned long long)wtotal);
+            if (P.wide) {
+                const uint64_t carry = wtotal_hi + ((before + wtotal < before) ? 1u : 0u);
+                if (carry) atomicAdd(&P.totals[1], (unsigned long long)carry);
+            }
+        }
     }
 }
 
@@ -645,11 +746,16 @@ static const void* select_kings_kernel(uint32_t mode, bool stats, bool leafctr) 
 }
 
 // The kernel for a launch shape; serving launches exist only as persistent,
-// row-counter, no-statistics kernels (nullptr otherwise).
+// no-statistics kernels, with the row counter except in form 3 (nullptr
+// otherwise).
 template <int LOOP>
 static const void* select_kernel_loop(uint32_t mode, bool stats, bool leafctr, bool serve) {
     const bool pers = mode == NQ_MODE_PERSISTENT;
-    if (serve) return (pers && !stats && leafctr) ? kernel_ptr<true, false, true, LOOP, true>() : nullptr;
+    if (serve) {
+        if (!pers || stats) return nullptr;
+        if (leafctr) return kernel_ptr<true, false, true, LOOP, true>();
+        return LOOP == 3 ? kernel_ptr<true, false, false, LOOP, true>() : nullptr;
+    }
     if (pers) {
         if (stats)
             return leafctr ? kernel_ptr<true, true, true, LOOP>() : kernel_ptr<true, true, false, LOOP>();
@@ -670,14 +776,14 @@ static int loop_form() {
     if (f >= 0) return f;
     const char* e = std::getenv("NQ_DFS_LOOP");
     f = kDefaultLoop;
-    if (e && e[0] >= '0' && e[0] <= '5' && e[0] != '3' && e[1] == 0) f = e[0] - '0';
+    if (e && e[0] >= '0' && e[0] <= '5' && e[1] == 0) f = e[0] - '0';
     int expect = -1;
     g_loop_form.compare_exchange_strong(expect, f);
     return g_loop_form.load(std::memory_order_relaxed);
 }
 
 int set_loop_form(int form, int* previous) {
-    if (form < -1 || form >= kLoopForms || form == 3) return NQ_EINVAL;
+    if (form < -1 || form >= kLoopForms) return NQ_EINVAL;
     if (previous) *previous = loop_form();
     g_loop_form.store(form, std::memory_order_relaxed);   // -1: read again on next use
     return NQ_OK;
@@ -719,6 +825,7 @@ static const void* select_kernel(int form, uint32_t mode, bool stats, bool leafc
         case 0: return select_kernel_loop<0>(mode, stats, leafctr, serve);
         case 1: return select_kernel_loop<1>(mode, stats, leafctr, serve);
         case 2: return select_kernel_loop<2>(mode, stats, leafctr, serve);
+        case 3: return select_kernel_loop<3>(mode, stats, leafctr, serve);
         case 4: return select_kernel_loop<4>(mode, stats, leafctr, serve);
         case 5: return select_kernel_loop<5>(mode, stats, leafctr, serve);
         default: return nullptr;
@@ -757,9 +864,13 @@ int device_info(DeviceInfo* out) {
 
 int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t waves_per_cu,
                 uint32_t frames, uint64_t len, bool stats, bool leafctr, LaunchCfg* cfg,
-                bool serve, bool kings) {
+                bool serve, bool kings, uint32_t max_n) {
     if (mode != NQ_MODE_PLAIN && mode != NQ_MODE_PERSISTENT) return NQ_EINVAL;
-    const int form = loop_form();
+    // the kings search runs form 1 only (its rd carries no marker)
+    const int form = kings ? 1 : loop_form();
+    // form 3's marker starts at bit 2n - 1 - placed = n + 1 + (frames of the
+    // entry): it fits in 32 bits for every entry when max_n + frames <= 30
+    if (form == 3) leafctr = leafctr && max_n + frames <= 30u;
     frames += kFormExtraFrames[form];
     if (wg_size == 0) {
         // Plain: up to 4 waves per workgroup, as many as the LDS stacks allow.

@@ -132,7 +132,7 @@ int expand_device(uint32_t n, uint32_t rows, const uint32_t* cols, const uint32_
                   const uint32_t* rd, const uint8_t* w, uint64_t len, uint32_t* ocols,
                   uint32_t* old, uint32_t* ord, uint8_t* ow, uint64_t cap, uint64_t* out_len,
                   void* scratch, void* stream) {
-    if (n < 1 || n > NQ_MAX_N || rows < 1 || rows > kMaxExpandRows || !out_len) return NQ_EINVAL;
+    if (n < 1 || n > NQ_MAX_N_WIDE || rows < 1 || rows > kMaxExpandRows || !out_len) return NQ_EINVAL;
     if (len >= (uint64_t)0x7fffffff) return NQ_EINVAL;        // scan index range
     hipStream_t s = (hipStream_t)stream;
     if (len == 0) { *out_len = 0; return NQ_OK; }

@@ -170,7 +170,7 @@ std::vector<uint64_t> root_offsets(uint32_t n, const std::vector<Root>& roots) {
 int frontier_fill(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld, uint32_t* rd,
                   uint8_t* weight, uint64_t capacity, uint64_t* out_len,
                   std::vector<uint64_t>* first_row_offsets, bool kings) {
-    if (n < 1 || n > NQ_MAX_N || depth > n || !out_len) return NQ_EINVAL;
+    if (n < 1 || n > NQ_MAX_N_WIDE || depth > n || !out_len) return NQ_EINVAL;
     std::vector<Root> roots = frontier_roots(n, depth, kings);
     std::vector<uint64_t> off = root_offsets(n, roots);
     const uint64_t total = off.back();
@@ -216,7 +216,7 @@ int frontier_fill(uint32_t n, uint32_t depth, uint32_t* cols, uint32_t* ld, uint
 
 extern "C" int nq_frontier_runs(uint32_t n, uint32_t depth, uint64_t* offsets, uint32_t capacity,
                                 uint32_t* out_runs) {
-    if (n < 1 || n > NQ_MAX_N || depth < 1 || depth > n || !out_runs) return NQ_EINVAL;
+    if (n < 1 || n > NQ_MAX_N_WIDE || depth < 1 || depth > n || !out_runs) return NQ_EINVAL;
     try {
         std::vector<uint64_t> runs;
         uint64_t total = 0;

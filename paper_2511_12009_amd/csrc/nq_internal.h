@@ -48,6 +48,8 @@ struct DfsParams {
     uint32_t frames;                // LDS stack frames per lane
     uint32_t refill_every;          // DFS steps between scheduler visits
     uint32_t reverse;               // persistent: claim entries from the last one down
+    uint32_t wide;                  // totals[0..1] is one 128-bit total (low word first),
+                                    // increased with carry (single-instance launches only)
     // Serving (all null / 0 otherwise).  Entries live in a ring: logical entry
     // i is physical (base + i) mod wrap.  The entries of one instance that a
     // wave retires together are added to totals[inst] and subtracted from
@@ -87,7 +89,7 @@ struct LaunchCfg {
     uint32_t grid;          // workgroups
     uint32_t lds_bytes;     // dynamic LDS per workgroup
     bool stats;             // count DFS steps per entry
-    bool leafctr;           // row counter in the high bits of cols (see the kernel)
+    bool leafctr;           // row counter in the high bits of cols (form 3: marker in rd)
     bool serve;             // serving epoch: per-request retirement (P.remaining set)
     int form;               // inner-loop form the launch was planned for
     bool kings;             // the kings search (NQ_FLAG_KINGS)
@@ -118,12 +120,15 @@ struct DeviceInfo {
 
 int device_info(DeviceInfo* out);
 
-// Fills `cfg` for `len` entries needing `frames` frames per lane; `serve`
-// plans a serving epoch (persistent, leafctr, no statistics only), `kings` a
-// launch of the kings search (default inner-loop form only).
+// Fills `cfg` for `len` entries of boards of at most `max_n` columns needing
+// `frames` frames per lane (before the extra frames of the inner-loop form);
+// `leafctr` says whether form 1's row counter fits every entry, and the
+// launch uses the row counter (or form 3's marker) only where it fits;
+// `serve` plans a serving epoch (persistent, no statistics), `kings` a launch
+// of the kings search (inner-loop form 1).
 int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t waves_per_cu,
                 uint32_t frames, uint64_t len, bool stats, bool leafctr, LaunchCfg* cfg,
-                bool serve = false, bool kings = false);
+                bool serve = false, bool kings = false, uint32_t max_n = NQ_MAX_N_WIDE);
 
 // Enqueues the DFS kernel (and, for the persistent mode, the zeroing of
 // *P.head) on `stream`.  Returns NQ_OK or NQ_EDEVICE.

@@ -433,7 +433,8 @@ void destroy_all(nq_server* s) {
 int serve_create(const nq_opts* opts, uint64_t hbm_budget, nq_server** out) {
     if (!out) return NQ_EINVAL;
     if (opts && (opts->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
-    if (opts && (opts->flags & NQ_FLAG_KINGS)) return NQ_EINVAL;   // queens only
+    // queens only; request totals are 64-bit (every board <= 28)
+    if (opts && (opts->flags & (NQ_FLAG_KINGS | NQ_FLAG_WIDE_TOTAL))) return NQ_EINVAL;
     nq_server* s = new (std::nothrow) nq_server();
     if (!s) return NQ_ENOMEM;
     if (opts) s->launch = *opts;

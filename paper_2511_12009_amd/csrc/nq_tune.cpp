@@ -65,7 +65,7 @@ int trial(uint32_t n, uint32_t depth, const TrialFrontier& tf, uint32_t waves_pe
     const uint32_t frames = std::max<uint32_t>(1, frames_needed(n, depth));
     LaunchCfg cfg;
     rc = plan_launch(dev, NQ_MODE_PERSISTENT, 0, waves_per_cu, frames, fr.len, false,
-                     leafctr_ok(n, depth), &cfg);
+                     leafctr_ok(n, depth), &cfg, false, false, n);
     if (rc != NQ_OK) return rc;
     DfsParams P{};
     P.cols = fr.cols; P.ld = fr.ld; P.rd = fr.rd; P.weight = fr.w;

@@ -12,6 +12,7 @@ MASK64 = (1 << 64) - 1
 
 RAGGED_SEED = 0x251112009
 SERVE_SEED = 0x5E4E
+SLICE_SAMPLE_SEED = 0x5E21
 
 
 def splitmix64(state: int) -> int:
@@ -47,3 +48,13 @@ def serve_count_ns(count: int, lo: int = 10, hi: int = 18, seed: int = SERVE_SEE
     """Board sizes of the COUNT requests of the serving workload: uniform in [lo, hi]."""
     span = hi - lo + 1
     return [lo + splitmix64((seed + 2 * i + 1) & MASK64) % span for i in range(count)]
+
+
+def sample_slices(count: int, nslices: int, seed: int = SLICE_SAMPLE_SEED):
+    """`count` distinct slice indices in [0, nslices), seeded (the oracle checks
+    of the serving workload's N=21 slices use them), in ascending order."""
+    picked, i = set(), 0
+    while len(picked) < min(count, nslices):
+        picked.add(splitmix64((seed + i) & MASK64) % nslices)
+        i += 1
+    return sorted(picked)

@@ -7,6 +7,11 @@ per-prefix counts and nodes (little-endian uint64 in canonical frontier order),
 so that a test can check every per-subproblem result without rerunning the
 oracle.  Usage:  python tests/golden/make_golden.py N:k [N:k ...] [--threads T]
 An existing line for the same (N, k) is replaced.
+
+With --slices N:k:len:count it instead writes oracle_slices.txt: the oracle's
+counts of `count` seeded slices of `len` entries of the (N, k) frontier (slice
+indices from seeded_inputs.sample_slices, plus the last, short slice), one line
+per slice: N k start len weighted_total node_total sha256(counts u64 LE).
 """
 import argparse
 import hashlib
@@ -20,8 +25,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
+import seeded_inputs  # noqa: E402
 
 OUT = os.path.join(HERE, "oracle_runs.txt")
+SLICES_OUT = os.path.join(HERE, "oracle_slices.txt")
+SLICES_HEADER = """# Oracle counts of seeded slices of a frontier (canonical order), written by
+# tests/golden/make_golden.py --slices (oracle only).
+# N k start len weighted_total node_total sha256(counts u64 LE)
+"""
 NODES_OUT = os.path.join(HERE, "oracle_nodes.txt")
 NODES_HEADER = """# Node counts nodes(N, k) (queens placed in rows k..N-2 below every frontier
 # prefix), written by tests/golden/make_golden.py.  "run" lines repeat an
@@ -75,11 +86,37 @@ def write_nodes():
             f.write(f"{n} {k} {v} {src}\n")
 
 
+def write_slices(spec, threads):
+    n, k, length, count = (int(x) for x in spec.split(":"))
+    pre, w = oracle.frontier(n, k)
+    nslices = (len(pre) + length - 1) // length
+    picks = sorted(set(seeded_inputs.sample_slices(count, nslices)) | {nslices - 1})
+    lines = []
+    if os.path.exists(SLICES_OUT):
+        with open(SLICES_OUT) as f:
+            lines = [ln for ln in f if ln.strip() and not ln.startswith("#")]
+    for j in picks:
+        lo, hi = j * length, min(len(pre), (j + 1) * length)
+        counts, nodes = oracle.count_prefixes(n, pre[lo:hi], threads=threads)
+        total = int(np.sum(counts.astype(object) * w[lo:hi].astype(object)))
+        line = f"{n} {k} {lo} {hi - lo} {total} {int(nodes.sum())} {digest(counts)}"
+        print(line, flush=True)
+        lines = [ln for ln in lines if ln.split()[:4] != line.split()[:4]] + [line + "\n"]
+    lines.sort(key=lambda ln: tuple(int(x) for x in ln.split()[:4]))
+    with open(SLICES_OUT, "w") as f:
+        f.write(SLICES_HEADER)
+        f.writelines(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("cases", nargs="*")
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
+    ap.add_argument("--slices", default=None, help="N:k:len:count")
     args = ap.parse_args()
+    if args.slices:
+        write_slices(args.slices, args.threads)
+        return
     for case in args.cases:
         n, k = (int(x) for x in case.split(":"))
         line = run(n, k, args.threads)

@@ -73,6 +73,18 @@ def test_frontier_matches_oracle_bench_shapes(n, k):
     np.testing.assert_array_equal(w, ow)
 
 
+@pytest.mark.parametrize("n,k", [(29, 3), (30, 3), (31, 3), (31, 4)])
+def test_frontier_beyond_64_bit_boards_matches_oracle(n, k):
+    """Boards of 29..31 (beyond the 64-bit counts of Section 4.5, still 32-bit
+    masks): the same prefixes, masks and weights as the oracle, index by index."""
+    cols, ld, rd, w = nq.frontier(n, k)
+    oc, ol, orr, ow = oracle.frontier_masks(n, k)
+    np.testing.assert_array_equal(cols, oc)
+    np.testing.assert_array_equal(ld, ol)
+    np.testing.assert_array_equal(rd, orr)
+    np.testing.assert_array_equal(w, ow)
+
+
 def test_frontier_sizes_match_oracle():
     for n, k in [(20, 5), (20, 6), (21, 6), (18, 5), (19, 5)]:
         assert nq.frontier_size(n, k) == oracle.frontier_size(n, k)
@@ -107,7 +119,8 @@ def test_frontier_rejects_bad_arguments():
     lib = nq.lib()
     ln = ct.c_uint64()
     assert lib.nq_frontier(0, 0, None, None, None, None, 0, ct.byref(ln)) == -1
-    assert lib.nq_frontier(29, 3, None, None, None, None, 0, ct.byref(ln)) == -1
+    assert lib.nq_frontier(32, 3, None, None, None, None, 0, ct.byref(ln)) == -1
+    assert lib.nq_frontier(31, 3, None, None, None, None, 0, ct.byref(ln)) == 0
     assert lib.nq_frontier(8, 9, None, None, None, None, 0, ct.byref(ln)) == -1
     assert lib.nq_frontier(8, 3, None, None, None, None, 0, None) == -1
 
@@ -173,14 +186,17 @@ def test_loop_form_setter_validates_and_restores():
     restores the default."""
     import paper_2511_12009_amd as nq
     prev = nq.set_loop_form(-1)
+    default = nq.set_loop_form(-1)
     try:
-        for bad in (-2, 3, 6, 100):
+        assert default in (1, 3)
+        for bad in (-2, 6, 100):
             with pytest.raises(nq.NQError):
                 nq.set_loop_form(bad)
-        assert nq.set_loop_form(4) == 1
-        assert nq.set_loop_form(5) == 4
+        assert nq.set_loop_form(4) == default
+        assert nq.set_loop_form(3) == 4
+        assert nq.set_loop_form(5) == 3
         assert nq.set_loop_form(-1) == 5
-        assert nq.set_loop_form(-1) == 1
+        assert nq.set_loop_form(-1) == default
     finally:
         nq.set_loop_form(prev)
 
@@ -259,3 +275,64 @@ def test_kings_flag_refused_where_unsupported(tmp_path):
                                                   0, c_.byref(t), c_.byref(d))
         nq._native._check(rc, "nq_count_resumable")
     assert not (tmp_path / "p").exists()
+
+
+def test_wide_resumable_totals_without_a_gpu(tmp_path):
+    """nq_count_resumable_wide keeps 128-bit totals in its progress record: a
+    finished record of any total up to 2^128 - 1 is answered exactly from the
+    file alone (decimal text across the 2^64 carry), a total of 2^128 or more
+    is refused; the 64-bit entry point answers NQ_ERANGE for a total of 2^64 or
+    more and refuses boards beyond 28; the domain of the wide entry point is
+    checked before any device work."""
+    path = str(tmp_path / "wide")
+    for total in (0, 14200, 2**64 - 1, 2**64, 2**64 + 12345, 2**127 + 3, 2**128 - 1):
+        with open(path, "w") as f:
+            f.write(_progress_record(30, 10, 5, 8, 8, total))
+        assert nq.count_resumable(30, path, chunks=8, depth=10, wide=True) == (total, 8, True)
+        # depth 0 continues the record's count
+        assert nq.count_resumable(30, path, chunks=8, wide=True) == (total, 8, True)
+    with pytest.raises(nq.NQError):
+        nq.count_resumable(30, path, chunks=8, depth=10)          # 64-bit entry: n <= 28
+    for bad in (str(2**128), "1" + "0" * 39, "-1", "12a"):
+        text = _progress_record(30, 10, 5, 8, 8, 0).replace("total=0 ", f"total={bad} ")
+        with open(path, "w") as f:
+            f.write(text)
+        with pytest.raises(nq.NQError):
+            nq.count_resumable(30, path, chunks=8, depth=10, wide=True)
+        with open(path) as f:
+            assert f.read() == text
+    big = 2**64 + 7
+    with open(path, "w") as f:
+        f.write(_progress_record(12, 4, 4, 8, 8, big))
+    with pytest.raises(nq.NQError) as e:
+        nq.count_resumable(12, path, chunks=8, depth=4)
+    assert e.value.status == nq._native.NQ_ERANGE
+    assert nq.count_resumable(12, path, chunks=8, depth=4, wide=True) == (big, 8, True)
+    fresh = str(tmp_path / "none")
+    for n, depth in ((32, 12), (0, 3), (30, 9), (31, 10), (29, 8)):
+        with pytest.raises(nq.NQError):
+            nq.count_resumable(n, fresh, chunks=8, depth=depth, wide=True)
+    assert not os.path.exists(fresh)
+
+
+def test_wide_boards_validate_before_touching_the_gpu():
+    """Boards beyond 28: nq_count refuses them (its total is 64 bits) and so does
+    nq_count_subproblems without a 128-bit total or with more than 20 rows
+    below the prefixes; nq_expand accepts up to 31."""
+    lib = nq.lib()
+    out = ct.c_uint64()
+    o = nq._native._opts(10, "persistent", 0, 0, 0, None, 0, 0)
+    fake = ct.c_void_p(16)                    # never dereferenced: refused first
+    assert lib.nq_count(29, ct.byref(o), ct.byref(out)) == -1
+    assert lib.nq_count_subproblems(30, fake, fake, fake, None, 1, None, fake, ct.byref(o)) == -1
+    o.flags = nq._native.FLAG_WIDE_TOTAL
+    o.depth = 9
+    assert lib.nq_count_subproblems(30, fake, fake, fake, None, 1, None, fake, ct.byref(o)) == -1
+    assert lib.nq_count_subproblems(32, fake, fake, fake, None, 1, None, fake, ct.byref(o)) == -1
+    o.depth = 10
+    assert lib.nq_count_subproblems(30, fake, fake, fake, None, 0, None, fake, ct.byref(o)) == 0
+    assert lib.nq_count(12, ct.byref(o), ct.byref(out)) == -1    # no device total to widen
+    o.flags = nq._native.FLAG_KINGS                            # kings(22) > 2^64
+    assert lib.nq_count(22, ct.byref(o), ct.byref(out)) == -1
+    assert lib.nq_expand(32, 1, None, None, None, None, 0, None, None, None, None, 0,
+                         ct.byref(out), None) == -1

@@ -1,9 +1,10 @@
 """GPU parity of every inner-loop form of the DFS kernel (nq_set_loop_form):
-the compiler-scheduled step (0), the negated-untried-set form (2), the paper's
-loop with the frame read from the LDS stack at every step (4) and the step
-without the last-row shortcut (5) give the oracle's counts and node counts, in
-plain and persistent launches, batches and the serving loop.  Form 1 (the
-default) is what every other GPU test runs."""
+the compiler-scheduled step (0), the hand-placed exec masks (1), the
+negated-untried-set form (2), the step without selects (3), the paper's loop
+with the frame read from the LDS stack at every step (4) and the step without
+the last-row shortcut (5) give the oracle's counts and node counts, in plain
+and persistent launches, batches and the serving loop, with the row counter
+(form 3: the rd marker) and with the popcount leaf test."""
 import hashlib
 
 import numpy as np
@@ -16,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-FORMS = [0, 2, 4, 5]
+FORMS = [0, 1, 2, 3, 4, 5]
 
 
 def _say(*a):
@@ -33,7 +34,7 @@ def nq_form(request):
         yield nq, request.param
     finally:
         nq.set_loop_form(-1)
-        assert prev in (0, 1, 2, 4, 5)
+        assert prev in FORMS
 
 
 def _golden_runs():
@@ -106,3 +107,24 @@ def test_batch_and_serving(nq_form, known_counts):
         pre, w = oracle.frontier(16, 5)
         ref, _ = oracle.count_prefixes(16, pre[100:400], threads=8)
         assert r["count"] == int((ref * w[100:400].astype(np.uint64)).sum())
+
+
+def test_shallow_promise_uses_popcount_leaf_test(nq_form):
+    """Entries of the N=18 depth-6 frontier counted under a promise of only 2
+    queens placed: the launch sizes its stack for 14 frames, and form 3 cannot
+    use its rd marker for such entries (n + frames > 30), so its popcount leaf
+    test runs; counts and node counts equal the oracle's per entry."""
+    nq, form = nq_form
+    n, k = 18, 6
+    pre_all, _ = oracle.frontier(n, k)
+    rng = np.random.default_rng(1806)
+    pre = pre_all[np.sort(rng.choice(len(pre_all), 400, replace=False))]
+    c, l, r = (_dev(x) for x in oracle.prefixes_masks(n, pre))
+    ref, ref_nodes = oracle.count_prefixes(n, pre, threads=8)
+    nodes = torch.empty(len(pre), dtype=torch.int64, device="cuda")
+    for mode in ("persistent", "plain"):
+        _say("form", form, "shallow promise", n, mode)
+        counts, _ = nq.count_subproblems(n, c, l, r, depth=2, mode=mode, nodes=nodes)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(counts.cpu().numpy().view(np.uint64), ref)
+        np.testing.assert_array_equal(nodes.cpu().numpy().view(np.uint64), ref_nodes)

@@ -96,12 +96,16 @@ def test_node_counts_and_dead_entries():
             np.testing.assert_array_equal(counts.cpu().numpy().view(np.uint64), ref)
 
 
-def test_kings_flag_outside_the_default_form_is_refused():
+def test_kings_runs_its_own_form_whatever_form_is_selected():
+    """The kings search has one inner-loop form (form 1's step with the
+    kings' attacks); selecting another form for the queens leaves it exact."""
     nq = _nq()
-    prev = nq.set_loop_form(0)
-    try:
-        with pytest.raises(nq.NQError):
-            nq.count(10, depth=3, kings=True)
-    finally:
-        nq.set_loop_form(-1)
-    assert prev in (0, 1, 2, 4, 5)
+    want = _kings_counts(10)[10]
+    for form in (0, 2, 3, 4, 5):
+        prev = nq.set_loop_form(form)
+        try:
+            _say("kings under form", form)
+            assert nq.count(10, depth=3, kings=True) == want
+        finally:
+            nq.set_loop_form(-1)
+        assert prev in (0, 1, 2, 3, 4, 5)

@@ -87,3 +87,83 @@ def test_n20_in_four_chunks(tmp_path, known_counts):
     assert (done, fin) == (2, False)
     _say("n20 the other two")
     assert nq.count_resumable(20, path, chunks=4, depth=9) == (known_counts[20], 4, True)
+
+
+def test_wide_total_carries_into_the_high_word(known_counts):
+    """NQ_FLAG_WIDE_TOTAL: the device total is 128 bits and is increased with
+    carry.  Started just below 2^64, an N = 12 count (14,200) must carry into
+    the high word, which keeps what it held."""
+    nq = _nq()
+    n, k = 12, 4
+    cols, ld, rd, w = nq.frontier(n, k)
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(x.view(np.int32)).to(dev) for x in (cols, ld, rd)]
+    tw = torch.from_numpy(w).to(dev)
+    start_lo = 2**64 - 100
+    total = torch.tensor([start_lo - 2**64, 7], dtype=torch.int64, device=dev)
+    _say("wide total N=12 persistent")
+    nq.count_subproblems(n, *t, weight=tw, counts=False, total=total, depth=k, wide=True)
+    lo, hi = (int(x) & (2**64 - 1) for x in total.cpu())
+    assert (hi << 64) + lo == (7 << 64) + start_lo + known_counts[n]
+    total = torch.tensor([-1, 0], dtype=torch.int64, device=dev)            # 2^64 - 1
+    _say("wide total N=12 plain")
+    nq.count_subproblems(n, *t, weight=tw, counts=False, total=total, depth=k, wide=True,
+                         mode="plain")
+    lo, hi = (int(x) & (2**64 - 1) for x in total.cpu())
+    assert (hi << 64) + lo == 2**64 - 1 + known_counts[n]
+
+
+def test_wide_resumable_crosses_two_to_the_64(tmp_path, known_counts):
+    """A record whose total is just below 2^64 with one chunk left: the last
+    chunk takes the 128-bit total across 2^64 in the record and the result;
+    the 64-bit entry point reports NQ_ERANGE for the same file.  A board of at
+    most 16 through the wide entry gives the published count."""
+    nq = _nq()
+    n, depth, chunks = 13, 6, 4
+    pre, w = oracle.frontier(n, 5)
+    ref, _ = oracle.count_prefixes(n, pre, threads=8)
+    wref = (ref * w.astype(np.uint64)).astype(object)
+    F = len(pre)
+    last = int(sum(wref[F * 3 // chunks:]))
+    assert last > 0
+    base = 2**64 - last // 2
+    path = str(tmp_path / "carry")
+    body = (f"nq-progress 1 n={n} depth={depth} host_depth=5 chunks={chunks} done=3 "
+            f"total={base}")
+    h = 0xcbf29ce484222325
+    for ch in body.encode():
+        h = ((h ^ ch) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    with open(path, "w") as f:
+        f.write(f"{body} check={h:016x}\n")
+    _say("wide resumable across 2^64")
+    assert nq.count_resumable(n, path, chunks=chunks, depth=depth, wide=True) == \
+        (base + last, chunks, True)
+    assert int(_fields(path)["total"]) == base + last > 2**64
+    with pytest.raises(nq.NQError) as e:
+        nq.count_resumable(n, path, chunks=chunks, depth=depth)
+    assert e.value.status == nq._native.NQ_ERANGE
+    _say("wide resumable N=16")
+    assert nq.count_resumable(16, str(tmp_path / "n16"), chunks=8, depth=8, wide=True) == \
+        (known_counts[16], 8, True)
+
+
+def test_automatic_depth_ignores_the_tuner(tmp_path, known_counts):
+    """With depth 0 the resumable count picks its depth without this process's
+    tuning results, and a record of the same count supplies its own depth, so
+    a tuned process and a fresh one continue the same file."""
+    nq = _nq()
+    n = 15
+    path = str(tmp_path / "n15")
+    _say("n15 resumable, depth 0, first half")
+    total, done, fin = nq.count_resumable(n, path, chunks=4, max_chunks=2)
+    assert (done, fin) == (2, False)
+    depth0 = int(_fields(path)["depth"])
+    _say("n15 autotune over other depths")
+    nq.autotune(n, depth0 + 1, depth0 + 2, budget_ms=2000)      # the tuner remembers another depth
+    _say("n15 resumable, depth 0, after tuning")
+    assert nq.count_resumable(n, path, chunks=4) == (known_counts[n], 4, True)
+    assert int(_fields(path)["depth"]) == depth0
+    fresh = str(tmp_path / "n15b")
+    _say("n15 resumable, depth 0, new file after tuning")
+    nq.count_resumable(n, fresh, chunks=4, max_chunks=1)
+    assert int(_fields(fresh)["depth"]) == depth0
