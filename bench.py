@@ -11,8 +11,10 @@ value = DFS nodes per second = nodes(20, k) / step time, where nodes(20, k) is
 the oracle's node count (queens placed in rows k..18 below every pre-placed
 prefix), read from tests/golden/oracle_runs.txt.
 
-The pre-placement depth and launch shape come from nq_autotune (depths 6..10)
-unless --depth is given.  Frontiers deeper than 8 rows are built on the host at
+The pre-placement depth and launch shape come from nq_autotune over depths
+5..10 (the workload's stated depths 5..8 and the two beyond them, which win on
+this GPU) unless --depth is given; every trial is reported, with the best
+within 5..8 beside the overall best.  Frontiers deeper than 8 rows are built on the host at
 depth k-2 and expanded on the device (nq_expand) before the timed region.  Printed: one JSON line with the metric, the "plain"
 form (one launch per row-0 column over the same frontier), the end-to-end
 nq_count wall time, the int-ALU roofline of the DFS kernel, the ragged
@@ -378,6 +380,74 @@ def profile_run(nq, torch, k, args):
           file=sys.stderr, flush=True)
 
 
+UB_OPS = {0: "v_add3_u32", 1: "v_bitop3_b32", 2: "v_cndmask_b32 (SGPR mask)",
+          3: "v_addc_co_u32 (SGPR carry-in)", 4: "v_add_lshl_u32", 5: "v_xad_u32",
+          6: "v_and_b32", 7: "v_xor_b32", 8: "v_or3_b32", 9: "v_sub_u32", 10: "v_lshrrev_b32",
+          11: "v_add_u32"}
+UB_LDS_OPS = {0: ("write b128 + read b128", 2), 1: ("read b128", 1), 2: ("write b128", 1),
+              3: ("exchange 16 B (wrxchg2_rtn_b64)", 1), 4: ("write b64 + read b64", 2),
+              5: ("write b32 + read b32", 2)}
+
+
+def run_ubench(nq, args):
+    """The microbenchmarks behind the roofline (include/nq_ubench.h): the int32
+    VALU rate of the DFS step's operations with eight independent chains per
+    lane at 1..8 waves per SIMD (and one chain, one wave: the dependent
+    latency), the shader clock during those runs (s_memtime cycles over event
+    time), and the LDS stack accesses in the interleaved and contiguous
+    layouts at several occupancies and active-lane counts."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {"valu": [], "lds": [], "cus": cus}
+
+    def valu(op, chains, wps, iters):
+        ms, cyc = nq.ubench_valu(op, chains, wps, iters)
+        lane_ops = cus * 4 * wps * 64 * chains * iters
+        row = {"op": UB_OPS[op], "chains": chains, "waves_per_simd": wps, "iters": iters,
+               "kernel_ms": ms, "lane_ops_per_s": lane_ops / (ms / 1e3),
+               "frac_of_peak": lane_ops / (ms / 1e3) / INT_PEAK,
+               "clock_ghz": cyc / (ms * 1e6),
+               "cycles_per_instr_per_wave": cyc / (chains * iters)}
+        out["valu"].append(row)
+        print(f"[bench] ubench valu {json.dumps(row)}", file=sys.stderr, flush=True)
+        return row
+
+    for op in range(len(UB_OPS)):
+        valu(op, 8, 1, 1 << 16)                              # warm the code object
+        for wps in (1, 2, 4, 8):
+            valu(op, 8, wps, 1 << 19)
+        valu(op, 1, 1, 1 << 19)
+
+    def lds(layout, op, wpc, active):
+        iters = 1 << 16
+        nq.ubench_lds(layout, active, wpc, 10, 1 << 10, op=op)      # warm the code object
+        ms = nq.ubench_lds(layout, active, wpc, 10, iters, op=op)
+        name, per_iter = UB_LDS_OPS[op]
+        instr = cus * wpc * iters * per_iter
+        row = {"layout": "interleaved" if layout == 0 else "contiguous", "op": name,
+               "waves_per_cu": wpc, "active_lanes": active, "frames": 10, "iters": iters,
+               "kernel_ms": ms, "lds_instr_per_cu_per_s": instr / cus / (ms / 1e3),
+               "cycles_per_instr_per_cu_at_2_4GHz": 2.4e9 / (instr / cus / (ms / 1e3))}
+        out["lds"].append(row)
+        print(f"[bench] ubench lds {json.dumps(row)}", file=sys.stderr, flush=True)
+
+    for layout in (0, 1):
+        for wpc in (4, 8, 16):
+            for active in (64, 32, 16):
+                lds(layout, 0, wpc, active)
+    for op in (1, 2, 3, 4, 5):
+        for wpc in (8, 16):
+            for active in (64, 16):
+                lds(0, op, wpc, active)
+    clocks = [r["clock_ghz"] for r in out["valu"] if r["waves_per_simd"] == 8]
+    out["clock_ghz_under_load"] = float(np.median(clocks)) if clocks else None
+    best = max(r["lane_ops_per_s"] for r in out["valu"])
+    out["best_lane_ops_per_s"] = best
+    out["peak_at_measured_clock"] = (cus * 4 * 16 * out["clock_ghz_under_load"] * 1e9
+                                     if out["clock_ghz_under_load"] else None)
+    return out
+
+
 def run_ablation(nq, torch):
     """The paper's design choices measured on this GPU (N=20, one launch over the
     resident frontier, kernel time from HIP events; every run checked against
@@ -463,7 +533,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--depth", type=int, default=0, help="0 = autotune over 6..10")
+    ap.add_argument("--depth", type=int, default=0, help="0 = autotune over 5..10")
     ap.add_argument("--tune-ms", type=float, default=40000.0)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--serve-rates", default="25,100,200", help="COUNT requests/s, comma list")
@@ -480,6 +550,12 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="measure the paper's design choices (depth, plain block size, loop "
                          "forms) at N=20 and print them as one JSON line instead")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the serving loop at --serve-rates (one JSON line)")
+    ap.add_argument("--ubench", action="store_true",
+                    help="the VALU and LDS microbenchmarks behind the roofline, as one JSON line")
+    ap.add_argument("--ubench-counters", action="store_true",
+                    help="one launch of each LDS layout and one VALU launch, for counter passes")
     ap.add_argument("--profile", action="store_true",
                     help="counter runs: one 256 MiB device copy (calibrates the HBM byte "
                          "counters), then one persistent DFS launch at --depth; no JSON line")
@@ -499,15 +575,41 @@ def main():
     if args.ablation:
         print(json.dumps({"ablation": run_ablation(nq, torch)}), flush=True)
         return
+    if args.ubench:
+        print(json.dumps({"ubench": run_ubench(nq, args)}), flush=True)
+        return
+    if args.serving_only:
+        rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
+        print(json.dumps({"serving": bench_serving(nq, torch, known_counts(), rates,
+                                                   args.serve_seconds)}), flush=True)
+        return
+    if args.ubench_counters:
+        for layout in (0, 1):
+            ms = nq.ubench_lds(layout, 64, 16, 10, 1 << 14)
+            print(f"[bench] ubench lds layout {layout}: {ms:.2f} ms", file=sys.stderr, flush=True)
+        ms = nq.ubench_lds(0, 64, 16, 10, 1 << 14, op=3)
+        print(f"[bench] ubench lds exchange: {ms:.2f} ms", file=sys.stderr, flush=True)
+        ms, cyc = nq.ubench_valu(0, 8, 8, 1 << 16)
+        print(f"[bench] ubench valu v_add3 8 waves/SIMD: {ms:.2f} ms", file=sys.stderr, flush=True)
+        return
 
     tuned = None
     if args.depth == 0:
-        print("[bench] autotune N=20 over depths 6..10", file=sys.stderr, flush=True)
-        tuned = nq.autotune(N, 6, 10, budget_ms=args.tune_ms)
-        print(f"[bench] tuned {tuned}", file=sys.stderr, flush=True)
+        print("[bench] autotune N=20 over depths 5..10", file=sys.stderr, flush=True)
+        tuned = nq.autotune(N, 5, 10, budget_ms=args.tune_ms, table=True)
+        print(f"[bench] tuned { {k: v for k, v in tuned.items() if k != 'table'} }",
+              file=sys.stderr, flush=True)
         if tuned["count"] != EXPECT:
             raise SystemExit(f"bench.py: autotune count {tuned['count']} != {EXPECT}")
+        stated = [r for r in tuned["table"] if 5 <= r["depth"] <= 8]
+        if stated:
+            b = min(stated, key=lambda r: r["ms"])
+            nodes_b = golden_nodes(N, b["depth"])
+            tuned["best_within_stated_depths_5_8"] = dict(
+                b, nodes_per_s=(nodes_b / (b["ms"] / 1e3)) if nodes_b else None)
         k = tuned["depth"]
+        if not args.wg:
+            args.wg = tuned["wg_size"]
         if not args.waves_per_cu:
             args.waves_per_cu = tuned["waves_per_cu"]
         if not args.refill:
@@ -600,7 +702,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": f"N-Queens N={N} full count, pre-placement depth {k}"
-                               f"{' (autotuned over 6..10)' if tuned else ''}, {F} subproblems "
+                               f"{' (autotuned over 5..10)' if tuned else ''}, {F} subproblems "
                                "resident in HBM, one persistent launch",
                    "n": N, "depth": k, "subproblems": F, "solutions": EXPECT,
                    "nodes": nodes, "nodes_source": src},

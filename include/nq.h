@@ -305,14 +305,17 @@ int nq_count_resumable_wide(uint32_t n, const nq_opts* opts, const char* path, u
  * nq_autotune -- measure the best pre-placement depth and launch shape for n.
  *
  * Times complete persistent counts of n on the current device: every depth in
- * [depth_lo, depth_hi] (0, 0 = max(1, n - 14) .. +4) with the default launch
- * shape, then, at the best depth, a few resident-wave counts per CU,
- * scheduler-visit intervals and claim block sizes, until budget_ms of device
- * time is spent (0 = 60 s).
- * The paper tunes the same choices by hand (Section 4.1 Table 3, Section 4.2
- * Table 4).  Every trial must produce the same count (else NQ_EDEVICE).  The
- * winner is written to *out and remembered for this process and device:
- * nq_count with opts->depth == 0 then uses it.  n in [4, 28].
+ * [depth_lo, depth_hi] (0, 0 = max(1, n - 14) .. +4) twice with the default
+ * launch shape, then, at the best depth, workgroup sizes of 64, 128 and 256
+ * threads, a few resident-wave counts per CU, scheduler-visit intervals and
+ * claim block sizes (entries a wave takes from the shared work head per
+ * atomic: the persistent scheduler's queue depth), each axis starting from the
+ * best so far, until budget_ms of device time is spent (0 = 60 s).
+ * The paper tunes the pre-placed rows and the block and stack size by hand
+ * (Section 4.1 Table 3, Section 4.2 Table 4).  Every trial must produce the
+ * same count (else NQ_EDEVICE).  The winner is written to *out and remembered
+ * for this process and device: nq_count with opts->depth == 0 then uses its
+ * depth and every launch field the caller left at 0.  n in [4, 28].
  */
 typedef struct nq_tuned {
     uint32_t depth;          /* pre-placed rows                                  */
@@ -322,9 +325,33 @@ typedef struct nq_tuned {
     double ms;               /* best device time of one count                    */
     uint64_t count;          /* the count every trial agreed on                  */
     uint32_t claim;          /* entries per work-head claim (0 = size default)   */
+    uint32_t wg_size;        /* threads per workgroup (0 = the default, 64)      */
 } nq_tuned;
 int nq_autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
                 nq_tuned* out);
+
+/*
+ * nq_autotune_trials -- nq_autotune that also reports every trial: trials[i]
+ * (caller-owned, `capacity` entries) receives the i-th timed count's depth,
+ * launch shape (0 = that field's default), subproblems and device time, in
+ * the order they ran; *out_count = the trials written (at most capacity; the
+ * search itself is not shortened).  NQ_EINVAL if trials or out_count is NULL.
+ */
+typedef struct nq_tune_trial {
+    uint32_t depth, wg_size, waves_per_cu, refill_every, claim, reserved;
+    double ms;
+    uint64_t subproblems;
+} nq_tune_trial;
+int nq_autotune_trials(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
+                       nq_tuned* out, nq_tune_trial* trials, uint32_t capacity,
+                       uint32_t* out_count);
+
+/*
+ * nq_tuned_lookup -- the tuning nq_autotune remembered for n on the current
+ * device in this process (what nq_count's automatic depth and launch shape
+ * use).  NQ_ENOENT when n has not been tuned; n in [1, 28].
+ */
+int nq_tuned_lookup(uint32_t n, nq_tuned* out);
 
 /*
  * nq_set_loop_form -- choose the DFS inner-loop form of the launches planned

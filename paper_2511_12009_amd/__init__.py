@@ -15,8 +15,11 @@ Functions (same names as the C entry points, without the ``nq_`` prefix):
   count_subproblems(n, cols, ld, rd, ...)    -> per-entry counts and weighted total
   count_batch(ns, depths=None, ...)          -> [Q(n) for n in ns]
   Batch(ns, depths=None).run()               -> replayable batch plan (HIP graph)
-  autotune(n, depth_lo=0, depth_hi=0)        -> measured best depth and launch shape
+  autotune(n, depth_lo=0, depth_hi=0, table=False) -> measured best depth and launch shape
+  tuned_lookup(n)                            -> the tuning nq_count uses for n, or None
   Server(...).submit_count / submit_slice / poll / wait -> continuous-batching serving
+  count_resumable(n, path, ..., wide=False)  -> a count in chunks with a progress file
+  ubench_valu / ubench_lds                   -> the microbenchmarks behind the roofline
 """
 from ._native import (  # noqa: F401
     Batch,
@@ -33,6 +36,9 @@ from ._native import (  # noqa: F401
     frontier_runs,
     frontier_size,
     set_loop_form,
+    tuned_lookup,
     lib,
     library_path,
+    ubench_lds,
+    ubench_valu,
 )

@@ -49,6 +49,20 @@ class NqTuned(ct.Structure):
         ("ms", ct.c_double),
         ("count", ct.c_uint64),
         ("claim", ct.c_uint32),
+        ("wg_size", ct.c_uint32),
+    ]
+
+
+class NqTuneTrial(ct.Structure):
+    _fields_ = [
+        ("depth", ct.c_uint32),
+        ("wg_size", ct.c_uint32),
+        ("waves_per_cu", ct.c_uint32),
+        ("refill_every", ct.c_uint32),
+        ("claim", ct.c_uint32),
+        ("reserved", ct.c_uint32),
+        ("ms", ct.c_double),
+        ("subproblems", ct.c_uint64),
     ]
 
 
@@ -120,6 +134,11 @@ def lib():
         L.nq_serve_destroy.restype = ct.c_int
         L.nq_autotune.argtypes = [u32, u32, u32, ct.c_double, ct.POINTER(NqTuned)]
         L.nq_autotune.restype = ct.c_int
+        L.nq_autotune_trials.argtypes = [u32, u32, u32, ct.c_double, ct.POINTER(NqTuned),
+                                         ct.POINTER(NqTuneTrial), u32, pu32]
+        L.nq_autotune_trials.restype = ct.c_int
+        L.nq_tuned_lookup.argtypes = [u32, ct.POINTER(NqTuned)]
+        L.nq_tuned_lookup.restype = ct.c_int
         L.nq_batch_create.argtypes = [u32, pu32, pu32, ct.POINTER(NqOpts), ct.POINTER(vp)]
         L.nq_batch_create.restype = ct.c_int
         L.nq_batch_run.argtypes = [vp, pu64, ct.POINTER(ct.c_double)]
@@ -135,6 +154,11 @@ def lib():
         L.nq_count_resumable_wide.restype = ct.c_int
         L.nq_set_loop_form.argtypes = [ct.c_int, ct.POINTER(ct.c_int)]
         L.nq_set_loop_form.restype = ct.c_int
+        pd = ct.POINTER(ct.c_double)
+        L.nq_ubench_valu.argtypes = [u32, u32, u32, u64, pd, pd]
+        L.nq_ubench_valu.restype = ct.c_int
+        L.nq_ubench_lds.argtypes = [u32, u32, u32, u32, u32, u64, pd]
+        L.nq_ubench_lds.restype = ct.c_int
         _LIB = L
     return _LIB
 
@@ -335,6 +359,23 @@ def set_loop_form(form: int) -> int:
     return prev.value
 
 
+def ubench_valu(op: int, chains: int, waves_per_simd: int, iters: int):
+    """nq_ubench_valu: (kernel ms, mean shader-clock cycles of a wave's loop)."""
+    ms, cyc = ct.c_double(), ct.c_double()
+    _check(lib().nq_ubench_valu(op, chains, waves_per_simd, iters, ct.byref(ms), ct.byref(cyc)),
+           "nq_ubench_valu")
+    return ms.value, cyc.value
+
+
+def ubench_lds(layout: int, active_lanes: int, waves_per_cu: int, frames: int, iters: int,
+               op: int = 0):
+    """nq_ubench_lds: kernel ms."""
+    ms = ct.c_double()
+    _check(lib().nq_ubench_lds(layout, op, active_lanes, waves_per_cu, frames, iters,
+                               ct.byref(ms)), "nq_ubench_lds")
+    return ms.value
+
+
 def count_batch(ns, depths=None, mode="persistent", wg_size: int = 0, waves_per_cu: int = 0,
                 refill_every: int = 0, stream=None, claim: int = 0):
     """[Q(n) for n in ns], all instances in one persistent launch."""
@@ -394,13 +435,41 @@ class Batch:
             pass
 
 
-def autotune(n: int, depth_lo: int = 0, depth_hi: int = 0, budget_ms: float = 0.0) -> dict:
-    """Measured best depth / waves per CU / visit interval / claim block for n
-    (nq_autotune)."""
+def _tuned(t) -> dict:
+    return {"depth": t.depth, "wg_size": t.wg_size, "waves_per_cu": t.waves_per_cu,
+            "refill_every": t.refill_every, "claim": t.claim, "trials": t.trials, "ms": t.ms,
+            "count": t.count}
+
+
+def autotune(n: int, depth_lo: int = 0, depth_hi: int = 0, budget_ms: float = 0.0,
+             table: bool = False) -> dict:
+    """Measured best depth / workgroup size / waves per CU / visit interval /
+    claim block for n (nq_autotune); table=True adds every trial
+    (nq_autotune_trials) under "table"."""
     t = NqTuned()
-    _check(lib().nq_autotune(n, depth_lo, depth_hi, budget_ms, ct.byref(t)), "nq_autotune")
-    return {"depth": t.depth, "waves_per_cu": t.waves_per_cu, "refill_every": t.refill_every,
-            "claim": t.claim, "trials": t.trials, "ms": t.ms, "count": t.count}
+    if not table:
+        _check(lib().nq_autotune(n, depth_lo, depth_hi, budget_ms, ct.byref(t)), "nq_autotune")
+        return _tuned(t)
+    cap = 256
+    rows = (NqTuneTrial * cap)()
+    cnt = ct.c_uint32()
+    _check(lib().nq_autotune_trials(n, depth_lo, depth_hi, budget_ms, ct.byref(t), rows, cap,
+                                    ct.byref(cnt)), "nq_autotune_trials")
+    out = _tuned(t)
+    out["table"] = [{"depth": r.depth, "wg_size": r.wg_size, "waves_per_cu": r.waves_per_cu,
+                     "refill_every": r.refill_every, "claim": r.claim, "ms": r.ms,
+                     "subproblems": r.subproblems} for r in rows[:cnt.value]]
+    return out
+
+
+def tuned_lookup(n: int):
+    """nq_tuned_lookup: the tuning remembered for n in this process, or None."""
+    t = NqTuned()
+    rc = lib().nq_tuned_lookup(n, ct.byref(t))
+    if rc == NQ_ENOENT:
+        return None
+    _check(rc, "nq_tuned_lookup")
+    return _tuned(t)
 
 
 class Server:

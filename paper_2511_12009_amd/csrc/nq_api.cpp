@@ -488,6 +488,7 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
         nq_tuned t;
         if (tune_lookup(n, &t) == NQ_OK) {
             local.depth = t.depth;
+            if (!local.wg_size) local.wg_size = t.wg_size;
             if (!local.waves_per_cu) local.waves_per_cu = t.waves_per_cu;
             if (!local.refill_every) local.refill_every = t.refill_every;
             if (!local.claim) local.claim = t.claim;

@@ -1,14 +1,16 @@
 // Autotuner: picks the pre-placement depth and the persistent launch shape
-// (waves per CU, steps between scheduler visits) for a board size by timing
-// full counts on the device.
+// (workgroup size, waves per CU, steps between scheduler visits, entries per
+// work-head claim) for a board size by timing full counts on the device.
 //
 // The paper tunes the pre-placed rows and the block/stack configuration by
 // hand (Section 4.1, Table 3; Section 4.2, Table 4); here the same choices are
 // measured.  The search is coordinate-wise: depth first (with the default
-// launch shape), then waves per CU, the visit interval and the size of the
-// per-wave claimed blocks, each trial a
-// complete persistent count over the resident frontier, stopping early when the
-// time budget is spent.  Results are kept per (device, n) for the process.
+// launch shape), then the workgroup size, waves per CU, the visit interval and
+// the size of the per-wave claimed blocks (the persistent scheduler's
+// counterpart of a queue depth), each trial a complete persistent count over
+// the resident frontier, stopping early when the time budget is spent.  Every
+// trial is recorded for the caller.  Results are kept per (device, n) for the
+// process.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,15 +58,16 @@ struct TrialFrontier {
 };
 
 // One timed persistent count; *ms is the device time of zero + DFS.
-int trial(uint32_t n, uint32_t depth, const TrialFrontier& tf, uint32_t waves_per_cu,
-          uint32_t refill, uint32_t claim, hipStream_t s, double* ms, uint64_t* total_out) {
+int trial(uint32_t n, uint32_t depth, const TrialFrontier& tf, uint32_t wg_size,
+          uint32_t waves_per_cu, uint32_t refill, uint32_t claim, hipStream_t s, double* ms,
+          uint64_t* total_out) {
     const DeviceFrontier& fr = tf.fr;
     DeviceInfo dev;
     int rc = device_info(&dev);
     if (rc != NQ_OK) return rc;
     const uint32_t frames = std::max<uint32_t>(1, frames_needed(n, depth));
     LaunchCfg cfg;
-    rc = plan_launch(dev, NQ_MODE_PERSISTENT, 0, waves_per_cu, frames, fr.len, false,
+    rc = plan_launch(dev, NQ_MODE_PERSISTENT, wg_size, waves_per_cu, frames, fr.len, false,
                      leafctr_ok(n, depth), &cfg, false, false, n);
     if (rc != NQ_OK) return rc;
     DfsParams P{};
@@ -113,8 +116,9 @@ int tune_lookup(uint32_t n, nq_tuned* out) {
     return NQ_OK;
 }
 
-int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms, nq_tuned* out) {
-    if (n < 4 || n > NQ_MAX_N || !out) return NQ_EINVAL;
+int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms, nq_tuned* out,
+             nq_tune_trial* table, uint32_t capacity, uint32_t* out_count) {
+    if (n < 4 || n > NQ_MAX_N || !out || (table && !capacity)) return NQ_EINVAL;
     if (depth_lo == 0) depth_lo = std::max<uint32_t>(1, std::min<uint32_t>(n - 2, n > 12 ? n - 14 : 1));
     if (depth_hi == 0) depth_hi = std::min<uint32_t>(n - 2, depth_lo + 4);
     if (depth_lo > depth_hi || depth_hi > n) return NQ_EINVAL;
@@ -132,22 +136,24 @@ int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
     double spent = 0.0;
     uint64_t expect = 0;
     bool have_expect = false;
-    int trials = 0;
-    auto consider = [&](uint32_t depth, const TrialFrontier& fr, uint32_t wpc, uint32_t rf,
-                        uint32_t claim, bool* better) -> int {
+    uint32_t trials = 0;
+    auto consider = [&](uint32_t depth, const TrialFrontier& fr, uint32_t wg, uint32_t wpc,
+                        uint32_t rf, uint32_t claim) -> int {
         double ms = 0;
         uint64_t total = 0;
-        int rc = trial(n, depth, fr, wpc, rf, claim, s, &ms, &total);
+        int rc = trial(n, depth, fr, wg, wpc, rf, claim, s, &ms, &total);
+        if (rc == NQ_EINVAL && wg != 0) return NQ_OK;   // this workgroup size does not fit
         if (rc != NQ_OK) return rc;
+        if (table && trials < capacity)
+            table[trials] = nq_tune_trial{depth, wg, wpc, rf, claim, 0u, ms, fr.fr.len};
         ++trials;
         spent += ms;
         if (have_expect && total != expect) return NQ_EDEVICE;   // counts must agree
         expect = total;
         have_expect = true;
-        *better = ms < best.ms;
-        if (*better) {
-            best.depth = depth; best.waves_per_cu = wpc; best.refill_every = rf;
-            best.claim = claim; best.ms = ms;
+        if (ms < best.ms) {
+            best.depth = depth; best.wg_size = wg; best.waves_per_cu = wpc;
+            best.refill_every = rf; best.claim = claim; best.ms = ms;
         }
         return NQ_OK;
     };
@@ -159,37 +165,41 @@ int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
             TrialFrontier fr;
             int rc = fr.load(n, d, s);
             if (rc != NQ_OK) return rc;
-            bool b = false;
             for (int rep = 0; rep < 2 && spent < budget_ms; ++rep)
-                if ((rc = consider(d, fr, 0, 512, 0, &b)) != NQ_OK) return rc;
+                if ((rc = consider(d, fr, 0, 0, 512, 0)) != NQ_OK) return rc;
         }
-        // 2. waves per CU, the visit interval and the claim block at the best
-        //    depth (claim 0 = the size-derived default).
+        // 2. workgroup size, waves per CU, the visit interval and the claim
+        //    block at the best depth (0 = the default of each).
         TrialFrontier fr;
         int rc = fr.load(n, best.depth, s);
         if (rc != NQ_OK) return rc;
         const uint32_t d = best.depth;
+        for (uint32_t wg : {64u, 128u, 256u}) {
+            if (spent >= budget_ms) break;
+            if ((rc = consider(d, fr, wg, 0, best.refill_every, best.claim)) != NQ_OK) return rc;
+        }
         for (uint32_t wpc : {8u, 16u, 24u}) {
             if (spent >= budget_ms) break;
-            bool b = false;
-            if ((rc = consider(d, fr, wpc, best.refill_every, best.claim, &b)) != NQ_OK) return rc;
+            if ((rc = consider(d, fr, best.wg_size, wpc, best.refill_every, best.claim)) != NQ_OK)
+                return rc;
         }
         for (uint32_t rf : {128u, 2048u}) {
             if (spent >= budget_ms) break;
-            bool b = false;
-            if ((rc = consider(d, fr, best.waves_per_cu, rf, best.claim, &b)) != NQ_OK) return rc;
+            if ((rc = consider(d, fr, best.wg_size, best.waves_per_cu, rf, best.claim)) != NQ_OK)
+                return rc;
         }
         for (uint32_t cl : {32u, 1024u}) {
             if (spent >= budget_ms) break;
-            bool b = false;
-            if ((rc = consider(d, fr, best.waves_per_cu, best.refill_every, cl, &b)) != NQ_OK)
+            if ((rc = consider(d, fr, best.wg_size, best.waves_per_cu, best.refill_every, cl)) !=
+                NQ_OK)
                 return rc;
         }
     } catch (const std::bad_alloc&) {
         return NQ_ENOMEM;
     }
-    best.trials = (uint32_t)trials;
+    best.trials = trials;
     best.count = expect;
+    if (out_count) *out_count = std::min(trials, table ? capacity : 0u);
     int dev = 0;
     (void)hipGetDevice(&dev);
     {
@@ -205,7 +215,27 @@ int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
 extern "C" int nq_autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
                            nq_tuned* out) {
     try {
-        return nqi::autotune(n, depth_lo, depth_hi, budget_ms, out);
+        return nqi::autotune(n, depth_lo, depth_hi, budget_ms, out, nullptr, 0, nullptr);
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
+}
+
+extern "C" int nq_autotune_trials(uint32_t n, uint32_t depth_lo, uint32_t depth_hi,
+                                  double budget_ms, nq_tuned* out, nq_tune_trial* trials,
+                                  uint32_t capacity, uint32_t* out_count) {
+    if (!trials || !out_count) return NQ_EINVAL;
+    try {
+        return nqi::autotune(n, depth_lo, depth_hi, budget_ms, out, trials, capacity, out_count);
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
+}
+
+extern "C" int nq_tuned_lookup(uint32_t n, nq_tuned* out) {
+    if (n < 1 || n > NQ_MAX_N || !out) return NQ_EINVAL;
+    try {
+        return nqi::tune_lookup(n, out);
     } catch (...) {
         return NQ_ENOMEM;
     }

@@ -12,28 +12,38 @@ import paper_2511_12009_amd as nq
 from conftest import ROOT, read_table
 
 
-def _declared_functions():
-    with open(os.path.join(ROOT, "include", "nq.h")) as f:
-        text = f.read()
+HEADERS = ("nq.h", "nq_ubench.h")
+
+
+def _header_text(name):
+    with open(os.path.join(ROOT, "include", name)) as f:
+        return f.read()
+
+
+def _declared_functions(name="nq.h"):
+    text = _header_text(name)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(nq_[a-z_0-9]+)\s*\(",
                                  text, flags=re.M)))
 
 
-def test_library_exports_every_declared_symbol():
-    names = _declared_functions()
-    assert "nq_frontier" in names and "nq_count" in names and len(names) >= 6
+@pytest.mark.parametrize("header", HEADERS)
+def test_library_exports_every_declared_symbol(header):
+    names = _declared_functions(header)
+    assert len(names) >= 2
+    if header == "nq.h":
+        assert "nq_frontier" in names and "nq_count" in names and len(names) >= 6
     lib = ct.CDLL(nq.library_path)
     for name in names:
         assert hasattr(lib, name), name
 
 
-def test_every_declared_function_is_documented():
-    """Each entry point of the C-ABI header carries its own documentation: its
+@pytest.mark.parametrize("header", HEADERS)
+def test_every_declared_function_is_documented(header):
+    """Each entry point of a C-ABI header carries its own documentation: its
     name appears in a comment, or a comment ends right above its declaration."""
-    with open(os.path.join(ROOT, "include", "nq.h")) as f:
-        text = f.read()
+    text = _header_text(header)
     comments = " ".join(re.findall(r"/\*.*?\*/", text, flags=re.S))
-    for name in _declared_functions():
+    for name in _declared_functions(header):
         if name in comments:
             continue
         decl = re.search(r"^[^\n]*\b" + name + r"\s*\(", text, flags=re.M)
@@ -336,3 +346,19 @@ def test_wide_boards_validate_before_touching_the_gpu():
     assert lib.nq_count(22, ct.byref(o), ct.byref(out)) == -1
     assert lib.nq_expand(32, 1, None, None, None, None, 0, None, None, None, None, 0,
                          ct.byref(out), None) == -1
+
+
+def test_ubench_arguments_are_checked_before_any_device_work():
+    """The microbenchmark entry points refuse arguments outside their stated
+    ranges before touching a device."""
+    L = nq.lib()
+    d1, d2 = ct.c_double(), ct.c_double()
+    for op, chains, wps, iters in ((12, 8, 1, 8), (0, 2, 1, 8), (0, 8, 0, 8), (0, 8, 9, 8),
+                                   (0, 8, 1, 0), (0, 8, 1, 12)):
+        assert L.nq_ubench_valu(op, chains, wps, iters, ct.byref(d1), ct.byref(d2)) == -1
+    assert L.nq_ubench_valu(0, 8, 1, 8, None, ct.byref(d2)) == -1
+    for layout, op, active, wpc, frames in ((2, 0, 64, 4, 10), (0, 6, 64, 4, 10),
+                                            (0, 0, 0, 4, 10), (0, 0, 65, 4, 10),
+                                            (0, 0, 64, 0, 10), (0, 0, 64, 33, 10),
+                                            (0, 0, 64, 4, 1), (0, 0, 64, 4, 33)):
+        assert L.nq_ubench_lds(layout, op, active, wpc, frames, 16, ct.byref(d1)) == -1

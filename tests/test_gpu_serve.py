@@ -134,3 +134,42 @@ def test_requests_beyond_a_small_budget_fail_alone(known_counts):
         for n, t in zip((8, 10, 11, 9, 12), small + more):
             r = srv.wait(t, timeout_s=60)
             assert r["status"] == 0 and r["count"] == known_counts[n], n
+
+
+def test_n21_seeded_slices_match_the_oracle():
+    """Seeded N=21 depth-6 slices (and the last, short one), against the
+    oracle's stored counts of the same slices (tests/golden/oracle_slices.txt,
+    make_golden.py --slices): each slice's weighted sum from the server, and
+    every entry's count from one direct launch over the slices' entries
+    (no expansion), element by element through the digest of the counts."""
+    import hashlib
+    from conftest import read_table
+    nq = _nq()
+    rows = [r for r in read_table("oracle_slices.txt") if r[:2] == ["21", "6"]]
+    assert len(rows) >= 5
+    cols, ld, rd, w = nq.frontier(21, 6)
+    with nq.Server() as srv:
+        tickets = [srv.submit_slice(21, 6, int(r[2]), int(r[3])) for r in rows]
+        for r, t in zip(rows, tickets):
+            _say("n21 slice at", r[2])
+            res = srv.wait(t, timeout_s=300)
+            assert res["status"] == 0
+            assert res["count"] == int(r[4]), r[2]
+    idx = np.concatenate([np.arange(int(r[2]), int(r[2]) + int(r[3])) for r in rows])
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(np.ascontiguousarray(x[idx]).view(np.int32)).to(dev)
+         for x in (cols, ld, rd)]
+    nodes = torch.empty(len(idx), dtype=torch.int64, device=dev)
+    _say("n21 slices per entry", len(idx))
+    counts, _ = nq.count_subproblems(21, *t, depth=6, nodes=nodes)
+    counts = counts.cpu().numpy().view(np.uint64)
+    nodes = nodes.cpu().numpy().view(np.uint64)
+    pos = 0
+    for r in rows:
+        ln = int(r[3])
+        c = counts[pos:pos + ln]
+        assert hashlib.sha256(np.ascontiguousarray(c, dtype="<u8").tobytes()).hexdigest() == r[6]
+        assert int(nodes[pos:pos + ln].sum()) == int(r[5])
+        assert int((c.astype(object) * w[int(r[2]):int(r[2]) + ln].astype(object)).sum()) == \
+            int(r[4])
+        pos += ln

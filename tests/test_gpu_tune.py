@@ -11,12 +11,39 @@ def test_autotune_small_board(known_counts):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     print("[gpu-tune] autotune n=14", flush=True)
-    best = nq.autotune(14, 2, 5, budget_ms=5000)
+    best = nq.autotune(14, 2, 5, budget_ms=5000, table=True)
     assert 2 <= best["depth"] <= 5
     assert best["count"] == known_counts[14]
     assert best["trials"] >= 4 and best["ms"] > 0
-    # nq_count with automatic depth now uses the tuned choice
+    table = best["table"]
+    assert len(table) == best["trials"]
+    assert {r["depth"] for r in table} >= {2, 3, 4, 5}
+    # the workgroup-size axis was measured at the best depth
+    assert {r["wg_size"] for r in table if r["depth"] == best["depth"]} >= {64, 128, 256}
+    assert min(r["ms"] for r in table) == best["ms"]
+    assert best["wg_size"] in (0, 64, 128, 256)
+    # nq_count with automatic depth now uses the tuned choice, remembered here
+    assert nq.tuned_lookup(14) == {k: v for k, v in best.items() if k != "table"}
     assert nq.count(14) == known_counts[14]
+
+
+def test_tuned_workgroup_size_is_used_and_exact(known_counts):
+    """A tuning whose best launch has a workgroup of several waves: nq_count
+    with the automatic depth runs that shape (the remembered tuning says so)
+    and stays exact."""
+    import paper_2511_12009_amd as nq
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    for n in (15, 16):
+        print(f"[gpu-tune] autotune n={n}", flush=True)
+        best = nq.autotune(n, 4, 6, budget_ms=8000, table=True)
+        assert best["count"] == known_counts[n]
+        for wg in (128, 256):
+            assert any(r["wg_size"] == wg for r in best["table"]), (n, wg)
+        assert nq.tuned_lookup(n)["wg_size"] == best["wg_size"]
+        assert nq.count(n) == known_counts[n]
+        for wg in (64, 128, 256):
+            assert nq.count(n, depth=best["depth"], wg_size=wg) == known_counts[n], (n, wg)
 
 
 def test_autotune_rejects_bad_ranges():

@@ -262,3 +262,17 @@ def test_node_identity_over_depth(n):
     ref = nodes(base)
     for k in range(base + 1, min(n - 1, 6)):
         assert ref == nodes(k) + sum(oracle.frontier_size(n, j) for j in range(base + 1, k + 1))
+
+
+def test_stored_oracle_runs_cover_the_ragged_batch():
+    """Every board size of the 256-instance ragged batch above 14 has a stored
+    oracle run (tests/golden/oracle_runs.txt), so the GPU batch tests check
+    every instance against the oracle (live for n <= 14); every stored run's
+    weighted total equals the published count of its board."""
+    import seeded_inputs
+    stored = {int(r[0]): int(r[3]) for r in read_table("oracle_runs.txt")}
+    for n in set(seeded_inputs.ragged_batch_ns()):
+        assert n <= 14 or n in stored, n
+    published = {int(r[0]): int(r[1]) for r in read_table("known_counts.txt")}
+    for n, t in stored.items():
+        assert published[n] == t, n
