@@ -241,6 +241,26 @@ int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const uint32_t* d_l
                          uint64_t* d_counts, uint64_t* d_total, const nq_opts* opts);
 
 /*
+ * nq_count_subproblems_noalloc -- nq_count_subproblems for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.
+ *
+ * Same arguments, layouts, ownership and results as nq_count_subproblems.  The
+ * persistent scheduler's 64-bit work head, the only device memory the DFS
+ * kernels need beyond the caller's buffers, lives in a 256-byte device array
+ * of the library (one per GPU, held until the process ends; the head uses its
+ * first 8 bytes, and no input size changes that), zeroed by a kernel before
+ * each launch.  The call allocates nothing, never synchronizes and records no
+ * memset.  opts->kernel_ms_out must be NULL (timing would create events):
+ * NQ_EINVAL otherwise.  The first call on a device looks up the array's
+ * device address.  Calls that overlap on one GPU (on different streams or
+ * threads) share the array and race on the head: the caller serializes them.
+ */
+int nq_count_subproblems_noalloc(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
+                                 const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len,
+                                 uint64_t* d_counts, uint64_t* d_total, const nq_opts* opts);
+
+/*
  * nq_count_batch -- many independent counts in one persistent launch.
  *
  * For each instance i < ninst, builds the frontier of ns[i] (depth from

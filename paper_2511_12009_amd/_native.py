@@ -120,6 +120,9 @@ def lib():
         L.nq_count.restype = ct.c_int
         L.nq_count_subproblems.argtypes = [u32, vp, vp, vp, vp, u64, vp, vp, ct.POINTER(NqOpts)]
         L.nq_count_subproblems.restype = ct.c_int
+        L.nq_count_subproblems_noalloc.argtypes = [u32, vp, vp, vp, vp, u64, vp, vp,
+                                                   ct.POINTER(NqOpts)]
+        L.nq_count_subproblems_noalloc.restype = ct.c_int
         L.nq_count_batch.argtypes = [u32, pu32, pu32, ct.POINTER(NqOpts), pu64]
         L.nq_count_batch.restype = ct.c_int
         L.nq_serve_create.argtypes = [ct.POINTER(NqOpts), u64, ct.POINTER(vp)]
