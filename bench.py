@@ -120,6 +120,30 @@ def profiled_executed(n, k):
     return {"lane_ops_per_s": rate, "frac": rate / INT_PEAK, "source": kv["source"]}
 
 
+def profiled_clock(n, k):
+    """The shader clock during the profiled DFS dispatch (GRBM_GUI_ACTIVE of the
+    8 XCDs over the dispatch's duration), in Hz, or None."""
+    kv = profiled_counters(n, k)
+    if not kv or "grbm_gui_active" not in kv:
+        return None
+    return int(kv["grbm_gui_active"]) / 8 / (int(kv["kernel_ns"]) / 1e9)
+
+
+def profiled_lds(n, k, kernel_ms):
+    """The DFS kernel's LDS instruction rate per CU (SQ_INSTS_LDS of the
+    committed counter run, per launch, over this run's kernel time) against
+    the ceiling the LDS microbenchmark measured for the same access pair (one
+    ds_write_b128 and one ds_read_b128 per wave-step, interleaved layout, 16
+    waves per CU), or None."""
+    kv = profiled_counters(n, k)
+    if not kv or "lds_instructions" not in kv or "lds_ceiling_per_cu" not in kv:
+        return None
+    rate = int(kv["lds_instructions"]) / 256 / (kernel_ms / 1e3)
+    ceiling = float(kv["lds_ceiling_per_cu"])
+    return {"instr_per_launch": int(kv["lds_instructions"]), "per_cu_per_s": rate,
+            "ceiling_per_cu_per_s": ceiling, "frac": rate / ceiling, "source": kv["source"]}
+
+
 def known_counts():
     """Expected Q(n): the oracle's weighted total where tests/golden/oracle_runs.txt
     holds an oracle run of n (written by tests/golden/make_golden.py), else the
@@ -237,18 +261,25 @@ def _serve_count_work(nq, torch, n, entries):
     raise SystemExit(f"bench.py: no frontier depth of N={n} has {entries} entries")
 
 
-def _slice_check(nq, torch, n, k, cols, ld, rd, w, start, length):
-    """A second path for one slice: its entries expanded two rows (as the server
-    does), searched by nq_count_subproblems with node counts; returns
-    (weighted total, entries searched, DFS nodes)."""
+def _slice_check(nq, torch, n, k, cols, ld, rd, w, start, length, entries):
+    """A second path for one slice: its entries expanded by as many rows as the
+    server expanded them (the rows whose child count is the `entries` the
+    server searched), searched by nq_count_subproblems with node counts;
+    returns (weighted total, entries searched, DFS nodes)."""
     dev = torch.device("cuda:0")
     sl = slice(start, start + length)
     t = [torch.from_numpy(np.ascontiguousarray(x[sl]).view(np.int32)).to(dev)
          for x in (cols, ld, rd)]
     tw = torch.from_numpy(np.ascontiguousarray(w[sl])).to(dev)
-    c, l, r, ww = nq.expand(n, 2, t[0], t[1], t[2], tw)
+    for rows in (3, 2, 1):
+        c, l, r, ww = nq.expand(n, rows, t[0], t[1], t[2], tw)
+        if c.numel() == entries:
+            break
+    else:
+        c, l, r, ww, rows = t[0], t[1], t[2], tw, 0
     nodes = torch.zeros(c.numel(), dtype=torch.int64, device=dev)
-    _, tot = nq.count_subproblems(n, c, l, r, weight=ww, counts=False, depth=k + 2, nodes=nodes)
+    _, tot = nq.count_subproblems(n, c, l, r, weight=ww, counts=False, depth=k + rows,
+                                  nodes=nodes)
     return int(tot.item()), c.numel(), int(nodes.sum())
 
 
@@ -266,7 +297,7 @@ def bench_serving(nq, torch, known, rates, seconds):
     c21, l21, r21, w21 = nq.frontier(n21, k21)
     res = {"solo_count_ms": {}, "rates": []}
     count_nodes, slice_ref = {}, {}
-    with nq.Server(hbm_budget=16 << 30) as srv:
+    with nq.Server(hbm_budget=64 << 30) as srv:
         srv.wait(srv.submit_slice(n21, k21, 0, 1))          # builds the resident frontier
         for n in range(10, 19):
             srv.wait(srv.submit_count(n))                     # builds this N's frontier
@@ -317,7 +348,7 @@ def bench_serving(nq, torch, known, rates, seconds):
                 else:
                     if arg not in slice_ref:
                         slice_ref[arg] = _slice_check(nq, torch, n21, k21, c21, l21, r21, w21,
-                                                      *arg)
+                                                      *arg, r["entries"])
                     want, entries, nd = slice_ref[arg]
                     if r["count"] != want or r["entries"] != entries:
                         raise SystemExit(f"bench.py: serving slice {arg} = {r['count']}, "
@@ -343,17 +374,17 @@ def bench_serving(nq, torch, known, rates, seconds):
     return res
 
 
-def device_frontier(nq, torch, dev, k):
-    """The N=20 depth-k frontier as device tensors (cols, ld, rd int32, weight
-    uint8): built on the host, and for k > 8 at depth k-2 and expanded by two
-    rows on the device."""
+def device_frontier(nq, torch, dev, k, n=N):
+    """The depth-k frontier of an n board (default N=20) as device tensors
+    (cols, ld, rd int32, weight uint8): built on the host, and for k > 8 at
+    depth k-2 and expanded by two rows on the device."""
     hk = k if k <= 8 else k - 2
-    cols, ld, rd, w = nq.frontier(N, hk)
+    cols, ld, rd, w = nq.frontier(n, hk)
     t = [torch.from_numpy(x.view(np.int32)).to(dev) for x in (cols, ld, rd)]
     tw = torch.from_numpy(w).to(dev)
     if hk == k:
         return t[0], t[1], t[2], tw
-    out = nq.expand(N, k - hk, t[0], t[1], t[2], tw)
+    out = nq.expand(n, k - hk, t[0], t[1], t[2], tw)
     torch.cuda.synchronize()
     return out
 
@@ -386,7 +417,9 @@ UB_OPS = {0: "v_add3_u32", 1: "v_bitop3_b32", 2: "v_cndmask_b32 (SGPR mask)",
           11: "v_add_u32"}
 UB_LDS_OPS = {0: ("write b128 + read b128", 2), 1: ("read b128", 1), 2: ("write b128", 1),
               3: ("exchange 16 B (wrxchg2_rtn_b64)", 1), 4: ("write b64 + read b64", 2),
-              5: ("write b32 + read b32", 2)}
+              5: ("write b32 + read b32", 2), 6: ("write b64", 1), 7: ("write b32", 1),
+              8: ("write b96", 1), 9: ("write 16 B as write2_b64", 1), 10: ("read b96", 1),
+              11: ("read 16 B as read2_b64", 1)}
 
 
 def run_ubench(nq, args):
@@ -435,7 +468,7 @@ def run_ubench(nq, args):
         for wpc in (4, 8, 16):
             for active in (64, 32, 16):
                 lds(layout, 0, wpc, active)
-    for op in (1, 2, 3, 4, 5):
+    for op in range(1, len(UB_LDS_OPS)):
         for wpc in (8, 16):
             for active in (64, 16):
                 lds(0, op, wpc, active)
@@ -448,56 +481,78 @@ def run_ubench(nq, args):
     return out
 
 
-def run_ablation(nq, torch):
-    """The paper's design choices measured on this GPU (N=20, one launch over the
-    resident frontier, kernel time from HIP events; every run checked against
-    Q(20)): the pre-placement depth (its Table 3), the block size of the plain
-    launch (its Table 4), the frame kept in registers or re-read from the LDS
-    stack every step, and the last-row step on or off (its Table 5)."""
+ABLATION_PLAN = {
+    # n: (pre-placement depths, depth of the plain block-size sweep, repetitions)
+    17: (range(3, 10), 5, 2),
+    18: (range(3, 10), 5, 2),
+    19: (range(4, 10), 5, 2),
+    20: (range(5, 11), 6, 2),
+    21: (range(7, 11), None, 1),
+}
+FORM_NAMES = {0: "registers, compiler-scheduled step", 1: "registers, hand-placed exec masks",
+              2: "registers, negated untried set", 3: "registers, no selects (push, pop back)",
+              4: "frame re-read from LDS every step", 5: "registers, no last-row step"}
+
+
+def run_ablation(nq, torch, n):
+    """The paper's design choices measured on this GPU for one board size (one
+    launch over the resident frontier, kernel time from HIP events; every run
+    checked against the expected count): the pre-placement depth (its Table
+    3), the block size of the plain launch (its Table 4), and, at the best
+    depth, every inner-loop form: the frame kept in registers or re-read from
+    the LDS stack every step, the last-row step on or off (its Table 5), and
+    the hand-scheduled steps (its inline assembly, Table 6)."""
     dev = torch.device("cuda:0")
-    out = {"n": N, "depth_sweep": [], "plain_block_sweep": [], "forms": []}
+    expect = known_counts()[n]
+    depths, plain_k, reps = ABLATION_PLAN[n]
+    out = {"n": n, "expected": expect, "depth_sweep": [], "plain_block_sweep": [], "forms": []}
 
     def once(t, k, **kw):
         total = torch.zeros(1, dtype=torch.int64, device=dev)
-        _, _, ms = nq.count_subproblems(N, t[0], t[1], t[2], weight=t[3], counts=False,
+        _, _, ms = nq.count_subproblems(n, t[0], t[1], t[2], weight=t[3], counts=False,
                                         total=total, depth=k, timing=True, **kw)
-        if int(total.item()) != EXPECT:
-            raise SystemExit(f"bench.py: ablation total {int(total.item())} != {EXPECT} ({kw})")
+        if int(total.item()) != expect:
+            raise SystemExit(f"bench.py: ablation N={n} total {int(total.item())} != {expect} "
+                             f"({kw})")
         return ms
 
-    for k in range(5, 11):
-        t = device_frontier(nq, torch, dev, k)
-        ms = min(once(t, k), once(t, k))
-        nodes = golden_nodes(N, k)
+    def best_of(t, k, **kw):
+        return min(once(t, k, **kw) for _ in range(reps))
+
+    for k in depths:
+        t = device_frontier(nq, torch, dev, k, n)
+        ms = best_of(t, k)
+        nodes = golden_nodes(n, k)
         out["depth_sweep"].append({"depth": k, "subproblems": t[0].numel(), "kernel_ms": ms,
                                    "nodes_per_s": nodes / (ms / 1e3) if nodes else None})
-        print(f"[bench] ablation depth {k}: {ms:.1f} ms", file=sys.stderr, flush=True)
-        if k == 6:
+        print(f"[bench] ablation N={n} depth {k}: {ms:.1f} ms", file=sys.stderr, flush=True)
+        if k == plain_k:
             for wg in (64, 128, 256, 512, 1024):
                 try:
                     pm = once(t, k, mode="plain", wg_size=wg)
                 except nq.NQError as e:               # stacks exceed the LDS of a workgroup
                     pm = None
-                    print(f"[bench] ablation plain k=6 wg {wg}: {e}", file=sys.stderr, flush=True)
+                    print(f"[bench] ablation N={n} plain k={k} wg {wg}: {e}", file=sys.stderr,
+                          flush=True)
                 out["plain_block_sweep"].append({"depth": k, "wg_size": wg, "kernel_ms": pm})
                 if pm is not None:
-                    print(f"[bench] ablation plain k=6 wg {wg}: {pm:.1f} ms", file=sys.stderr,
-                          flush=True)
-        if k == 9:
-            names = {0: "registers, compiler-scheduled step", 1: "registers, hand-placed exec masks",
-                     2: "registers, negated untried set", 4: "frame re-read from LDS every step",
-                     5: "registers, no last-row step"}
-            for form in (1, 0, 2, 4, 5):
-                nq.set_loop_form(form)
-                try:
-                    fm = min(once(t, k), once(t, k))
-                finally:
-                    nq.set_loop_form(-1)
-                out["forms"].append({"form": form, "what": names[form], "depth": k,
-                                     "kernel_ms": fm})
-                print(f"[bench] ablation form {form}: {fm:.1f} ms", file=sys.stderr, flush=True)
+                    print(f"[bench] ablation N={n} plain k={k} wg {wg}: {pm:.1f} ms",
+                          file=sys.stderr, flush=True)
         del t
         torch.cuda.empty_cache()
+    best = min(out["depth_sweep"], key=lambda r: r["kernel_ms"])["depth"]
+    t = device_frontier(nq, torch, dev, best, n)
+    for form in (1, 0, 2, 3, 4, 5):
+        nq.set_loop_form(form)
+        try:
+            fm = best_of(t, best)
+        finally:
+            nq.set_loop_form(-1)
+        out["forms"].append({"form": form, "what": FORM_NAMES[form], "depth": best,
+                             "kernel_ms": fm})
+        print(f"[bench] ablation N={n} form {form}: {fm:.1f} ms", file=sys.stderr, flush=True)
+    del t
+    torch.cuda.empty_cache()
     return out
 
 
@@ -549,7 +604,9 @@ def main():
     ap.add_argument("--no-shards", action="store_true")
     ap.add_argument("--ablation", action="store_true",
                     help="measure the paper's design choices (depth, plain block size, loop "
-                         "forms) at N=20 and print them as one JSON line instead")
+                         "forms) and print them as one JSON line instead")
+    ap.add_argument("--ablation-n", default="20",
+                    help="board sizes of --ablation, comma list from 17..21")
     ap.add_argument("--serving-only", action="store_true",
                     help="only the serving loop at --serve-rates (one JSON line)")
     ap.add_argument("--ubench", action="store_true",
@@ -573,7 +630,8 @@ def main():
         profile_run(nq, torch, args.depth or 8, args)
         return
     if args.ablation:
-        print(json.dumps({"ablation": run_ablation(nq, torch)}), flush=True)
+        res = [run_ablation(nq, torch, int(x)) for x in args.ablation_n.split(",") if x.strip()]
+        print(json.dumps({"ablation": res}), flush=True)
         return
     if args.ubench:
         print(json.dumps({"ubench": run_ubench(nq, args)}), flush=True)
@@ -716,11 +774,16 @@ def main():
     }
     if nodes:
         achieved = nodes * OPS_PER_NODE / (kern_ms / 1e3)
+        clk = profiled_clock(N, k)
         out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_PEAK / 1e12,
                            "unit": "Tint32op/s", "frac": achieved / INT_PEAK,
                            "traffic": profiled_traffic(N, k),
                            "executed": profiled_executed(N, k),
-                           "ops_per_node": OPS_PER_NODE, "kernel_ms": kern_ms}
+                           "ops_per_node": OPS_PER_NODE, "kernel_ms": kern_ms,
+                           "clock_ghz": clk / 1e9 if clk else None,
+                           "peak_at_measured_clock": (256 * 64 * clk / 1e12) if clk else None,
+                           "frac_at_measured_clock": (achieved / (256 * 64 * clk)) if clk else None,
+                           "lds": profiled_lds(N, k, kern_ms)}
     out["launch"] = {"waves_per_cu": args.waves_per_cu, "refill_every": args.refill,
                      "claim": args.claim,
                      "wg_size": args.wg, "autotune": tuned}

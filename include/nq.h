@@ -424,13 +424,15 @@ int nq_batch_destroy(nq_batch* batch);
  * pre-placed subproblem of Section 1, searched by the DFS of Algorithm 2 /
  * Algorithm 3.  Requests:
  *   NQ_REQ_COUNT  Q(n); depth = pre-placement depth (0 = the server picks the
- *                 shallowest depth with >= 2^18 subproblems, at most n - 4).
+ *                 shallowest depth with >= 2^18 subproblems and at least
+ *                 n - 11, at most n - 4).
  *   NQ_REQ_SLICE  sum(weight * count) over entries [start, start + len) of the
  *                 (n, depth) frontier in nq_frontier order.
  * Every (n, depth) frontier is built once and kept in device memory; requests
  * are copied out of it on the device.  For slices of a frontier of >= 2^16
- * entries (depth >= 2) the kept frontier is expanded by two rows (one when
- * n < depth + 10), as far as the budget allows: a slice's subtrees are then
+ * entries (depth >= 2) the kept frontier is expanded by three rows (two when
+ * n < depth + 13, one when n < depth + 10), as far as the budget allows (half
+ * of it holds kept frontiers): a slice's subtrees are then
  * searched as their children, a contiguous range of the expanded frontier with
  * the same weights, so the result is unchanged and the work spreads wider.
  * A scheduler thread owned by the server admits requests in arrival order while

@@ -66,17 +66,71 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
 
 }  // namespace
 
-// Serving: adds the entries that the wave's lanes retire at one scheduler
-// visit to their requests, with one atomic add to the total and one atomic
-// subtraction from the remaining count per request present among them (the
-// lanes that retire together mostly hold entries of one request, so a request
-// of F entries costs about F / 64 atomic pairs, not F on one address).  The
-// lane whose subtraction takes a request's remaining count to zero publishes
-// its total to host memory: value first, then the generation flag, each a
-// system-scope store, so a host that sees the flag also sees the value.  Every
-// lane of the wave calls it; `retiring` lanes pass their request slot `s` and
-// weighted count `val`.
-__device__ __forceinline__ void retire_to_requests(uint32_t* remaining, unsigned long long* totals,
+// Serving: the wave's retirements, added to their requests.  A request's total
+// and remaining count are only touched by device-scope atomics; the lane whose
+// subtraction takes the remaining count to zero publishes the total to host
+// memory: value first, then the generation flag, each a system-scope store,
+// so a host that sees the flag also sees the value.
+//
+// Ordering without cache maintenance: device-scope atomics are performed at
+// one point for all CUs, and a flush waits for its addition to the total to
+// return before it issues its subtraction, so when the subtractions reach zero
+// every addition has been performed and the finishing lane's atomic read of
+// the total sees them all.  (A device-scope fence here would write back and
+// invalidate the L2 of the wave's XCD.)
+//
+// Each atomic pair makes the wave wait for a round trip to that point, so a
+// wave keeps what its lanes retire for one request (wave-uniform: slot, sum,
+// entries) and flushes it when a retirement of another request arrives, after
+// kRetireHold scheduler visits, or when the wave ends; the lanes of a wave
+// mostly hold consecutive entries of one request, so most visits only add to
+// the held sum.
+constexpr uint32_t kNoSlot = 0xffffffffu;
+constexpr uint32_t kRetireHold = 8;
+
+struct RetireHold {
+    uint32_t slot = kNoSlot;     // request slot held (wave-uniform), kNoSlot = none
+    uint32_t entries = 0;        // entries retired and not yet subtracted
+    uint32_t visits = 0;         // scheduler visits since the first held retirement
+    uint64_t sum = 0;            // weighted count not yet added
+};
+
+// Adds the held retirements to their request (lane 0 issues the atomics).
+__device__ __forceinline__ void retire_flush(RetireHold& h, uint32_t* remaining,
+                                             unsigned long long* totals, const uint32_t* gen,
+                                             unsigned long long* host_val,
+                                             unsigned long long* host_flag, uint32_t lane) {
+    if (h.slot == kNoSlot) return;
+    if (lane == 0) {
+        const uint32_t s0 = h.slot;
+        if (h.sum != 0) {
+            const unsigned long long was = __hip_atomic_fetch_add(
+                &totals[s0], (unsigned long long)h.sum, __ATOMIC_RELAXED,
+                __HIP_MEMORY_SCOPE_AGENT);
+            asm volatile("" : : "v"(was) : "memory");       // returned: performed
+        }
+        const uint32_t before = __hip_atomic_fetch_sub(&remaining[s0], h.entries,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (before == h.entries) {
+            const unsigned long long t = __hip_atomic_fetch_add(
+                &totals[s0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&host_val[s0], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&host_flag[s0], (unsigned long long)gen[s0], __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+    h.slot = kNoSlot;
+    h.entries = 0;
+    h.visits = 0;
+    h.sum = 0;
+}
+
+// One scheduler visit's retirements: `retiring` lanes pass their request slot
+// `s` and weighted count `val`; every lane of the wave calls it.  The lanes of
+// one request are summed with a wave reduction and added to the held
+// retirements (flushing those first when they belong to another request).
+__device__ __forceinline__ void retire_to_requests(RetireHold& h, uint32_t* remaining,
+                                                   unsigned long long* totals,
                                                    const uint32_t* gen,
                                                    unsigned long long* host_val,
                                                    unsigned long long* host_flag, bool retiring,
@@ -84,26 +138,20 @@ __device__ __forceinline__ void retire_to_requests(uint32_t* remaining, unsigned
     uint64_t pend = __builtin_amdgcn_ballot_w64(retiring);
     while (pend != 0) {
         const int leader = __ffsll((unsigned long long)pend) - 1;
-        const uint32_t s0 = (uint32_t)__shfl((int)s, leader, 64);
+        const uint32_t s0 = __builtin_amdgcn_readfirstlane((uint32_t)__shfl((int)s, leader, 64));
         const bool mine = retiring && s == s0;
         const uint64_t grp = __builtin_amdgcn_ballot_w64(mine);
         uint64_t add = mine ? val : 0u;
         for (int off = 32; off > 0; off >>= 1) add += shfl_xor_u64(add, off);
-        if ((int)lane == leader) {
-            const uint32_t cnt = (uint32_t)__popcll(grp);
-            if (add != 0) atomicAdd(&totals[s0], (unsigned long long)add);
-            __threadfence();                              // the total before the count
-            const uint32_t before = atomicSub(&remaining[s0], cnt);
-            if (before == cnt) {
-                __threadfence();
-                const unsigned long long t = atomicAdd(&totals[s0], 0ull);
-                __hip_atomic_store(&host_val[s0], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                __hip_atomic_store(&host_flag[s0], (unsigned long long)gen[s0], __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_SYSTEM);
-            }
-        }
+        if (h.slot != s0)
+            retire_flush(h, remaining, totals, gen, host_val, host_flag, lane);
+        h.slot = s0;
+        h.entries += (uint32_t)__popcll(grp);
+        h.sum += add;
         pend &= ~grp;
     }
+    if (h.slot != kNoSlot && ++h.visits >= kRetireHold)
+        retire_flush(h, remaining, totals, gen, host_val, host_flag, lane);
 }
 
 // Per-lane state of the search.  `top` and `floor` are LDS byte addresses in
@@ -310,6 +358,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
     uint64_t wtotal_hi = 0;               // its carries (128-bit totals, P.wide)
     uint32_t acc_s = 0u;                  // batches: instance of the lane's pending sum
     uint64_t acc_v = 0;                   // batches: weighted sum not yet added
+    RetireHold held;                      // serving: retirements not yet added
     bool has_task = false;                // holds an entry not yet retired
     bool exhausted = !PERSISTENT;         // no entries left to claim (wave-uniform)
     bool claimed_all = false;             // head has passed the end (wave-uniform)
@@ -413,7 +462,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
             has_task = false;
         }
         if (SERVE)
-            retire_to_requests(P.remaining, P.totals, P.inst_gen, P.host_val, P.host_flag,
+            retire_to_requests(held, P.remaining, P.totals, P.inst_gen, P.host_val, P.host_flag,
                                req_retire, req_slot, req_val, lane);
         if (PERSISTENT && !exhausted) {
             // Idle lanes take, in rank order, the wave's unused claimed
@@ -677,6 +726,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         c = st.x; l = st.y; r = st.z; v = st.w;
     }
 
+    if (SERVE) retire_flush(held, P.remaining, P.totals, P.inst_gen, P.host_val, P.host_flag, lane);
     if (!SERVE && P.totals && P.inst && acc_v)
         atomicAdd(&P.totals[acc_s], (unsigned long long)acc_v);
     if (P.totals && !P.inst) {

@@ -3,7 +3,7 @@
 // Requests (a full count Q(n), or the weighted sum over a contiguous slice of
 // a frontier) arrive at any time.  Every request is served out of a frontier
 // kept in device memory: built once per (n, depth) and, for slices of a
-// shallow frontier, pre-expanded by up to two rows on the device, so that a
+// shallow frontier, pre-expanded by up to three rows on the device, so that a
 // slice of a few thousand subtrees becomes a few hundred thousand smaller ones
 // (children are contiguous and in order, so a slice maps to one contiguous
 // range of the expanded frontier) and spreads over the whole GPU.  A scheduler
@@ -140,12 +140,16 @@ namespace nqi {
 
 namespace {
 
-// Smallest depth whose frontier has at least kCountEntries entries, within the
-// server's stack budget (frames) and at most n - 4 (n - 2 for small boards).
+// Smallest depth whose frontier has at least kCountEntries entries, and at
+// least n - 11 (at most 9 stack frames per lane: the LDS-bound DFS keeps 16
+// waves per CU, and a large board's subtrees stay a few thousand nodes, so
+// one request's tail is short), within the server's stack budget (frames) and
+// at most n - 4 (n - 2 for small boards).
 uint32_t count_depth(uint32_t n, uint32_t max_frames) {
     if (n <= 3) return n;                       // tiny boards: full pre-placement
     const uint32_t hi = n > 6 ? n - 4 : n - 2;
-    const uint32_t lo = (n >= max_frames + 2) ? std::max<uint32_t>(1, n - 2 - max_frames) : 1u;
+    uint32_t lo = (n >= max_frames + 2) ? std::max<uint32_t>(1, n - 2 - max_frames) : 1u;
+    if (n > 11 + lo) lo = std::min(hi, n - 11);
     for (uint32_t k = lo; k <= hi; ++k) {
         uint64_t f = 0;
         if (frontier_fill(n, k, nullptr, nullptr, nullptr, nullptr, 0, &f, nullptr) != NQ_OK)
@@ -160,8 +164,8 @@ uint32_t count_depth(uint32_t n, uint32_t max_frames) {
 // for).  COUNT residents are the plain frontier (its depth already gives
 // kCountEntries subtrees).  SLICE residents of a frontier of at least
 // kSliceSplit entries, where a slice is a small part of a large search, are
-// expanded by two rows (one when fewer rows would be left below), as far as the
-// resident budget allows.
+// expanded by three rows (two or one when fewer rows would be left below), as
+// far as the resident budget allows.
 int ensure_resident(nq_server* s, uint32_t n, uint32_t depth, uint32_t kind, Resident** out) {
     auto key = std::make_tuple(n, depth, kind);
     auto it = s->resident.find(key);
@@ -174,7 +178,7 @@ int ensure_resident(nq_server* s, uint32_t n, uint32_t depth, uint32_t kind, Res
     if (rc != NQ_OK) return rc;
     uint32_t rows = 0;
     if (kind == NQ_REQ_SLICE && depth >= 2 && F >= kSliceSplit)
-        rows = (n >= depth + 10) ? 2u : (n >= depth + 7) ? 1u : 0u;
+        rows = (n >= depth + 13) ? 3u : (n >= depth + 10) ? 2u : (n >= depth + 7) ? 1u : 0u;
     const uint64_t avail = s->budget / 2 > s->resident_bytes ? s->budget / 2 - s->resident_bytes : 0;
     for (; rows > 0; --rows) {                   // the deepest expansion that fits
         uint64_t Fd = 0;
