@@ -607,6 +607,16 @@ def main():
                          "forms) and print them as one JSON line instead")
     ap.add_argument("--ablation-n", default="20",
                     help="board sizes of --ablation, comma list from 17..21")
+    ap.add_argument("--big-counts", default=None,
+                    help="comma list of boards (21..23) counted whole by nq_count's automatic "
+                         "chunked path; one JSON line per board")
+    ap.add_argument("--resumable", type=int, default=0,
+                    help="count this board with nq_count_resumable, one chunk per call, "
+                         "printing a line per chunk (with --resumable-path, --resumable-upto)")
+    ap.add_argument("--resumable-path", default="n.progress")
+    ap.add_argument("--resumable-upto", type=int, default=0, help="stop after this many chunks")
+    ap.add_argument("--resumable-chunks", type=int, default=64)
+    ap.add_argument("--resumable-depth", type=int, default=0)
     ap.add_argument("--serving-only", action="store_true",
                     help="only the serving loop at --serve-rates (one JSON line)")
     ap.add_argument("--ubench", action="store_true",
@@ -635,6 +645,34 @@ def main():
         return
     if args.ubench:
         print(json.dumps({"ubench": run_ubench(nq, args)}), flush=True)
+        return
+    if args.big_counts:
+        known = known_counts()
+        for n in (int(x) for x in args.big_counts.split(",") if x.strip()):
+            t = time.perf_counter()
+            got, ms = nq.count(n, timing=True)
+            row = {"n": n, "count": got, "exact": got == known.get(n), "kernel_ms": ms,
+                   "wall_s": time.perf_counter() - t}
+            if got != known.get(n):
+                raise SystemExit(f"bench.py: Q({n}) = {got}, expected {known.get(n)}")
+            print(json.dumps(row), flush=True)
+        return
+    if args.resumable:
+        t0 = time.perf_counter()
+        while True:
+            t = time.perf_counter()
+            total, done, fin = nq.count_resumable(args.resumable, args.resumable_path,
+                                                  chunks=args.resumable_chunks, max_chunks=1,
+                                                  depth=args.resumable_depth)
+            print(json.dumps({"n": args.resumable, "chunks_done": done, "total": total,
+                              "chunk_s": time.perf_counter() - t,
+                              "elapsed_s": time.perf_counter() - t0, "finished": fin}),
+                  flush=True)
+            if fin or (args.resumable_upto and done >= args.resumable_upto):
+                break
+        if fin and total != known_counts().get(args.resumable, total):
+            raise SystemExit(f"bench.py: Q({args.resumable}) = {total}, expected "
+                             f"{known_counts()[args.resumable]}")
         return
     if args.serving_only:
         rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]

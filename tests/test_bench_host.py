@@ -59,6 +59,13 @@ def test_counter_record_is_read_when_the_digest_matches(monkeypatch):
     rate = int(rec["valu_lane_ops"]) / (int(rec["kernel_ns"]) / 1e9)
     assert ex["lane_ops_per_s"] == pytest.approx(rate)
     assert 0.0 < ex["frac"] <= 1.0
+    clk = bench.profiled_clock(20, 9)
+    assert clk == pytest.approx(int(rec["grbm_gui_active"]) / 8 / (int(rec["kernel_ns"]) / 1e9))
+    assert 1.0e9 < clk < 2.5e9
+    lds = bench.profiled_lds(20, 9, 1000.0)
+    assert lds["instr_per_launch"] == int(rec["lds_instructions"])
+    assert lds["per_cu_per_s"] == pytest.approx(int(rec["lds_instructions"]) / 256 / 1.0)
+    assert lds["frac"] == pytest.approx(lds["per_cu_per_s"] / float(rec["lds_ceiling_per_cu"]))
     # another workload has no record
     assert bench.profiled_counters(20, 8) is None
     assert bench.profiled_counters(21, 9) is None
@@ -70,6 +77,7 @@ def test_counter_record_is_ignored_for_other_sources_or_overrides(monkeypatch):
     assert bench.profiled_counters(20, 9) is None
     assert bench.profiled_traffic(20, 9) is None
     assert bench.profiled_executed(20, 9) is None
+    assert bench.profiled_clock(20, 9) is None and bench.profiled_lds(20, 9, 1000.0) is None
     monkeypatch.setattr(bench, "kernel_digest", lambda: rec["kernel_sha256"])
     monkeypatch.setenv("NQ_DFS_LOOP", "2")
     assert bench.profiled_counters(20, 9) is None
