@@ -23,6 +23,12 @@ kings section of ``oracle.c``), with the same shapes:
 kings(n), kings_brute_count(n, prefix=()), kings_frontier(n, k),
 kings_frontier_size(n, k), kings_prefixes_masks(n, prefixes),
 kings_count_prefixes(n, prefixes, threads)
+
+The third search (the permanent of a 0/1 matrix ``a``, uint8[n, n]: the
+permutations s with a[r, s(r)] != 0 for every row r; see the permanents
+section of ``oracle.c``); prefixes carry no weights:
+permanent(a), perm_frontier(a, k), perm_frontier_size(a, k),
+perm_prefixes_cols(n, prefixes), perm_count_prefixes(a, prefixes, threads)
 """
 from __future__ import annotations
 
@@ -70,10 +76,16 @@ def _lib():
                                            u32p]
         lib.oqk_count_prefixes.argtypes = [_ct.c_int, _ct.c_int, i32p, _ct.c_uint64, _ct.c_int,
                                            u64p, u64p]
+        lib.oqp_count_prefix.argtypes = [_ct.c_int, u8p, _ct.c_int, i32p, u64p, u64p]
+        lib.oqp_frontier.argtypes = [_ct.c_int, u8p, _ct.c_int, i32p, u8p, _ct.c_uint64, u64p]
+        lib.oqp_prefixes_cols.argtypes = [_ct.c_int, _ct.c_int, i32p, _ct.c_uint64, u32p]
+        lib.oqp_count_prefixes.argtypes = [_ct.c_int, u8p, _ct.c_int, i32p, _ct.c_uint64,
+                                           _ct.c_int, u64p, u64p]
         for f in (lib.oq_queens, lib.oq_count_prefix, lib.oq_brute_count, lib.oq_frontier,
                   lib.oq_prefix_masks, lib.oq_prefixes_masks, lib.oq_count_prefixes,
                   lib.oqk_count_prefix, lib.oqk_brute_count, lib.oqk_frontier,
-                  lib.oqk_prefixes_masks, lib.oqk_count_prefixes):
+                  lib.oqk_prefixes_masks, lib.oqk_count_prefixes, lib.oqp_count_prefix,
+                  lib.oqp_frontier, lib.oqp_prefixes_cols, lib.oqp_count_prefixes):
             f.restype = _ct.c_int
         _LIB = lib
     return _LIB
@@ -238,3 +250,70 @@ def kings_count_prefixes(n: int, prefixes, threads: int = 1):
                                      nodes.ctypes.data_as(_ct.POINTER(_ct.c_uint64))),
            "oqk_count_prefixes")
     return counts[:m], nodes[:m]
+
+
+# ---- the third search: permanents of 0/1 matrices ----
+
+def _matrix(a):
+    m = _np.ascontiguousarray(_np.asarray(a, dtype=_np.uint8))
+    if m.ndim != 2 or m.shape[0] != m.shape[1] or m.shape[0] < 1:
+        raise OracleError("the matrix must be n x n with n >= 1")
+    return m, m.shape[0], m.ctypes.data_as(_ct.POINTER(_ct.c_uint8))
+
+
+def permanent(a):
+    """The permanent of the 0/1 matrix ``a`` (uint8[n, n]) by plain backtracking
+    over the rows, and its nodes (placements in rows 0..n-2)."""
+    m, n, p = _matrix(a)
+    c, nd = _ct.c_uint64(), _ct.c_uint64()
+    _check(_lib().oqp_count_prefix(n, p, 0, None, _ct.byref(c), _ct.byref(nd)),
+           "oqp_count_prefix")
+    return c.value, nd.value
+
+
+def perm_frontier_size(a, k: int) -> int:
+    m, n, p = _matrix(a)
+    ln = _ct.c_uint64()
+    _check(_lib().oqp_frontier(n, p, k, None, None, 0, _ct.byref(ln)), "oqp_frontier(size)")
+    return ln.value
+
+
+def perm_frontier(a, k: int):
+    """Every prefix of length k (int32[F, k]): rows 0..k-1 in allowed, distinct
+    columns, lexicographic."""
+    m, n, p = _matrix(a)
+    size = perm_frontier_size(m, k)
+    pre = _np.zeros((max(size, 1), max(k, 1)), dtype=_np.int32)
+    ln = _ct.c_uint64()
+    _check(_lib().oqp_frontier(n, p, k, pre.ctypes.data_as(_ct.POINTER(_ct.c_int)), None, size,
+                               _ct.byref(ln)), "oqp_frontier")
+    return pre[:size, :k]
+
+
+def perm_prefixes_cols(n: int, prefixes):
+    """The used-column set (uint32[m], bit c = column c) of each prefix."""
+    pre = _np.ascontiguousarray(_np.asarray(prefixes, dtype=_np.int32))
+    m, k = pre.shape
+    cols = _np.zeros(max(m, 1), dtype=_np.uint32)
+    buf = pre if pre.size else _np.zeros(1, dtype=_np.int32)
+    _check(_lib().oqp_prefixes_cols(n, k, buf.ctypes.data_as(_ct.POINTER(_ct.c_int)), m,
+                                    cols.ctypes.data_as(_ct.POINTER(_ct.c_uint32))),
+           "oqp_prefixes_cols")
+    return cols[:m]
+
+
+def perm_count_prefixes(a, prefixes, threads: int = 1):
+    """Completions and nodes (rows k..n-2) of each prefix of the permanent search."""
+    m, n, p = _matrix(a)
+    pre = _np.ascontiguousarray(_np.asarray(prefixes, dtype=_np.int32))
+    if pre.ndim == 1:
+        pre = pre.reshape(-1, 0) if pre.size == 0 else pre.reshape(1, -1)
+    cnt, k = pre.shape
+    counts = _np.zeros(max(cnt, 1), dtype=_np.uint64)
+    nodes = _np.zeros(max(cnt, 1), dtype=_np.uint64)
+    buf = pre if pre.size else _np.zeros(1, dtype=_np.int32)
+    _check(_lib().oqp_count_prefixes(n, p, k, buf.ctypes.data_as(_ct.POINTER(_ct.c_int)), cnt,
+                                     threads, counts.ctypes.data_as(_ct.POINTER(_ct.c_uint64)),
+                                     nodes.ctypes.data_as(_ct.POINTER(_ct.c_uint64))),
+           "oqp_count_prefixes")
+    return counts[:cnt], nodes[:cnt]

@@ -6,6 +6,9 @@
  * GPU library: no bitmasks, no shifts, no Somers state.  Every board is held as
  * three arrays of occupancy flags, exactly as the problem is defined.
  *
+ * Three searches: the queens (below), the n kings of the second search and the
+ * permanents of 0/1 matrices of the third (at the end of the file).
+ *
  * What is computed (paper, Section 1 and Section 2):
  *   Q(N) = number of ways to put N queens on an N x N board, one per row, with
  *   no two on a common column or diagonal.  A prefix pi = (c_0..c_{k-1}) fixes
@@ -552,6 +555,168 @@ int oqk_count_prefixes(int n, int k, const int* prefixes, uint64_t m, int thread
     for (int t = 0; t < threads; ++t)
         if (pthread_create(&tid[started], NULL, kpool_worker, &p) == 0) ++started;
     if (started == 0) kpool_worker(&p);
+    for (int t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+    return OQ_OK;
+}
+
+/* ================================= third search: permanents of 0/1 matrices */
+/*
+ * The number of permutations s of 0..n-1 with a[r][s(r)] = 1 for every row r:
+ * the permanent of the 0/1 matrix a, a combinatorial permutation count of the
+ * kind the paper's conclusion names as a target of the same method.  It is
+ * run on the GPU with a frame of two words (the used columns and the untried
+ * columns of the row being filled) and a different leaf rule: the last row
+ * has as many completions as it has usable columns.  Here a board is the
+ * array of used columns and the matrix itself, n x n bytes in row-major order
+ * (a[r * n + c] != 0: row r may take column c); prefixes fix the column of
+ * rows 0..k-1 (no symmetry reduction: every weight is 1), in lexicographic
+ * order.  A node is one placement in rows k..n-2, as for the queens.
+ *
+ * Pins (tests/): permutation brute force, Ryser's inclusion-exclusion formula,
+ * the all-ones matrix (n!), permutation matrices (1), the tridiagonal band
+ * (Fibonacci numbers), and the frontier totals against the whole count.
+ */
+
+typedef struct {
+    int n;
+    const uint8_t* a;              /* the matrix, row-major                     */
+    unsigned char used[OQ_MAXN];   /* column c taken by an earlier row          */
+} pboard_t;
+
+static int pboard_allows(const pboard_t* b, int r, int c) {
+    return b->a[r * b->n + c] != 0 && !b->used[c];
+}
+
+/* Completions of rows row..n-1; placements in rows <= n-2 are nodes. */
+static uint64_t pboard_complete(pboard_t* b, int row, uint64_t* nodes) {
+    if (row == b->n) return 1;
+    uint64_t total = 0;
+    for (int c = 0; c < b->n; ++c) {
+        if (!pboard_allows(b, row, c)) continue;
+        if (row <= b->n - 2) ++*nodes;
+        b->used[c] = 1;
+        total += pboard_complete(b, row + 1, nodes);
+        b->used[c] = 0;
+    }
+    return total;
+}
+
+static int pboard_init(pboard_t* b, int n, const uint8_t* a) {
+    memset(b, 0, sizeof(*b));
+    b->n = n;
+    b->a = a;
+    return a != NULL;
+}
+
+/* Place a prefix on an empty board; 0 if a row does not allow its column or a
+ * column repeats. */
+static int pboard_place_prefix(pboard_t* b, int k, const int* prefix) {
+    for (int r = 0; r < k; ++r) {
+        const int c = prefix[r];
+        if (c < 0 || c >= b->n || !pboard_allows(b, r, c)) return 0;
+        b->used[c] = 1;
+    }
+    return 1;
+}
+
+int oqp_count_prefix(int n, const uint8_t* a, int k, const int* prefix, uint64_t* count,
+                     uint64_t* nodes) {
+    if (!valid_nk(n, k) || !count || (k > 0 && !prefix)) return OQ_EINVAL;
+    pboard_t b;
+    if (!pboard_init(&b, n, a)) return OQ_EINVAL;
+    uint64_t nd = 0;
+    *count = pboard_place_prefix(&b, k, prefix) ? pboard_complete(&b, k, &nd) : 0;
+    if (nodes) *nodes = nd;
+    return OQ_OK;
+}
+
+typedef struct {
+    frontier_ctx f;
+    pboard_t b;
+} pfrontier_ctx;
+
+static void pextend(pfrontier_ctx* x, int row) {
+    if (row == x->f.k) { emit(&x->f, 1); return; }
+    for (int c = 0; c < x->f.n; ++c) {
+        if (!pboard_allows(&x->b, row, c)) continue;
+        x->f.cur[row] = c;
+        x->b.used[c] = 1;
+        pextend(x, row + 1);
+        x->b.used[c] = 0;
+    }
+}
+
+/* Every prefix of length k (rows 0..k-1 in allowed, distinct columns),
+ * lexicographic; weights, when asked for, are all 1. */
+int oqp_frontier(int n, const uint8_t* a, int k, int* prefixes, uint8_t* weights,
+                 uint64_t cap, uint64_t* out_len) {
+    if (!valid_nk(n, k) || !out_len) return OQ_EINVAL;
+    pfrontier_ctx x;
+    memset(&x, 0, sizeof(x));
+    x.f.n = n; x.f.k = k; x.f.prefixes = prefixes; x.f.weights = weights;
+    x.f.cap = (prefixes || weights) ? cap : 0;
+    if (!pboard_init(&x.b, n, a)) return OQ_EINVAL;
+    pextend(&x, 0);
+    *out_len = x.f.len;
+    if ((prefixes || weights) && x.f.len > cap) return OQ_ERANGE;
+    return OQ_OK;
+}
+
+/* The used-column set of each prefix (bit c = some row of the prefix took
+ * column c). */
+int oqp_prefixes_cols(int n, int k, const int* prefixes, uint64_t m, uint32_t* cols) {
+    if (!valid_nk(n, k) || !cols || (m > 0 && k > 0 && !prefixes)) return OQ_EINVAL;
+    for (uint64_t i = 0; i < m; ++i) {
+        const int* p = prefixes + i * (uint64_t)k;
+        uint32_t C = 0;
+        for (int r = 0; r < k; ++r) {
+            if (p[r] < 0 || p[r] >= n) return OQ_EINVAL;
+            C |= (uint32_t)1 << p[r];
+        }
+        cols[i] = C;
+    }
+    return OQ_OK;
+}
+
+typedef struct {
+    int n, k;
+    const uint8_t* a;
+    const int* prefixes;
+    uint64_t m;
+    uint64_t* counts;
+    uint64_t* nodes;
+    uint64_t next;
+} ppool_ctx;
+
+static void* ppool_worker(void* arg) {
+    ppool_ctx* p = (ppool_ctx*)arg;
+    for (;;) {
+        uint64_t i = __atomic_fetch_add(&p->next, 1, __ATOMIC_RELAXED);
+        if (i >= p->m) break;
+        uint64_t c = 0, nd = 0;
+        oqp_count_prefix(p->n, p->a, p->k, p->prefixes + i * (uint64_t)p->k, &c, &nd);
+        p->counts[i] = c;
+        if (p->nodes) p->nodes[i] = nd;
+    }
+    return NULL;
+}
+
+/* Completions (and nodes) of m prefixes; threads only spread prefixes. */
+int oqp_count_prefixes(int n, const uint8_t* a, int k, const int* prefixes, uint64_t m,
+                       int threads, uint64_t* counts, uint64_t* nodes) {
+    if (!valid_nk(n, k) || !a || !counts || (m > 0 && k > 0 && !prefixes)) return OQ_EINVAL;
+    ppool_ctx p = { n, k, a, prefixes, m, counts, nodes, 0 };
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    if (threads == 1 || m < 2) {
+        ppool_worker(&p);
+        return OQ_OK;
+    }
+    pthread_t tid[256];
+    int started = 0;
+    for (int t = 0; t < threads; ++t)
+        if (pthread_create(&tid[started], NULL, ppool_worker, &p) == 0) ++started;
+    if (started == 0) ppool_worker(&p);
     for (int t = 0; t < started; ++t) pthread_join(tid[t], NULL);
     return OQ_OK;
 }

@@ -1,7 +1,8 @@
 """Seeded synthetic inputs shared by the tests, the benchmark and the oracle runs.
 
 Holds no part of the counting method: only the random draws that define the
-workloads (board sizes of a ragged batch, request streams of the serving loop).
+workloads (board sizes of a ragged batch, request streams of the serving loop,
+the 0/1 matrices of the permanent search).
 The generator is SplitMix64 (Steele, Lea and Flood, "Fast splittable
 pseudorandom number generators", OOPSLA 2014), written from its published
 definition; a draw for index i is the SplitMix64 output of state seed + i.
@@ -13,6 +14,7 @@ MASK64 = (1 << 64) - 1
 RAGGED_SEED = 0x251112009
 SERVE_SEED = 0x5E4E
 SLICE_SAMPLE_SEED = 0x5E21
+MATRIX_SEED = 0x9E12
 
 
 def splitmix64(state: int) -> int:
@@ -58,3 +60,10 @@ def sample_slices(count: int, nslices: int, seed: int = SLICE_SAMPLE_SEED):
         picked.add(splitmix64((seed + i) & MASK64) % nslices)
         i += 1
     return sorted(picked)
+
+
+def matrix01(n: int, density: float, seed: int = MATRIX_SEED):
+    """An n x n 0/1 matrix (list of rows of ints 0/1): entry (r, c) is 1 when
+    the uniform draw of index r * n + c is at most `density`."""
+    return [[1 if uniform01((seed + r * n + c) & MASK64) <= density else 0 for c in range(n)]
+            for r in range(n)]
