@@ -28,7 +28,8 @@ The third search (the permanent of a 0/1 matrix ``a``, uint8[n, n]: the
 permutations s with a[r, s(r)] != 0 for every row r; see the permanents
 section of ``oracle.c``); prefixes carry no weights:
 permanent(a), perm_frontier(a, k), perm_frontier_size(a, k),
-perm_prefixes_cols(n, prefixes), perm_count_prefixes(a, prefixes, threads)
+perm_prefixes_cols(n, prefixes), perm_count_prefixes(a, prefixes, threads),
+permanent_ryser(a) (Ryser's formula, n <= 20)
 """
 from __future__ import annotations
 
@@ -81,11 +82,13 @@ def _lib():
         lib.oqp_prefixes_cols.argtypes = [_ct.c_int, _ct.c_int, i32p, _ct.c_uint64, u32p]
         lib.oqp_count_prefixes.argtypes = [_ct.c_int, u8p, _ct.c_int, i32p, _ct.c_uint64,
                                            _ct.c_int, u64p, u64p]
+        lib.oqp_ryser.argtypes = [_ct.c_int, u8p, u64p]
         for f in (lib.oq_queens, lib.oq_count_prefix, lib.oq_brute_count, lib.oq_frontier,
                   lib.oq_prefix_masks, lib.oq_prefixes_masks, lib.oq_count_prefixes,
                   lib.oqk_count_prefix, lib.oqk_brute_count, lib.oqk_frontier,
                   lib.oqk_prefixes_masks, lib.oqk_count_prefixes, lib.oqp_count_prefix,
-                  lib.oqp_frontier, lib.oqp_prefixes_cols, lib.oqp_count_prefixes):
+                  lib.oqp_frontier, lib.oqp_prefixes_cols, lib.oqp_count_prefixes,
+                  lib.oqp_ryser):
             f.restype = _ct.c_int
         _LIB = lib
     return _LIB
@@ -263,7 +266,7 @@ def _matrix(a):
 
 def permanent(a):
     """The permanent of the 0/1 matrix ``a`` (uint8[n, n]) by plain backtracking
-    over the rows, and its nodes (placements in rows 0..n-2)."""
+    over the rows, and its nodes (placements in rows 0..n-3)."""
     m, n, p = _matrix(a)
     c, nd = _ct.c_uint64(), _ct.c_uint64()
     _check(_lib().oqp_count_prefix(n, p, 0, None, _ct.byref(c), _ct.byref(nd)),
@@ -303,7 +306,7 @@ def perm_prefixes_cols(n: int, prefixes):
 
 
 def perm_count_prefixes(a, prefixes, threads: int = 1):
-    """Completions and nodes (rows k..n-2) of each prefix of the permanent search."""
+    """Completions and nodes (rows k..n-3) of each prefix of the permanent search."""
     m, n, p = _matrix(a)
     pre = _np.ascontiguousarray(_np.asarray(prefixes, dtype=_np.int32))
     if pre.ndim == 1:
@@ -317,3 +320,12 @@ def perm_count_prefixes(a, prefixes, threads: int = 1):
                                      nodes.ctypes.data_as(_ct.POINTER(_ct.c_uint64))),
            "oqp_count_prefixes")
     return counts[:cnt], nodes[:cnt]
+
+
+def permanent_ryser(a):
+    """The permanent of ``a`` by Ryser's inclusion-exclusion formula (exact in
+    128-bit arithmetic, n <= 20): independent of the search above."""
+    m, n, p = _matrix(a)
+    c = _ct.c_uint64()
+    _check(_lib().oqp_ryser(n, p, _ct.byref(c)), "oqp_ryser")
+    return c.value

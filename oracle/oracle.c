@@ -565,12 +565,14 @@ int oqk_count_prefixes(int n, int k, const int* prefixes, uint64_t m, int thread
  * the permanent of the 0/1 matrix a, a combinatorial permutation count of the
  * kind the paper's conclusion names as a target of the same method.  It is
  * run on the GPU with a frame of two words (the used columns and the untried
- * columns of the row being filled) and a different leaf rule: the last row
- * has as many completions as it has usable columns.  Here a board is the
+ * columns of the row being filled) and a different leaf rule: the last two
+ * rows are never entered; their completions are counted in closed form.
+ * Here a board is the
  * array of used columns and the matrix itself, n x n bytes in row-major order
  * (a[r * n + c] != 0: row r may take column c); prefixes fix the column of
  * rows 0..k-1 (no symmetry reduction: every weight is 1), in lexicographic
- * order.  A node is one placement in rows k..n-2, as for the queens.
+ * order.  A node is one placement in rows k..n-3 (the rows the search enters;
+ * placements in the last two rows belong to the leaf count).
  *
  * Pins (tests/): permutation brute force, Ryser's inclusion-exclusion formula,
  * the all-ones matrix (n!), permutation matrices (1), the tridiagonal band
@@ -587,13 +589,13 @@ static int pboard_allows(const pboard_t* b, int r, int c) {
     return b->a[r * b->n + c] != 0 && !b->used[c];
 }
 
-/* Completions of rows row..n-1; placements in rows <= n-2 are nodes. */
+/* Completions of rows row..n-1; placements in rows <= n-3 are nodes. */
 static uint64_t pboard_complete(pboard_t* b, int row, uint64_t* nodes) {
     if (row == b->n) return 1;
     uint64_t total = 0;
     for (int c = 0; c < b->n; ++c) {
         if (!pboard_allows(b, row, c)) continue;
-        if (row <= b->n - 2) ++*nodes;
+        if (row <= b->n - 3) ++*nodes;
         b->used[c] = 1;
         total += pboard_complete(b, row + 1, nodes);
         b->used[c] = 0;
@@ -718,5 +720,32 @@ int oqp_count_prefixes(int n, const uint8_t* a, int k, const int* prefixes, uint
         if (pthread_create(&tid[started], NULL, ppool_worker, &p) == 0) ++started;
     if (started == 0) ppool_worker(&p);
     for (int t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+    return OQ_OK;
+}
+
+/*
+ * The permanent by Ryser's inclusion-exclusion formula (H. J. Ryser,
+ * Combinatorial Mathematics, 1963), a second and independent way to the same
+ * number: perm(a) = (-1)^n sum over column sets S of (-1)^|S| prod_r
+ * (number of columns of S that row r allows).  Every term is below
+ * n^n <= 20^20 < 2^87, so 128-bit signed sums are exact for n <= 20.
+ */
+int oqp_ryser(int n, const uint8_t* a, uint64_t* count) {
+    if (n < 1 || n > 20 || !a || !count) return OQ_EINVAL;
+    __int128 total = 0;
+    for (uint32_t s = 0; s < (1u << n); ++s) {
+        __int128 prod = 1;
+        int size = 0;
+        for (int c = 0; c < n; ++c) size += (s >> c) & 1u;
+        for (int r = 0; r < n && prod != 0; ++r) {
+            int in_s = 0;
+            for (int c = 0; c < n; ++c)
+                if (((s >> c) & 1u) && a[r * n + c]) ++in_s;
+            prod *= in_s;
+        }
+        total += ((n - size) % 2 == 0) ? prod : -prod;
+    }
+    if (total < 0) return OQ_ERANGE;          /* impossible for a 0/1 matrix */
+    *count = (uint64_t)total;
     return OQ_OK;
 }

@@ -12,6 +12,11 @@ With --slices N:k:len:count it instead writes oracle_slices.txt: the oracle's
 counts of `count` seeded slices of `len` entries of the (N, k) frontier (slice
 indices from seeded_inputs.sample_slices, plus the last, short slice), one line
 per slice: N k start len weighted_total node_total sha256(counts u64 LE).
+
+With --perm N:density[:seed] ... it writes perm_totals.txt: the permanent of
+the seeded 0/1 matrix (seeded_inputs.matrix01 with seed MATRIX_SEED + seed)
+by the oracle's Ryser routine, and for N <= 15 also by its search (both must
+agree): N density seed permanent.
 """
 import argparse
 import hashlib
@@ -40,6 +45,12 @@ NODES_HEADER = """# Node counts nodes(N, k) (queens placed in rows k..N-2 below 
 # the node identity nodes(k) = nodes(j) + F(k+1) + ... + F(j) for k < j (and the
 # same with the sign reversed for k > j), with F from the oracle's frontier.
 # N k nodes source
+"""
+PERM_OUT = os.path.join(HERE, "perm_totals.txt")
+PERM_HEADER = """# Permanents of seeded 0/1 matrices (seeded_inputs.matrix01(N, density,
+# MATRIX_SEED + seed)), written by tests/golden/make_golden.py --perm (oracle only:
+# Ryser's formula, and the oracle's search where it finishes).
+# N density seed permanent
 """
 HEADER = """# Oracle results per frontier, written by tests/golden/make_golden.py (oracle only).
 # N k F weighted_total node_total sha256(counts u64 LE) sha256(nodes u64 LE) oracle_seconds threads
@@ -108,14 +119,40 @@ def write_slices(spec, threads):
         f.writelines(lines)
 
 
+def write_perm(specs):
+    lines = []
+    if os.path.exists(PERM_OUT):
+        with open(PERM_OUT) as f:
+            lines = [ln for ln in f if ln.strip() and not ln.startswith("#")]
+    for spec in specs:
+        parts = spec.split(":")
+        n, dens = int(parts[0]), float(parts[1])
+        seed = int(parts[2]) if len(parts) > 2 else 0
+        a = np.array(seeded_inputs.matrix01(n, dens, seeded_inputs.MATRIX_SEED + seed), np.uint8)
+        value = oracle.permanent_ryser(a)
+        if n <= 15 and oracle.permanent(a)[0] != value:
+            raise SystemExit(f"oracle search and Ryser disagree for {spec}")
+        line = f"{n} {dens} {seed} {value}"
+        print(line, flush=True)
+        lines = [ln for ln in lines if ln.split()[:3] != line.split()[:3]] + [line + "\n"]
+    lines.sort(key=lambda ln: (int(ln.split()[0]), float(ln.split()[1]), int(ln.split()[2])))
+    with open(PERM_OUT, "w") as f:
+        f.write(PERM_HEADER)
+        f.writelines(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("cases", nargs="*")
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
     ap.add_argument("--slices", default=None, help="N:k:len:count")
+    ap.add_argument("--perm", nargs="+", default=None, help="N:density[:seed] ...")
     args = ap.parse_args()
     if args.slices:
         write_slices(args.slices, args.threads)
+        return
+    if args.perm:
+        write_perm(args.perm)
         return
     for case in args.cases:
         n, k = (int(x) for x in case.split(":"))

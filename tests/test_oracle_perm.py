@@ -2,7 +2,8 @@
 definition by enumeration of permutations, Ryser's inclusion-exclusion
 formula (H. J. Ryser, Combinatorial Mathematics, 1963), the all-ones matrix
 (n!), permutation matrices (1), the tridiagonal band (Fibonacci numbers), and
-the frontier totals and node identity.  No GPU."""
+the frontier totals and node identity.  The oracle's own Ryser routine (used
+for boards too large for its search) is pinned the same way.  No GPU."""
 import itertools
 import math
 
@@ -62,7 +63,11 @@ def test_permanent_matches_ryser(n):
 
 def test_special_matrices():
     for n in range(1, 10):
-        assert oracle.permanent(np.ones((n, n), np.uint8))[0] == math.factorial(n)
+        total, nodes = oracle.permanent(np.ones((n, n), np.uint8))
+        assert total == math.factorial(n)
+        # row j of the all-ones matrix is reached by n! / (n - j - 1)! placements;
+        # rows 0..n-3 are nodes
+        assert nodes == sum(math.perm(n, j + 1) for j in range(n - 2))
         assert oracle.permanent(np.eye(n, dtype=np.uint8))[0] == 1
         perm = np.eye(n, dtype=np.uint8)[np.roll(np.arange(n), 3 % n)]
         assert oracle.permanent(perm)[0] == 1
@@ -117,8 +122,8 @@ def test_frontier_totals_and_node_identity(n):
         counts, nodes = oracle.perm_count_prefixes(a, pre, threads=4)
         assert int(counts.sum()) == total, k
         # nodes from row 0 = placements in rows 0..k-1 (that are nodes, i.e.
-        # rows <= n-2) + nodes below every prefix
-        above = sum(sizes[j + 1] for j in range(min(k, n - 1)))
+        # rows <= n-3) + nodes below every prefix
+        above = sum(sizes[j + 1] for j in range(min(k, n - 2)))
         assert above + int(nodes.sum()) == nodes0, k
         assert len(pre) == sizes[k]
 
@@ -134,3 +139,40 @@ def test_prefix_columns_and_bad_arguments():
     a = np.ones((4, 4), np.uint8)
     a[1, 1] = 0
     assert oracle.perm_count_prefixes(a, bad)[0].tolist() == [0, 0, 0]
+
+
+def test_oracle_ryser_routine():
+    """oracle.permanent_ryser against the search, the formula retyped here in
+    Python, and the closed forms up to n = 20."""
+    for n in range(1, 13):
+        for seed, dens in ((300 + n, 0.5), (400 + n, 0.8)):
+            a = _matrix(n, dens, seed)
+            assert oracle.permanent_ryser(a) == oracle.permanent(a)[0], (n, seed)
+            if n <= 9:
+                assert oracle.permanent_ryser(a) == _ryser(a)
+    fib = [1, 1]
+    for _ in range(30):
+        fib.append(fib[-1] + fib[-2])
+    for n in (1, 5, 13, 17, 20):
+        assert oracle.permanent_ryser(np.ones((n, n), np.uint8)) == math.factorial(n)
+        assert oracle.permanent_ryser(np.eye(n, dtype=np.uint8)) == 1
+        band = np.array([[1 if abs(r - c) <= 1 else 0 for c in range(n)] for r in range(n)],
+                        np.uint8)
+        assert oracle.permanent_ryser(band) == fib[n]
+    with pytest.raises(oracle.OracleError):
+        oracle.permanent_ryser(np.ones((21, 21), np.uint8))
+
+
+def test_stored_permanents_are_the_oracles():
+    """tests/golden/perm_totals.txt (written by make_golden.py --perm): recomputed
+    by the Ryser routine up to n = 18, and by the search up to n = 15."""
+    from conftest import read_table
+    rows = read_table("perm_totals.txt")
+    assert {(int(r[0]), float(r[1])) for r in rows} >= {(20, 0.5), (20, 0.3)}
+    for n, dens, seed, value in ((int(r[0]), float(r[1]), int(r[2]), int(r[3])) for r in rows):
+        if n > 18:
+            continue
+        a = _matrix(n, dens, seed)
+        assert oracle.permanent_ryser(a) == value
+        if n <= 15:
+            assert oracle.permanent(a)[0] == value
