@@ -19,7 +19,8 @@ depth k-2 and expanded on the device (nq_expand) before the timed region.  Print
 form (one launch per row-0 column over the same frontier), the end-to-end
 nq_count wall time, the int-ALU roofline of the DFS kernel, the ragged
 256-instance batch (one graph replay), the kings search (a second DFS on the
-same engine, n = 16), one GPU's share of an N=21 count
+same engine, n = 16), the permanent of a seeded 20 x 20 0/1 matrix (a third
+DFS, with two-word frames), one GPU's share of an N=21 count
 dealt round-robin over 8 GPUs (all 8 shares run in turn; their totals must add
 up to Q(21)), the serving loop at a few request rates (p50/p99 latency,
 throughput) and the oracle timed on the host cores.
@@ -62,7 +63,7 @@ def golden_nodes(n, k):
     return None
 
 
-KERNEL_FILES = ("paper_2511_12009_amd/csrc/nq_dfs.hip", "paper_2511_12009_amd/csrc/nq_internal.h",
+KERNEL_FILES = ("paper_2511_12009_amd/csrc/nq_dfs.hip", "paper_2511_12009_amd/csrc/nq_kernel.h",
                 "paper_2511_12009_amd/build.py")
 
 
@@ -242,6 +243,55 @@ def bench_kings(nq, n=16):
         best = ms if best is None else min(best, ms)
     return {"n": n, "solutions": want, "kernel_ms": best, "solutions_per_s": want / (best / 1e3),
             "exact": True, "form": "kings search on the queens lane-stack engine (NQ_FLAG_KINGS)"}
+
+
+def perm_stored():
+    """Stored permanents of seeded 0/1 matrices (tests/golden/perm_totals.txt,
+    the oracle's Ryser routine): {(n, density, seed): permanent}."""
+    out = {}
+    with open(os.path.join(ROOT, "tests", "golden", "perm_totals.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if line:
+                out[(int(line[0]), float(line[1]), int(line[2]))] = int(line[3])
+    return out
+
+
+def bench_perm(nq, torch, n=20, density=0.5):
+    """The third search on the same engine: the permanent of the seeded n x n
+    0/1 matrix of the given density (two-word frames, two-row leaf rule), one
+    persistent launch over the host frontier resident on the device, at depths
+    6..8; kernel time from HIP events, nodes (placements in rows k..n-3) from
+    one node-counting launch per depth, the total checked against the stored
+    permanent."""
+    import seeded_inputs
+    a = np.array(seeded_inputs.matrix01(n, density), np.uint8)
+    want = perm_stored()[(n, density, 0)]
+    rows = []
+    for k in (6, 7, 8):
+        cols = nq.perm_frontier(a, k)
+        d = torch.from_numpy(np.ascontiguousarray(cols).view(np.int32)).cuda()
+        nodes = torch.empty(len(cols), dtype=torch.int64, device="cuda")
+        _, tot = nq.perm_count_subproblems(a, d, k, counts=False, nodes=nodes)
+        torch.cuda.synchronize()
+        if int(tot.item()) != want:
+            raise SystemExit(f"bench.py: permanent {int(tot.item())} != {want} (node run, k={k})")
+        below = int(nodes.sum().item())
+        best = None
+        for _ in range(3):
+            _, tot, ms = nq.perm_count_subproblems(a, d, k, counts=False, timing=True)
+            if int(tot.item()) != want:
+                raise SystemExit(f"bench.py: permanent {int(tot.item())} != {want} (k={k})")
+            best = ms if best is None else min(best, ms)
+        rows.append({"depth": k, "subproblems": len(cols), "kernel_ms": best, "nodes": below,
+                     "nodes_per_s": below / (best / 1e3)})
+        del d, nodes
+        torch.cuda.empty_cache()
+    top = min(rows, key=lambda r: r["kernel_ms"])
+    return {"n": n, "density": density, "permanent": want, "exact": True,
+            "best_depth": top["depth"], "kernel_ms": top["kernel_ms"],
+            "nodes_per_s": top["nodes_per_s"], "depths": rows,
+            "form": "permanent search on the lane-stack engine (8-byte frames, two-row leaf)"}
 
 
 def _serve_count_work(nq, torch, n, entries):
@@ -592,6 +642,8 @@ def main():
     ap.add_argument("--tune-ms", type=float, default=40000.0)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--serve-rates", default="25,100,200", help="COUNT requests/s, comma list")
+    ap.add_argument("--perm-only", action="store_true",
+                    help="only the permanent search (third DFS workload; one JSON line)")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
@@ -673,6 +725,9 @@ def main():
         if fin and total != known_counts().get(args.resumable, total):
             raise SystemExit(f"bench.py: Q({args.resumable}) = {total}, expected "
                              f"{known_counts()[args.resumable]}")
+        return
+    if args.perm_only:
+        print(json.dumps({"perm": bench_perm(nq, torch)}), flush=True)
         return
     if args.serving_only:
         rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
@@ -833,6 +888,8 @@ def main():
         out["batch"] = bench_batch(nq, known)
     print("[bench] kings search (second DFS workload)", file=sys.stderr, flush=True)
     out["kings"] = bench_kings(nq)
+    print("[bench] permanent search (third DFS workload)", file=sys.stderr, flush=True)
+    out["perm"] = bench_perm(nq, torch)
     if not args.no_shards:
         print("[bench] one GPU's share of N=21 over 8 GPUs", file=sys.stderr, flush=True)
         out["shard"] = bench_shards(nq, torch, known)

@@ -336,6 +336,14 @@ int nq_count_resumable_wide(uint32_t n, const nq_opts* opts, const char* path, u
  * same count (else NQ_EDEVICE).  The winner is written to *out and remembered
  * for this process and device: nq_count with opts->depth == 0 then uses its
  * depth and every launch field the caller left at 0.  n in [4, 28].
+ * Boards whose automatic count runs in chunks (n = 21, 22, 23: a whole count
+ * takes 9 s to 13 min) are tuned on one chunk instead: the middle chunk of
+ * the count's chunk plan (16 chunks for 21, 64 for 22 and 23) at every depth
+ * in [depth_lo, depth_hi] (0, 0 = the plan's depth - 1 .. + 1; at least 5)
+ * with the default launch shape, timed in wall-clock time (host frontier,
+ * device expansion, DFS, result); out->chunks = the plan's chunk count,
+ * out->count = that chunk's count (every depth must agree on it), and
+ * nq_count then runs its chunked count at the tuned depth.
  */
 typedef struct nq_tuned {
     uint32_t depth;          /* pre-placed rows                                  */
@@ -346,6 +354,10 @@ typedef struct nq_tuned {
     uint64_t count;          /* the count every trial agreed on                  */
     uint32_t claim;          /* entries per work-head claim (0 = size default)   */
     uint32_t wg_size;        /* threads per workgroup (0 = the default, 64)      */
+    uint32_t chunks;         /* 0 = one launch over the whole frontier; else the
+                                count runs in this many chunks of the depth-5
+                                frontier (n = 21..23)                           */
+    uint32_t reserved;       /* 0                                                */
 } nq_tuned;
 int nq_autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
                 nq_tuned* out);
@@ -358,9 +370,10 @@ int nq_autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_
  * search itself is not shortened).  NQ_EINVAL if trials or out_count is NULL.
  */
 typedef struct nq_tune_trial {
-    uint32_t depth, wg_size, waves_per_cu, refill_every, claim, reserved;
+    uint32_t depth, wg_size, waves_per_cu, refill_every, claim;
+    uint32_t chunks;         /* 0 = a whole count; else one chunk of this many */
     double ms;
-    uint64_t subproblems;
+    uint64_t subproblems;    /* entries searched (0 for a chunk trial)         */
 } nq_tune_trial;
 int nq_autotune_trials(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms,
                        nq_tuned* out, nq_tune_trial* trials, uint32_t capacity,
@@ -491,6 +504,48 @@ int nq_serve_submit(nq_server* server, const nq_request* req, uint64_t* out_tick
 int nq_serve_poll(nq_server* server, uint64_t ticket, nq_result* out);
 int nq_serve_wait(nq_server* server, uint64_t ticket, nq_result* out, uint64_t timeout_ns);
 int nq_serve_destroy(nq_server* server);
+
+/*
+ * The third search on the same engine: the permanent of an n x n 0/1 matrix,
+ * the number of permutations s with a[r][s(r)] = 1 for every row r, counted
+ * by a depth-first search over the rows (the paper's conclusion, Section 5,
+ * names combinatorial permutation problems among the searches its method
+ * carries over to).  It uses a two-word frame (used columns, untried columns
+ * of the row being filled) in the lane-interleaved LDS stack with 8-byte
+ * slots, and its own leaf rule: the last two rows are never entered, their
+ * completions are counted in closed form.  A node is one placement in rows
+ * depth..n-3.
+ *
+ * rows (host, n words): rows[r] = the columns row r allows (bit c = a[r][c]);
+ * bits at or above n are NQ_EINVAL.  n in [1, NQ_PERM_MAX_N] (20: the
+ * permanent is at most n!, below 2^64).
+ *
+ * nq_perm_frontier: every assignment of rows 0..depth-1 to distinct allowed
+ * columns, in lexicographic order of the columns, written as the set of used
+ * columns (cols[i]); depth in [0, n].  The size query and partial fill follow
+ * nq_frontier (NQ_ERANGE when capacity < F).  Host memory; thread-safe.
+ *
+ * nq_perm_count_subproblems: counts below `len` device-resident entries
+ * d_cols (used-column sets with exactly `depth` rows assigned; the launch's
+ * stack is sized for n - 3 - depth frames, and an entry that needs more is
+ * reported as UINT64_MAX in d_counts and left out of the total).  d_counts
+ * (nullable, uint64[len]) receives each entry's count, *d_total (nullable) is
+ * increased by their sum; opts: mode, wg_size, waves_per_cu, refill_every,
+ * claim, stream, kernel_ms_out, d_nodes (uint64[len]: nodes per entry);
+ * flags must be 0.  Asynchronous on opts->stream unless kernel_ms_out is set.
+ *
+ * nq_perm_count: the permanent.  Builds the frontier on the host at
+ * opts->depth (0 = the shallowest depth with at least 2^20 entries, at most
+ * n - 2 and 2^26 entries), copies it to the device and counts it;
+ * synchronous.  opts->flags, counts_out and d_nodes must be 0.
+ */
+#define NQ_PERM_MAX_N 20
+int nq_perm_frontier(uint32_t n, const uint32_t* rows, uint32_t depth, uint32_t* cols,
+                     uint64_t capacity, uint64_t* out_len);
+int nq_perm_count_subproblems(uint32_t n, const uint32_t* rows, const uint32_t* d_cols,
+                              uint64_t len, uint32_t depth, uint64_t* d_counts,
+                              unsigned long long* d_total, const nq_opts* opts);
+int nq_perm_count(uint32_t n, const uint32_t* rows, const nq_opts* opts, uint64_t* out_total);
 
 #ifdef __cplusplus
 }

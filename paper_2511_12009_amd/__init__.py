@@ -20,6 +20,8 @@ Functions (same names as the C entry points, without the ``nq_`` prefix):
   Server(...).submit_count / submit_slice / poll / wait -> continuous-batching serving
   count_resumable(n, path, ..., wide=False)  -> a count in chunks with a progress file
   ubench_valu / ubench_lds                   -> the microbenchmarks behind the roofline
+  perm_count / perm_frontier / perm_count_subproblems -> the third search: permanents of
+                                               0/1 matrices on the same engine
 """
 from ._native import (  # noqa: F401
     Batch,
@@ -39,6 +41,10 @@ from ._native import (  # noqa: F401
     tuned_lookup,
     lib,
     library_path,
+    perm_count,
+    perm_count_subproblems,
+    perm_frontier,
+    perm_rows,
     ubench_lds,
     ubench_valu,
 )

@@ -50,6 +50,8 @@ class NqTuned(ct.Structure):
         ("count", ct.c_uint64),
         ("claim", ct.c_uint32),
         ("wg_size", ct.c_uint32),
+        ("chunks", ct.c_uint32),
+        ("reserved", ct.c_uint32),
     ]
 
 
@@ -60,7 +62,7 @@ class NqTuneTrial(ct.Structure):
         ("waves_per_cu", ct.c_uint32),
         ("refill_every", ct.c_uint32),
         ("claim", ct.c_uint32),
-        ("reserved", ct.c_uint32),
+        ("chunks", ct.c_uint32),
         ("ms", ct.c_double),
         ("subproblems", ct.c_uint64),
     ]
@@ -162,6 +164,13 @@ def lib():
         L.nq_ubench_valu.restype = ct.c_int
         L.nq_ubench_lds.argtypes = [u32, u32, u32, u32, u32, u64, pd]
         L.nq_ubench_lds.restype = ct.c_int
+        L.nq_perm_frontier.argtypes = [u32, pu32, u32, pu32, u64, pu64]
+        L.nq_perm_frontier.restype = ct.c_int
+        L.nq_perm_count_subproblems.argtypes = [u32, pu32, vp, u64, u32, vp, vp,
+                                                ct.POINTER(NqOpts)]
+        L.nq_perm_count_subproblems.restype = ct.c_int
+        L.nq_perm_count.argtypes = [u32, pu32, ct.POINTER(NqOpts), pu64]
+        L.nq_perm_count.restype = ct.c_int
         _LIB = L
     return _LIB
 
@@ -335,6 +344,84 @@ def count_subproblems(n: int, cols, ld, rd, weight=None, counts=None, total=None
     return (counts, total, ms.value) if timing else (counts, total)
 
 
+def perm_rows(a):
+    """The rows of a 0/1 matrix (n x n, anything numpy reads) as the library
+    takes them: uint32[n], bit c of word r = a[r][c] != 0."""
+    m = np.asarray(a)
+    if m.ndim != 2 or m.shape[0] != m.shape[1] or not 1 <= m.shape[0] <= 32:
+        raise ValueError("the matrix must be n x n with 1 <= n <= 32")
+    bits = (m != 0).astype(np.uint64) << np.arange(m.shape[0], dtype=np.uint64)
+    return np.ascontiguousarray(bits.sum(axis=1).astype(np.uint32))
+
+
+def _rows_arg(a):
+    rows = perm_rows(a)
+    return rows, len(rows), rows.ctypes.data_as(ct.POINTER(ct.c_uint32))
+
+
+def perm_frontier(a, depth: int):
+    """Used-column sets (uint32[F], host) of every assignment of rows
+    0..depth-1 of the 0/1 matrix `a` (nq_perm_frontier), lexicographic."""
+    rows, n, rp = _rows_arg(a)
+    ln = ct.c_uint64()
+    _check(lib().nq_perm_frontier(n, rp, depth, None, 0, ct.byref(ln)), "nq_perm_frontier")
+    f = ln.value
+    cols = np.zeros(max(f, 1), np.uint32)
+    _check(lib().nq_perm_frontier(n, rp, depth, cols.ctypes.data_as(ct.POINTER(ct.c_uint32)),
+                                  f, ct.byref(ln)), "nq_perm_frontier")
+    return cols[:f]
+
+
+def perm_count(a, depth: int = 0, mode="persistent", wg_size: int = 0, waves_per_cu: int = 0,
+               refill_every: int = 0, claim: int = 0, timing: bool = False, stream=None):
+    """The permanent of the 0/1 matrix `a` (nq_perm_count); with timing=True
+    also the DFS kernel time in ms.  Synchronous."""
+    rows, n, rp = _rows_arg(a)
+    o = _opts(depth, mode, wg_size, waves_per_cu, refill_every,
+              stream if stream is None else _stream_handle(stream), 0, claim)
+    ms = ct.c_double(0.0)
+    if timing:
+        o.kernel_ms_out = ct.pointer(ms)
+    total = ct.c_uint64()
+    _check(lib().nq_perm_count(n, rp, ct.byref(o), ct.byref(total)), "nq_perm_count")
+    return (total.value, ms.value) if timing else total.value
+
+
+def perm_count_subproblems(a, cols, depth: int, counts=None, total=None, nodes=None,
+                           mode="persistent", wg_size: int = 0, waves_per_cu: int = 0,
+                           refill_every: int = 0, claim: int = 0, stream=None,
+                           timing: bool = False):
+    """Counts below device-resident used-column sets `cols` (int32 CUDA tensor;
+    every entry has `depth` rows assigned) of the matrix `a`
+    (nq_perm_count_subproblems).  ``counts`` (int64[F]) and ``total``
+    (int64[1], accumulated) are allocated when not given; ``counts=False``
+    requests none; ``nodes`` (int64[F]) receives the nodes of every entry.
+    Returns (counts, total) or (counts, total, kernel_ms)."""
+    import torch
+    rows, n, rp = _rows_arg(a)
+    length = cols.numel()
+    if not cols.is_cuda or cols.dtype != torch.int32 or not cols.is_contiguous():
+        raise ValueError("cols must be a contiguous int32 CUDA tensor")
+    if counts is None:
+        counts = torch.empty(length, dtype=torch.int64, device=cols.device)
+    if total is None:
+        total = torch.zeros(1, dtype=torch.int64, device=cols.device)
+    o = _opts(depth, mode, wg_size, waves_per_cu, refill_every, _stream_handle(stream), 0, claim)
+    if nodes is not None:
+        if nodes.dtype != torch.int64 or nodes.numel() != length or not nodes.is_cuda:
+            raise ValueError("nodes must be an int64 CUDA tensor of the same length")
+        o.d_nodes = nodes.data_ptr()
+    ms = ct.c_double(0.0)
+    if timing:
+        o.kernel_ms_out = ct.pointer(ms)
+    _check(lib().nq_perm_count_subproblems(
+        n, rp, cols.data_ptr(), length, depth,
+        None if counts is False else counts.data_ptr(),
+        None if total is False else total.data_ptr(), ct.byref(o)),
+        "nq_perm_count_subproblems")
+    return (counts, total, ms.value) if timing else (counts, total)
+
+
 def count_resumable(n: int, path: str, chunks: int = 0, max_chunks: int = 0, depth: int = 0,
                     mode="persistent", waves_per_cu: int = 0, refill_every: int = 0,
                     claim: int = 0, wide: bool = False):
@@ -356,7 +443,7 @@ def count_resumable(n: int, path: str, chunks: int = 0, max_chunks: int = 0, dep
 
 def set_loop_form(form: int) -> int:
     """nq_set_loop_form: the DFS inner-loop form of launches planned from now on
-    (-1 = default; 0, 1, 2, 4 or 5); returns the form that was in use."""
+    (-1 = default; 0 to 5); returns the form that was in use."""
     prev = ct.c_int(0)
     _check(lib().nq_set_loop_form(int(form), ct.byref(prev)), "nq_set_loop_form")
     return prev.value
@@ -441,14 +528,15 @@ class Batch:
 def _tuned(t) -> dict:
     return {"depth": t.depth, "wg_size": t.wg_size, "waves_per_cu": t.waves_per_cu,
             "refill_every": t.refill_every, "claim": t.claim, "trials": t.trials, "ms": t.ms,
-            "count": t.count}
+            "count": t.count, "chunks": t.chunks}
 
 
 def autotune(n: int, depth_lo: int = 0, depth_hi: int = 0, budget_ms: float = 0.0,
              table: bool = False) -> dict:
     """Measured best depth / workgroup size / waves per CU / visit interval /
-    claim block for n (nq_autotune); table=True adds every trial
-    (nq_autotune_trials) under "table"."""
+    claim block for n (nq_autotune; for n = 21..23 the depth of the chunked
+    count, "chunks" > 0); table=True adds every trial (nq_autotune_trials)
+    under "table"."""
     t = NqTuned()
     if not table:
         _check(lib().nq_autotune(n, depth_lo, depth_hi, budget_ms, ct.byref(t)), "nq_autotune")
@@ -460,8 +548,8 @@ def autotune(n: int, depth_lo: int = 0, depth_hi: int = 0, budget_ms: float = 0.
                                     ct.byref(cnt)), "nq_autotune_trials")
     out = _tuned(t)
     out["table"] = [{"depth": r.depth, "wg_size": r.wg_size, "waves_per_cu": r.waves_per_cu,
-                     "refill_every": r.refill_every, "claim": r.claim, "ms": r.ms,
-                     "subproblems": r.subproblems} for r in rows[:cnt.value]]
+                     "refill_every": r.refill_every, "claim": r.claim, "chunks": r.chunks,
+                     "ms": r.ms, "subproblems": r.subproblems} for r in rows[:cnt.value]]
     return out
 
 

@@ -26,7 +26,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           f"--offload-arch={ARCH}", "-I", os.path.join(os.path.dirname(HERE), "include")]
 
 SOURCES = ["nq_frontier.cpp", "nq_dfs.hip", "nq_expand.hip", "nq_api.cpp", "nq_batch.cpp", "nq_tune.cpp",
-           "nq_serve.cpp", "nq_noalloc.hip", "nq_ubench.hip"]
+           "nq_serve.cpp", "nq_noalloc.hip", "nq_ubench.hip", "nq_perm.hip"]
 
 
 def _run(cmd, verbose):

@@ -29,6 +29,21 @@ constexpr uint32_t kMaxKingsN = 21;
 
 void set_hip_error(int err) { g_last_hip_error = err; }
 
+// Boards whose automatic count runs in chunks, with the depth and chunk count
+// measured best (nq_autotune re-measures the depth for the device at hand):
+// N = 21 at depth 10 in 16 chunks (8.86 s against 9.0 s for the whole depth-9
+// frontier), N = 22 at depth 11 in 64 chunks (79.9 s against 86.4 s), N = 23
+// at depth 11 in 64 chunks (753 s; depth 11 beat 9 and 10 on the same chunk).
+namespace {
+constexpr ChunkPlan kChunkPlans[] = {{21, 10, 16}, {22, 11, 64}, {23, 11, 64}};
+}  // namespace
+
+const ChunkPlan* chunk_plan(uint32_t n) {
+    for (const ChunkPlan& p : kChunkPlans)
+        if (p.n == n) return &p;
+    return nullptr;
+}
+
 namespace {
 
 #define NQ_HIP(call)                                       \
@@ -115,20 +130,6 @@ uint32_t auto_depth(uint32_t n) {
         }
     }
     return std::max<uint32_t>(1, k);
-}
-
-// Boards whose automatic count runs in chunks, with the depth and chunk count
-// measured best: N = 21 at depth 10 in 16 chunks (8.86 s against 9.0 s for the
-// whole depth-9 frontier), N = 22 at depth 11 in 64 chunks (79.9 s against
-// 86.4 s), N = 23 at depth 11 in 64 chunks (753 s; depth 11 beat 9 and 10 on
-// the same chunk).
-struct ChunkPlan { uint32_t n, depth, chunks; };
-constexpr ChunkPlan kChunkPlans[] = {{21, 10, 16}, {22, 11, 64}, {23, 11, 64}};
-
-const ChunkPlan* chunk_plan(uint32_t n) {
-    for (const ChunkPlan& p : kChunkPlans)
-        if (p.n == n) return &p;
-    return nullptr;
 }
 
 // The kings search's automatic depth: the shallowest whose host frontier has
@@ -403,6 +404,29 @@ int count_chunks(uint32_t n, const nq_opts& local, uint32_t depth, uint32_t host
     return NQ_OK;
 }
 
+int time_chunk(uint32_t n, uint32_t depth, uint32_t chunks, uint32_t index, const nq_opts& opts,
+               double* ms, unsigned __int128* total) {
+    if (n > NQ_MAX_N || chunks == 0 || index >= chunks || depth < kChunkHostDepth || depth > n)
+        return NQ_EINVAL;
+    nq_opts local = opts;
+    local.depth = depth;
+    local.counts_out = nullptr;
+    local.d_nodes = nullptr;
+    local.kernel_ms_out = nullptr;
+    unsigned __int128 got = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = count_chunks(n, local, depth, kChunkHostDepth, chunks, index, 1, nullptr,
+                                [&](uint32_t, unsigned __int128 part) {
+                                    got = part;
+                                    return (int)NQ_OK;
+                                });
+    const auto t1 = std::chrono::steady_clock::now();
+    if (rc != NQ_OK) return rc;
+    *ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    *total = got;
+    return NQ_OK;
+}
+
 }  // namespace nqi
 
 using namespace nqi;
@@ -484,10 +508,12 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
     const bool kings = (local.flags & NQ_FLAG_KINGS) != 0;
     // the number of king placements passes 2^64 at n = 22 (about n! / e^2)
     if (kings && n > kMaxKingsN) return NQ_EINVAL;
+    uint32_t tuned_chunks = 0;                        // the tuner chose a chunked count
     if (local.depth == 0 && !kings) {
         nq_tuned t;
         if (tune_lookup(n, &t) == NQ_OK) {
             local.depth = t.depth;
+            tuned_chunks = t.chunks;
             if (!local.wg_size) local.wg_size = t.wg_size;
             if (!local.waves_per_cu) local.waves_per_cu = t.waves_per_cu;
             if (!local.refill_every) local.refill_every = t.refill_every;
@@ -498,16 +524,20 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
     const uint32_t depth = local.depth ? local.depth : kings ? kings_auto_depth(n) : auto_depth(n);
     if (depth > n) return NQ_EINVAL;
     const ChunkPlan* plan = chunk_plan(n);
-    if (auto_pick && !kings && plan && !local.counts_out && opt_mode(opts) == NQ_MODE_PERSISTENT) {
+    if (!kings && ((auto_pick && plan) || tuned_chunks) && !local.counts_out &&
+        opt_mode(opts) == NQ_MODE_PERSISTENT) {
         // A whole frontier deep enough for these boards does not fit in device
-        // memory; chunks of the depth-5 frontier deepened to plan->depth do
-        // (as nq_count_resumable, without a progress file).
+        // memory; chunks of the depth-5 frontier deepened to the plan's (or the
+        // tuner's) depth do (as nq_count_resumable, without a progress file).
+        const uint32_t depth_c = tuned_chunks ? depth : plan->depth;
+        const uint32_t chunks_c = tuned_chunks ? tuned_chunks : plan->chunks;
+        if (depth_c < kChunkHostDepth) return NQ_EINVAL;
         try {
             TraceRange whole("nq_count (chunked)");
             uint64_t total = 0;
             double ms = 0.0;
-            local.depth = plan->depth;
-            int rc = count_chunks(n, local, plan->depth, 5, plan->chunks, 0, 0,
+            local.depth = depth_c;
+            int rc = count_chunks(n, local, depth_c, kChunkHostDepth, chunks_c, 0, 0,
                                   opts_in && opts_in->kernel_ms_out ? &ms : nullptr,
                                   [&](uint32_t, unsigned __int128 part) {
                                       total += (uint64_t)part;    // Q(n <= 23) < 2^64
@@ -590,7 +620,7 @@ extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total)
 
 namespace {
 
-constexpr uint32_t kResumeHostDepth = 5;   // chunks are ranges of this host frontier
+constexpr uint32_t kResumeHostDepth = kChunkHostDepth;   // chunks are ranges of this host frontier
 constexpr uint32_t kResumeChunks = 64;
 
 struct Progress {

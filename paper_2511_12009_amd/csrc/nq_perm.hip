@@ -1,0 +1,466 @@
+// Third search on the lane-stack engine: the permanent of a 0/1 matrix,
+// i.e. the number of permutations s of 0..n-1 with a[r][s(r)] = 1 for every
+// row r, counted by a depth-first search over the rows.
+//
+// The paper's conclusion names combinatorial permutation problems among the
+// searches its method carries over to (many subproblems, an iterative form
+// with a stack, frames of more than one word).  This search differs from the
+// queens in the two places that the conclusion leaves open:
+//   * the frame is two words, (used columns, untried columns of the row being
+//     filled), 8 bytes: the stack is the same lane-interleaved LDS layout with
+//     an 8-byte slot, frame f of lane l of wave w at
+//     ((w * (frames + 1) + f) * 64 + l) * 8, so a wave-wide ds_write_b64 /
+//     ds_read_b64 touches 512 consecutive bytes whatever the lanes' depths;
+//   * the leaf rule: the last two rows are never entered.  When the row about
+//     to be filled is row n - 2, two columns x, y are left, and the lane adds
+//     the completions in closed form, [a(n-2, x) a(n-1, y)] + [a(n-2, y)
+//     a(n-1, x)] (0, 1 or 2), where the queens' last-row step adds one when
+//     the last row has a free square.
+// The next row's allowed columns depend on the row, which differs from lane
+// to lane: the matrix's rows sit in LDS and a lane reads the word of its row
+// (the row is the popcount of the used columns).
+//
+// Scheduling is the queens kernel's protocol: plain launches take one entry
+// per lane; persistent launches keep a resident grid whose waves visit a
+// scheduler every `refill_every` steps (or once `idle_min` lanes are idle),
+// retire finished lanes, and hand idle lanes entries by rank from a block
+// claimed with one atomic add on a global head.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "nq_internal.h"
+#include "nq_trace.h"
+
+namespace nqi {
+
+namespace {
+
+constexpr uint32_t kPermParked = 0xffffffffu;     // sentinel: all columns used, nothing untried
+constexpr uint32_t kPermFrameBytes = 8;
+
+struct PermParams {
+    const uint32_t* cols;        // used columns of each entry (device)
+    uint64_t* counts;            // nullable: count per entry
+    unsigned long long* total;   // nullable: accumulated total
+    uint64_t* nodes;             // stats kernels: DFS steps per entry
+    unsigned long long* head;    // persistent kernels: next unclaimed entry
+    uint64_t len;
+    uint32_t n;
+    uint32_t frames;             // LDS frames per lane
+    uint32_t refill_every;
+    uint32_t idle_min;
+    uint32_t claim;
+    uint32_t rows[32];           // row r's allowed columns (bit c)
+};
+
+__device__ __forceinline__ uint32_t perm_lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t perm_shfl_u64(uint64_t v, int src) {
+    const uint32_t lo = __shfl((int)(uint32_t)v, src, 64);
+    const uint32_t hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// A frame: (used columns, untried columns), one 8-byte LDS slot.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) u32x2 lds_frame2;
+
+__device__ __forceinline__ lds_frame2* frame2_at(uint32_t addr) {
+    return (lds_frame2*)(uintptr_t)addr;
+}
+
+// Completions of the last two rows when `left` holds the two unused columns
+// and ra, rb are the allowed columns of rows n-2 and n-1.
+__device__ __forceinline__ uint32_t two_rows(uint32_t left, uint32_t ra, uint32_t rb) {
+    const uint32_t x = left & (0u - left), y = left ^ x;
+    return (uint32_t)(((ra & x) != 0u) & ((rb & y) != 0u)) +
+           (uint32_t)(((ra & y) != 0u) & ((rb & x) != 0u));
+}
+
+template <bool PERSISTENT, bool STATS>
+__global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
+    extern __shared__ u32x2 perm_stack[];
+    __shared__ uint32_t mrows[32];
+    if (threadIdx.x < 32) mrows[threadIdx.x] = threadIdx.x < P.n ? P.rows[threadIdx.x] : 0u;
+    __syncthreads();
+    const uint32_t lds = (uint32_t)(uintptr_t)(lds_frame2*)perm_stack;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t floor = lds + ((wave * (P.frames + 1u)) * 64u + lane) * kPermFrameBytes;
+    const uint32_t stride = 64u * kPermFrameBytes;
+    const uint32_t n = P.n;
+    const uint32_t board = (n >= 32u) ? 0xffffffffu : ((1u << n) - 1u);
+    // the last two rows' allowed columns (wave-uniform)
+    const uint32_t ra = n >= 2u ? mrows[n - 2u] : 0u, rb = mrows[(n - 1u) & 31u];
+    uint32_t top = floor;
+    *frame2_at(floor) = u32x2{kPermParked, 0u};
+
+    uint32_t c = kPermParked, v = 0u;
+    uint64_t idx = 0, sum = 0, steps = 0, wtotal = 0;
+    bool has_task = false;
+    bool exhausted = !PERSISTENT;
+    bool claimed_all = false;
+    uint64_t qlo = 0, qhi = 0;
+
+    // Takes entry i: its used columns, the sentinel, and the cases that need
+    // no search (at most two rows left, or a row with no allowed column).
+    auto take = [&](uint64_t i) {
+        idx = i;
+        has_task = true;
+        top = floor;
+        sum = 0;
+        steps = 0;
+        *frame2_at(floor) = u32x2{kPermParked, 0u};
+        c = P.cols[i] & board;
+        v = 0u;
+        const uint32_t placed = __popc(c);
+        if (placed >= n) {
+            sum = 1;                                   // a complete permutation
+        } else if (placed + 1u == n) {
+            sum = __popc(rb & ~c & board);             // the last row
+        } else if (placed + 2u == n) {
+            sum = two_rows(~c & board, ra, rb);        // the last two rows
+        } else if (n - 3u - placed > P.frames) {
+            sum = kCountInvalid;                       // does not fit this launch's stack
+        } else {
+            v = mrows[placed] & ~c & board;
+        }
+        if (v == 0u) c = kPermParked;
+    };
+
+    if (!PERSISTENT) {
+        const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (i < P.len) take(i);
+    }
+
+    for (;;) {
+        // ---- scheduler visit: retire finished lanes, refill idle ones.
+        if (has_task && v == 0u) {
+            if (P.counts) P.counts[idx] = sum;
+            if (STATS) P.nodes[idx] = steps;
+            if (sum != kCountInvalid) wtotal += sum;
+            has_task = false;
+        }
+        if (PERSISTENT && !exhausted) {
+            const uint64_t idle = __ballot(!has_task);
+            if (idle != 0) {
+                const uint32_t want = (uint32_t)__popcll(idle);
+                const uint64_t have = qhi - qlo;
+                uint64_t nlo = 0, nhi = 0;
+                if (have < want && !claimed_all) {
+                    const uint64_t grab = max((uint64_t)(want - have), (uint64_t)P.claim);
+                    const int leader = __ffsll((unsigned long long)idle) - 1;
+                    uint64_t first = 0;
+                    if ((int)lane == leader) first = atomicAdd(P.head, (unsigned long long)grab);
+                    first = perm_shfl_u64(first, leader);
+                    nlo = min(first, P.len);
+                    nhi = min(first + grab, P.len);
+                    if (first + grab >= P.len) claimed_all = true;
+                }
+                if (!has_task) {
+                    const uint64_t rk = perm_lane_rank(idle);
+                    if (rk < have) take(qlo + rk);
+                    else if (nlo + (rk - have) < nhi) take(nlo + (rk - have));
+                }
+                if (want <= have) {
+                    qlo += want;
+                } else {
+                    qlo = min(nlo + (want - have), nhi);
+                    qhi = nhi;
+                }
+                if (claimed_all && qlo >= qhi) exhausted = true;
+            }
+        }
+        if (!__any(v != 0u)) {
+            if (exhausted && !__any(has_task)) break;
+            continue;
+        }
+        // ---- DFS steps: place the lowest untried column of the current row.
+        // A parked lane (sentinel popped) has every column used and nothing
+        // untried: p = 0, its "next row" is 32 (read as row 0: nothing allowed
+        // that is unused), no leaf, no descent, and its pops read the sentinel
+        // again (top stays at floor).
+        for (uint32_t it = 0; it < P.refill_every; it += 32u) {
+            for (int s = 0; s < 32; ++s) {
+                const uint32_t p = v & (0u - v);
+                v ^= p;
+                const uint32_t nc = c | p;
+                const uint32_t row = __popc(nc);       // the row to fill next
+                const uint32_t left = ~nc & board;     // unused columns
+                const uint32_t a = mrows[row & 31u] & left;
+                const bool leaf = row + 2u == n;       // the last two rows are left
+                if (STATS) steps += (p != 0u) ? 1u : 0u;
+                if (leaf && p != 0u) sum += two_rows(left, ra, rb);
+                const bool desc = a != 0u && !leaf;
+                if (desc && v != 0u) {                 // keep the frame if it has work
+                    top += stride;
+                    *frame2_at(top) = u32x2{c, v};
+                }
+                c = desc ? nc : c;
+                v = desc ? a : v;
+                if (v == 0u) {                         // exhausted: pop
+                    const u32x2 f = *frame2_at(top);
+                    c = f.x;
+                    v = f.y;
+                    // unsigned addresses: never step below the sentinel
+                    top = (top > floor) ? top - stride : floor;
+                }
+            }
+            const uint64_t idle = __ballot(v == 0u);
+            const uint32_t lanes = (uint32_t)__popcll(__ballot(true));
+            const uint32_t nidle = (uint32_t)__popcll(idle);
+            if (nidle == lanes || (PERSISTENT && !exhausted && nidle >= P.idle_min)) break;
+        }
+    }
+    if (P.total) {
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t lo = __shfl_xor((int)(uint32_t)wtotal, off, 64);
+            const uint32_t hi = __shfl_xor((int)(uint32_t)(wtotal >> 32), off, 64);
+            wtotal += ((uint64_t)hi << 32) | lo;
+        }
+        if (lane == 0 && wtotal != 0) atomicAdd(P.total, (unsigned long long)wtotal);
+    }
+}
+
+const void* perm_kernel(bool persistent, bool stats) {
+    if (persistent)
+        return stats ? reinterpret_cast<const void*>(&nq_perm_kernel<true, true>)
+                     : reinterpret_cast<const void*>(&nq_perm_kernel<true, false>);
+    return stats ? reinterpret_cast<const void*>(&nq_perm_kernel<false, true>)
+                 : reinterpret_cast<const void*>(&nq_perm_kernel<false, false>);
+}
+
+// Rows of an n x n matrix: every bit is a column of the board.
+bool rows_ok(uint32_t n, const uint32_t* rows) {
+    if (n < 1 || n > NQ_PERM_MAX_N || !rows) return false;
+    const uint32_t board = (1u << n) - 1u;
+    for (uint32_t r = 0; r < n; ++r)
+        if (rows[r] & ~board) return false;
+    return true;
+}
+
+// Depth-first enumeration of the prefixes of length `depth`, lexicographic
+// (row 0's column ascending, then row 1's, ...).
+struct PermFrontier {
+    uint32_t n, depth;
+    const uint32_t* rows;
+    uint32_t* out;
+    uint64_t cap, len;
+    void walk(uint32_t row, uint32_t used) {
+        if (row == depth) {
+            if (out && len < cap) out[len] = used;
+            ++len;
+            return;
+        }
+        uint32_t a = rows[row] & ~used;
+        while (a) {
+            const uint32_t p = a & (0u - a);
+            a ^= p;
+            walk(row + 1, used | p);
+        }
+    }
+};
+
+// The automatic depth: the shallowest with at least 2^20 entries, at most
+// n - 2 and with at most 2^26 entries (the frontier is built on the host).
+uint32_t perm_auto_depth(uint32_t n, const uint32_t* rows) {
+    if (n <= 2) return n;
+    uint32_t best = 1;
+    for (uint32_t d = 1; d + 2 <= n; ++d) {
+        PermFrontier f{n, d, rows, nullptr, 0, 0};
+        f.walk(0, 0u);
+        if (f.len > (1ull << 26)) break;
+        best = d;
+        if (f.len >= (1ull << 20)) break;
+    }
+    return best;
+}
+
+int perm_run(uint32_t n, const uint32_t* rows, const uint32_t* d_cols, uint64_t len,
+             uint32_t depth, uint64_t* d_counts, unsigned long long* d_total,
+             const nq_opts* opts) {
+    if (len == 0) {
+        if (opts && opts->kernel_ms_out) *opts->kernel_ms_out = 0.0;
+        return NQ_OK;
+    }
+    const uint32_t mode = (opts && opts->mode) ? opts->mode : (uint32_t)NQ_MODE_PERSISTENT;
+    if (mode != NQ_MODE_PLAIN && mode != NQ_MODE_PERSISTENT) return NQ_EINVAL;
+    DeviceInfo dev;
+    int rc = device_info(&dev);
+    if (rc != NQ_OK) return rc;
+    // frames for rows depth..n-4 (the current frame is in registers and the
+    // last two rows are never entered)
+    const uint32_t frames = std::max<uint32_t>(1, n >= depth + 3u ? n - 3u - depth : 0u);
+    uint32_t wg = opts && opts->wg_size ? opts->wg_size : 64u;
+    if (wg % 64u != 0 || wg > 1024u) return NQ_EINVAL;
+    const uint64_t lds = (uint64_t)wg * (frames + 1u) * kPermFrameBytes;
+    if (lds + 32u * 4u > (uint64_t)dev.lds_per_block) return NQ_EINVAL;   // + the matrix
+    const bool stats = opts && opts->d_nodes;
+    const void* fn = perm_kernel(mode == NQ_MODE_PERSISTENT, stats);
+    uint32_t grid = 0;
+    if (mode == NQ_MODE_PLAIN) {
+        const uint64_t g = (len + wg - 1) / wg;
+        if (g > 0x7fffffffull) return NQ_EINVAL;
+        grid = (uint32_t)g;
+    } else {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)wg,
+                                                                    (size_t)lds);
+        if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
+        if (per_cu < 1) return NQ_EINVAL;
+        if (opts && opts->waves_per_cu)
+            per_cu = std::min(per_cu, (int)std::max(1u, opts->waves_per_cu / (wg / 64u)));
+        grid = (uint32_t)per_cu * (uint32_t)dev.cu_count;
+    }
+    PermParams P{};
+    P.cols = d_cols;
+    P.counts = d_counts;
+    P.total = d_total;
+    P.nodes = stats ? opts->d_nodes : nullptr;
+    P.len = len;
+    P.n = n;
+    P.frames = frames;
+    P.refill_every = (opts && opts->refill_every) ? opts->refill_every : 512u;
+    P.idle_min = default_idle_min();
+    {
+        const uint64_t waves = (uint64_t)grid * (wg / 64u);
+        P.claim = (opts && opts->claim) ? opts->claim
+                                        : (uint32_t)std::min<uint64_t>(256, len / (waves * 16));
+    }
+    for (uint32_t r = 0; r < n; ++r) P.rows[r] = rows[r];
+    hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
+    hipError_t e;
+    unsigned long long* head = nullptr;
+    if (mode == NQ_MODE_PERSISTENT) {
+        if ((e = hipMallocAsync((void**)&head, 8, s)) != hipSuccess) {
+            set_hip_error(e);
+            return NQ_EDEVICE;
+        }
+        rc = launch_zero_u64(head, 1, s);
+    }
+    P.head = head;
+    hipEvent_t a = nullptr, b = nullptr;
+    const bool timed = opts && opts->kernel_ms_out;
+    if (rc == NQ_OK && timed) {
+        if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess ||
+            (e = hipEventRecord(a, s)) != hipSuccess) {
+            set_hip_error(e);
+            rc = NQ_EDEVICE;
+        }
+    }
+    if (rc == NQ_OK) {
+        void* args[] = {&P};
+        e = hipLaunchKernel(fn, dim3(grid), dim3(wg), args, (size_t)lds, s);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e != hipSuccess) { set_hip_error(e); rc = NQ_EDEVICE; }
+    }
+    if (rc == NQ_OK && timed) {
+        float f = 0.f;
+        if ((e = hipEventRecord(b, s)) != hipSuccess || (e = hipEventSynchronize(b)) != hipSuccess ||
+            (e = hipEventElapsedTime(&f, a, b)) != hipSuccess) {
+            set_hip_error(e);
+            rc = NQ_EDEVICE;
+        } else {
+            *opts->kernel_ms_out = f;
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (head) {
+        e = hipFreeAsync(head, s);
+        if (e != hipSuccess && rc == NQ_OK) { set_hip_error(e); rc = NQ_EDEVICE; }
+    }
+    return rc;
+}
+
+}  // namespace
+
+}  // namespace nqi
+
+using namespace nqi;
+
+extern "C" int nq_perm_frontier(uint32_t n, const uint32_t* rows, uint32_t depth, uint32_t* cols,
+                                uint64_t capacity, uint64_t* out_len) {
+    if (!rows_ok(n, rows) || depth > n || !out_len) return NQ_EINVAL;
+    try {
+        const bool fill = cols != nullptr && capacity != 0;   // else a size query
+        PermFrontier f{n, depth, rows, fill ? cols : nullptr, fill ? capacity : 0, 0};
+        f.walk(0, 0u);
+        *out_len = f.len;
+        return (fill && f.len > capacity) ? NQ_ERANGE : NQ_OK;
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
+}
+
+extern "C" int nq_perm_count_subproblems(uint32_t n, const uint32_t* rows, const uint32_t* d_cols,
+                                         uint64_t len, uint32_t depth, uint64_t* d_counts,
+                                         unsigned long long* d_total, const nq_opts* opts) {
+    if (!rows_ok(n, rows) || depth > n || (len > 0 && !d_cols)) return NQ_EINVAL;
+    if (opts && opts->flags != 0) return NQ_EINVAL;
+    try {
+        TraceRange t("perm dfs");
+        return perm_run(n, rows, d_cols, len, depth, d_counts, d_total, opts);
+    } catch (...) {
+        return NQ_ENOMEM;
+    }
+}
+
+extern "C" int nq_perm_count(uint32_t n, const uint32_t* rows, const nq_opts* opts,
+                             uint64_t* out_total) {
+    if (!rows_ok(n, rows) || !out_total) return NQ_EINVAL;
+    if (opts && (opts->flags != 0 || opts->counts_out || opts->d_nodes)) return NQ_EINVAL;
+    const uint32_t depth = (opts && opts->depth) ? opts->depth : perm_auto_depth(n, rows);
+    if (depth > n) return NQ_EINVAL;
+    try {
+        TraceRange whole("nq_perm_count");
+        PermFrontier f{n, depth, rows, nullptr, 0, 0};
+        f.walk(0, 0u);
+        std::vector<uint32_t> h(f.len);
+        f.out = h.data();
+        f.cap = f.len;
+        f.len = 0;
+        f.walk(0, 0u);
+        hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
+        uint32_t* d_cols = nullptr;
+        unsigned long long* d_total = nullptr;
+        hipError_t e;
+        const size_t bytes = ((h.size() * 4 + 255) / 256) * 256 + 256;
+        if ((e = hipMalloc((void**)&d_cols, bytes)) != hipSuccess) {
+            set_hip_error(e);
+            return e == hipErrorOutOfMemory ? NQ_ENOMEM : NQ_EDEVICE;
+        }
+        d_total = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(d_cols) + bytes - 256);
+        int rc = NQ_OK;
+        if (!h.empty() && (e = hipMemcpyAsync(d_cols, h.data(), h.size() * 4,
+                                              hipMemcpyHostToDevice, s)) != hipSuccess) {
+            set_hip_error(e);
+            rc = NQ_EDEVICE;
+        }
+        if (rc == NQ_OK) rc = launch_zero_u64(d_total, 1, s);
+        if (rc == NQ_OK) rc = perm_run(n, rows, d_cols, h.size(), depth, nullptr, d_total, opts);
+        unsigned long long t = 0;
+        if (rc == NQ_OK) {
+            if ((e = hipMemcpyAsync(&t, d_total, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess) {
+                set_hip_error(e);
+                rc = NQ_EDEVICE;
+            }
+        }
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(d_cols);
+        if (rc != NQ_OK) return rc;
+        *out_total = t;
+        return NQ_OK;
+    } catch (const std::bad_alloc&) {
+        return NQ_ENOMEM;
+    } catch (...) {
+        return NQ_EINVAL;
+    }
+}

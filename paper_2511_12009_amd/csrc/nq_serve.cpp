@@ -113,11 +113,17 @@ struct nq_server {
     hipStream_t aux = nullptr;              // resident frontier builds
     std::map<std::tuple<uint32_t, uint32_t, uint32_t>, Resident> resident;   // (n, depth, kind)
 
-    // scheduling state (guarded by mu)
+    // Request state shared with the callers' threads (guarded by mu).
     std::mutex mu;
     std::condition_variable cv;
     std::deque<uint64_t> pending;
     std::unordered_map<uint64_t, Req> reqs;
+    bool stop = false;
+    int fatal = NQ_OK;
+    int fatal_hip = 0;            // hipError_t behind `fatal`, handed to the caller's thread
+
+    // Device-side bookkeeping, touched by the scheduler thread only (so the
+    // HIP calls that enqueue an epoch run without mu held).
     struct Admit {                          // a request on the device, in ring order
         uint64_t ticket, ring_start, ring_len;
         uint32_t slot, gen;
@@ -130,9 +136,6 @@ struct nq_server {
     uint64_t ring_head = 0, ring_tail = 0;  // logical positions, tail - head in use
     uint64_t epoch_no = 0;
     std::deque<Epoch> epochs;
-    bool stop = false;
-    int fatal = NQ_OK;
-    int fatal_hip = 0;            // hipError_t behind `fatal`, handed to the caller's thread
     std::thread worker;
 };
 
@@ -213,17 +216,39 @@ void ring_segments(const nq_server* s, uint64_t pos, uint64_t len, CopyFn&& fn) 
     }
 }
 
-// Collects finished requests and frees their slots and ring space.  mu held.
+// A pending request handed to the scheduler thread (copied out under mu).
+struct Candidate {
+    uint64_t ticket;
+    nq_request rq;
+    uint32_t depth;
+};
+
+// What admission decided for a candidate, applied to its Req under mu.
+struct Outcome {
+    uint64_t ticket;
+    int status;                 // NQ_OK, or the error the request ends with
+    bool admitted;              // on the device (else finished now with `count`)
+    uint64_t count;
+    uint64_t entries, ring_start, ring_len;
+    uint32_t slot, gen;
+    uint64_t t;
+};
+
+// Reads the published results of admitted requests, marks them done and frees
+// their slots and ring space.  mu held (it writes Req records).
 void collect(nq_server* s) {
     const uint64_t t = now_ns();
     for (auto& a : s->admitted) {
         if (a.done) continue;
         const unsigned long long flag = __atomic_load_n(&s->h_flag[a.slot], __ATOMIC_ACQUIRE);
         if (flag != a.gen) continue;
-        Req& r = s->reqs.at(a.ticket);                 // present until done and polled
-        r.count = __atomic_load_n(&s->h_val[a.slot], __ATOMIC_ACQUIRE);
-        r.t_done = t;
-        r.state = ReqState::Done;
+        auto it = s->reqs.find(a.ticket);              // present until done and polled
+        if (it != s->reqs.end()) {
+            Req& r = it->second;
+            r.count = __atomic_load_n(&s->h_val[a.slot], __ATOMIC_ACQUIRE);
+            r.t_done = t;
+            r.state = ReqState::Done;
+        }
         a.done = true;
         s->free_slots.push_back(a.slot);
     }
@@ -233,80 +258,77 @@ void collect(nq_server* s) {
         s->admitted.pop_front();
     }
     if (s->admitted.empty()) s->ring_head = s->ring_tail;
-    // Retire finished epochs' staging buffers.  An epoch whose event reports a
-    // device error is retired too, and the error becomes the server's fatal
-    // status: its requests will never publish.
-    while (!s->epochs.empty()) {
-        const hipError_t q = hipEventQuery(s->epochs.front().done);
-        if (q == hipErrorNotReady) break;
-        if (q != hipSuccess && s->fatal == NQ_OK) {
-            s->fatal_hip = (int)q;
-            s->fatal = NQ_EDEVICE;
-        }
-        (void)hipEventDestroy(s->epochs.front().done);
-        s->epochs.pop_front();
-    }
     s->cv.notify_all();
 }
 
-// Admits pending requests and launches one epoch over them.  mu held; the
-// HIP calls are made with it held too (they only enqueue work).
-int admit_and_launch(nq_server* s) {
-    if (s->pending.empty() || s->free_slots.empty()) return NQ_OK;
+// Retires finished epochs' staging buffers (scheduler thread, mu not held).
+// An epoch whose event reports a device error is retired too; the error is
+// returned, to become the server's fatal status: its requests will never
+// publish.
+int retire_epochs(nq_server* s) {
+    int err = 0;
+    while (!s->epochs.empty()) {
+        const hipError_t q = hipEventQuery(s->epochs.front().done);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess && err == 0) err = (int)q;
+        (void)hipEventDestroy(s->epochs.front().done);
+        s->epochs.pop_front();
+    }
+    return err;
+}
+
+// Admits candidates in arrival order while request slots and ring space
+// allow and launches one epoch over them (scheduler thread, mu not held:
+// resident frontier builds and the enqueued copies and launch do not block
+// submitters).  *used receives how many candidates were decided (admitted or
+// finished); the others wait for ring space.
+int admit_and_launch(nq_server* s, const std::vector<Candidate>& cand, std::vector<Outcome>* out,
+                     size_t* used) {
+    *used = 0;
+    if (cand.empty() || s->free_slots.empty()) return NQ_OK;
     TraceRange t("epoch");
     Epoch ep;
     const uint64_t epoch_start = s->ring_tail;
-    std::vector<uint64_t> taken;
     uint32_t frames = 0;                                  // deepest stack of the epoch
     struct Copy { const Resident* res; uint64_t src, pos, len; uint32_t slot; };
     std::vector<Copy> copies;
-    while (!s->pending.empty() && !s->free_slots.empty()) {
-        Req& r = s->reqs.at(s->pending.front());
-        auto finish = [&](int status) {
-            r.status = status;
-            r.state = ReqState::Done;
-            r.t_admit = r.t_done = now_ns();
-            s->pending.pop_front();
+    size_t idx = 0;
+    for (; idx < cand.size() && !s->free_slots.empty(); ++idx) {
+        const Candidate& c = cand[idx];
+        auto finish = [&](int status, uint64_t count) {
+            const uint64_t now = now_ns();
+            out->push_back({c.ticket, status, false, count, 0, 0, 0, 0, 0, now});
         };
         Resident* res = nullptr;
-        int rc = ensure_resident(s, r.rq.n, r.depth, r.rq.kind, &res);
-        if (rc != NQ_OK) { finish(rc); continue; }
+        int rc = ensure_resident(s, c.rq.n, c.depth, c.rq.kind, &res);
+        if (rc != NQ_OK) { finish(rc, 0); continue; }
         uint64_t lo = 0, hi = res->len;                   // entries of the (n, depth) frontier
-        if (r.rq.kind == NQ_REQ_SLICE) {
-            if (r.rq.start > res->len || r.rq.len > res->len - r.rq.start) {
-                finish(NQ_EINVAL);
+        if (c.rq.kind == NQ_REQ_SLICE) {
+            if (c.rq.start > res->len || c.rq.len > res->len - c.rq.start) {
+                finish(NQ_EINVAL, 0);
                 continue;
             }
-            lo = r.rq.start;
-            hi = r.rq.start + r.rq.len;
+            lo = c.rq.start;
+            hi = c.rq.start + c.rq.len;
         }
         const uint64_t src = res->first(lo);
         const uint64_t F = res->first(hi) - src;          // subproblems in the ring
-        if (F > s->ring_cap) { finish(NQ_ENOMEM); continue; }     // can never fit
+        if (F > s->ring_cap) { finish(NQ_ENOMEM, 0); continue; }  // can never fit
         if (s->ring_tail + F - s->ring_head > s->ring_cap) break;   // wait for space
-        if (F == 0) {                                     // nothing to search
-            r.count = 0;
-            finish(NQ_OK);
-            continue;
-        }
+        if (F == 0) { finish(NQ_OK, 0); continue; }       // nothing to search
         const uint32_t slot = s->free_slots.back();
         s->free_slots.pop_back();
-        r.slot = slot;
-        r.gen = ++s->slot_gen[slot];
-        r.ring_start = s->ring_tail;
-        r.ring_len = F;
-        r.entries = F;
+        const uint32_t gen = ++s->slot_gen[slot];
+        const uint64_t start = s->ring_tail;
         s->ring_tail += F;
-        frames = std::max(frames, frames_needed(r.rq.n, r.depth + res->rows));
-        ep.inits.push_back({slot, r.rq.n, (uint32_t)F, r.gen});
-        copies.push_back({res, src, r.ring_start, F, slot});
-        r.state = ReqState::Admitted;
-        r.t_admit = now_ns();
-        taken.push_back(s->pending.front());
-        s->admitted.push_back({s->pending.front(), r.ring_start, r.ring_len, slot, r.gen, false});
-        s->pending.pop_front();
+        frames = std::max(frames, frames_needed(c.rq.n, c.depth + res->rows));
+        ep.inits.push_back({slot, c.rq.n, (uint32_t)F, gen});
+        copies.push_back({res, src, start, F, slot});
+        out->push_back({c.ticket, NQ_OK, true, 0, F, start, F, slot, gen, now_ns()});
+        s->admitted.push_back({c.ticket, start, F, slot, gen, false});
     }
-    if (taken.empty()) return NQ_OK;
+    *used = idx;
+    if (copies.empty()) return NQ_OK;
     const uint64_t n_entries = s->ring_tail - epoch_start;
     hipStream_t st = s->streams[s->epoch_no % kStreams];
     hipError_t e = hipSuccess;
@@ -380,23 +402,79 @@ int admit_and_launch(nq_server* s) {
     return NQ_OK;
 }
 
+// Applies admission outcomes and returns undecided candidates to the front of
+// the queue (or drops them when the server is being destroyed, as the queue
+// itself was).  mu held.
+void apply(nq_server* s, const std::vector<Candidate>& cand, const std::vector<Outcome>& out) {
+    for (const Outcome& o : out) {
+        auto it = s->reqs.find(o.ticket);
+        if (it == s->reqs.end()) continue;
+        Req& r = it->second;
+        r.status = o.status;
+        r.t_admit = o.t;
+        if (o.admitted) {
+            r.state = ReqState::Admitted;
+            r.slot = o.slot;
+            r.gen = o.gen;
+            r.ring_start = o.ring_start;
+            r.ring_len = o.ring_len;
+            r.entries = o.entries;
+        } else {
+            r.count = o.count;
+            r.t_done = o.t;
+            r.state = ReqState::Done;
+        }
+    }
+    for (size_t i = cand.size(); i-- > out.size();) {
+        if (s->stop)
+            s->reqs.erase(cand[i].ticket);
+        else
+            s->pending.push_front(cand[i].ticket);
+    }
+    s->cv.notify_all();
+}
+
 void worker_main(nq_server* s) {
+    std::vector<Candidate> cand;
+    std::vector<Outcome> out;
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
+        cand.clear();
+        out.clear();
+        int rc = NQ_OK, hip = 0;
         try {
             collect(s);
+            // The oldest pending requests, as many as there are free slots,
+            // leave the queue while the device work is enqueued unlocked.
             if (s->fatal == NQ_OK) {
-                int rc = admit_and_launch(s);
-                if (rc != NQ_OK) {
-                    s->fatal = rc;
-                    s->fatal_hip = nq_last_hip_error();   // set on this (the worker) thread
+                const size_t take = std::min(s->pending.size(), s->free_slots.size());
+                cand.reserve(take);
+                out.reserve(take);
+                for (size_t i = 0; i < take; ++i) {
+                    const uint64_t t = s->pending.front();
+                    const Req& r = s->reqs.at(t);
+                    cand.push_back({t, r.rq, r.depth});
+                    s->pending.pop_front();
                 }
             }
-        } catch (...) {                 // a host allocation failed: stop admitting
-            if (s->fatal == NQ_OK) {
-                s->fatal = NQ_ENOMEM;
-                s->fatal_hip = 0;
+            lk.unlock();
+            if (const int ev = retire_epochs(s)) {
+                rc = NQ_EDEVICE;
+                hip = ev;
+            } else if (!cand.empty()) {
+                size_t used = 0;
+                rc = admit_and_launch(s, cand, &out, &used);
+                if (rc != NQ_OK) hip = nq_last_hip_error();   // set on this (the worker) thread
             }
+        } catch (...) {                 // a host allocation failed: stop admitting
+            rc = NQ_ENOMEM;
+            hip = 0;
+        }
+        if (!lk.owns_lock()) lk.lock();
+        apply(s, cand, out);
+        if (rc != NQ_OK && s->fatal == NQ_OK) {
+            s->fatal = rc;
+            s->fatal_hip = hip;
             s->cv.notify_all();
         }
         // After a fatal error nothing admitted is waited for: its results

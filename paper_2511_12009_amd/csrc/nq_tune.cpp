@@ -1,6 +1,8 @@
 // Autotuner: picks the pre-placement depth and the persistent launch shape
 // (workgroup size, waves per CU, steps between scheduler visits, entries per
-// work-head claim) for a board size by timing full counts on the device.
+// work-head claim) for a board size by timing full counts on the device; for
+// the boards whose count runs in chunks (N = 21..23), the depth, timed on one
+// chunk.
 //
 // The paper tunes the pre-placed rows and the block/stack configuration by
 // hand (Section 4.1, Table 3; Section 4.2, Table 4); here the same choices are
@@ -104,6 +106,68 @@ int trial(uint32_t n, uint32_t depth, const TrialFrontier& tf, uint32_t wg_size,
     return NQ_OK;
 }
 
+// Boards whose count runs in chunks: the depth is measured on one chunk (the
+// middle one of the plan's chunk count), which every depth counts the same
+// way, in wall-clock time, since a deeper chunk also spends more time in its
+// device expansion.  The first depth is timed twice (the first run also loads
+// the code objects).
+int autotune_chunked(uint32_t n, const ChunkPlan& plan, uint32_t lo, uint32_t hi,
+                     double budget_ms, nq_tuned* out, nq_tune_trial* table, uint32_t capacity,
+                     uint32_t* out_count) {
+    if (lo == 0) lo = std::max(kChunkHostDepth, plan.depth - 1);
+    if (hi == 0) hi = std::min(n - 2, plan.depth + 1);
+    if (lo < kChunkHostDepth || lo > hi || hi > n) return NQ_EINVAL;
+    if (budget_ms <= 0) budget_ms = 60000.0;
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) { set_hip_error(e); return NQ_EDEVICE; }
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } guard{s};
+    nq_opts o{};
+    o.mode = NQ_MODE_PERSISTENT;
+    o.stream = s;
+    const uint32_t index = plan.chunks / 2;
+    nq_tuned best{};
+    best.ms = 1e300;
+    double spent = 0.0;
+    unsigned __int128 expect = 0;
+    bool have_expect = false;
+    uint32_t trials = 0;
+    for (uint32_t d = lo; d <= hi && spent < budget_ms; ++d) {
+        for (int rep = 0; rep < (d == lo ? 2 : 1) && spent < budget_ms; ++rep) {
+            double ms = 0.0;
+            unsigned __int128 total = 0;
+            const int rc = time_chunk(n, d, plan.chunks, index, o, &ms, &total);
+            if (rc != NQ_OK) return rc;
+            if (table && trials < capacity)
+                table[trials] = nq_tune_trial{d, 0u, 0u, 0u, 0u, plan.chunks, ms, 0u};
+            ++trials;
+            spent += ms;
+            if (have_expect && total != expect) return NQ_EDEVICE;   // counts must agree
+            expect = total;
+            have_expect = true;
+            if (ms < best.ms) {
+                best.depth = d;
+                best.ms = ms;
+            }
+        }
+    }
+    best.chunks = plan.chunks;
+    best.trials = trials;
+    best.count = (uint64_t)expect;          // a chunk of n <= 23: below 2^64
+    if (out_count) *out_count = std::min(trials, table ? capacity : 0u);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[{dev, n}] = best;
+    }
+    *out = best;
+    return NQ_OK;
+}
+
 }  // namespace
 
 int tune_lookup(uint32_t n, nq_tuned* out) {
@@ -119,6 +183,9 @@ int tune_lookup(uint32_t n, nq_tuned* out) {
 int autotune(uint32_t n, uint32_t depth_lo, uint32_t depth_hi, double budget_ms, nq_tuned* out,
              nq_tune_trial* table, uint32_t capacity, uint32_t* out_count) {
     if (n < 4 || n > NQ_MAX_N || !out || (table && !capacity)) return NQ_EINVAL;
+    if (const ChunkPlan* plan = chunk_plan(n))
+        return autotune_chunked(n, *plan, depth_lo, depth_hi, budget_ms, out, table, capacity,
+                                out_count);
     if (depth_lo == 0) depth_lo = std::max<uint32_t>(1, std::min<uint32_t>(n - 2, n > 12 ? n - 14 : 1));
     if (depth_hi == 0) depth_hi = std::min<uint32_t>(n - 2, depth_lo + 4);
     if (depth_lo > depth_hi || depth_hi > n) return NQ_EINVAL;

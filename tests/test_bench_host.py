@@ -88,3 +88,9 @@ def test_kernel_digest_covers_the_kernel_sources():
     assert len(d) == 64 and int(d, 16) >= 0
     for rel in bench.KERNEL_FILES:
         assert os.path.exists(os.path.join(ROOT, rel))
+
+
+def test_stored_permanent_lookup():
+    stored = bench.perm_stored()
+    assert stored[(20, 0.5, 0)] == 1910787252054
+    assert all(v > 0 for v in stored.values())

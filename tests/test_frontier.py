@@ -181,6 +181,10 @@ def test_batch_serve_tune_entry_points_validate_before_touching_the_gpu():
     assert lib.nq_autotune(20, 0, 0, 0.0, None) == -1
     assert lib.nq_autotune(20, 9, 6, 0.0, ct.byref(tuned)) == -1
     assert lib.nq_autotune(20, 6, 21, 0.0, ct.byref(tuned)) == -1
+    # chunked boards (21..23): chunk depths start at the host depth 5
+    assert lib.nq_autotune(21, 3, 4, 0.0, ct.byref(tuned)) == -1
+    assert lib.nq_autotune(22, 11, 10, 0.0, ct.byref(tuned)) == -1
+    assert lib.nq_autotune(23, 9, 24, 0.0, ct.byref(tuned)) == -1
 
 
 def test_frontier_runs_cover_row0_columns():
@@ -362,3 +366,77 @@ def test_ubench_arguments_are_checked_before_any_device_work():
                                             (0, 0, 64, 0, 10), (0, 0, 64, 33, 10),
                                             (0, 0, 64, 4, 1), (0, 0, 64, 4, 33)):
         assert L.nq_ubench_lds(layout, op, active, wpc, frames, 16, ct.byref(d1)) == -1
+
+
+@pytest.mark.skipif(__import__("shutil").which("gcc") is None, reason="needs gcc")
+def test_binding_structures_have_the_header_layout(tmp_path):
+    """Every structure the binding passes by pointer has the size and field
+    offsets that a C compiler gives the header's declaration."""
+    import subprocess
+    from paper_2511_12009_amd import _native as nat
+    pairs = [("nq_opts", nat.NqOpts), ("nq_tuned", nat.NqTuned),
+             ("nq_tune_trial", nat.NqTuneTrial), ("nq_request", nat.NqRequest),
+             ("nq_result", nat.NqResult)]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "nq.h"', "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True, capture_output=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                               text=True).stdout.splitlines():
+        cname, field, v = line.split()
+        got[(cname, field)] = int(v)
+    for cname, cls in pairs:
+        assert got[(cname, "size")] == ct.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+@pytest.mark.parametrize("n,dens,seed", [(1, 1.0, 0), (2, 0.7, 1), (7, 0.6, 2), (10, 0.5, 3),
+                                         (12, 0.8, 4)])
+def test_perm_frontier_matches_oracle(n, dens, seed):
+    """The permanent search's frontier: the used-column set of every prefix the
+    oracle enumerates, in the same (lexicographic) order, at every depth."""
+    import seeded_inputs
+    a = np.array(seeded_inputs.matrix01(n, dens, seeded_inputs.MATRIX_SEED + seed), np.uint8)
+    for k in range(0, min(n, 6) + 1):
+        got = nq.perm_frontier(a, k)
+        ref = oracle.perm_prefixes_cols(n, oracle.perm_frontier(a, k))
+        np.testing.assert_array_equal(got, ref)
+
+
+def test_perm_entry_points_validate_before_touching_the_gpu():
+    lib = nq.lib()
+    rows = (ct.c_uint32 * 32)(*([0b111] * 3 + [0] * 29))
+    out = ct.c_uint64()
+    cols = (ct.c_uint32 * 8)()
+    assert lib.nq_perm_frontier(3, rows, 2, cols, 8, ct.byref(out)) == 0 and out.value == 6
+    assert lib.nq_perm_frontier(3, rows, 2, cols, 4, ct.byref(out)) == -2   # NQ_ERANGE
+    assert lib.nq_perm_frontier(3, rows, 2, None, 0, ct.byref(out)) == 0 and out.value == 6
+    assert lib.nq_perm_frontier(0, rows, 0, None, 0, ct.byref(out)) == -1
+    assert lib.nq_perm_frontier(21, rows, 0, None, 0, ct.byref(out)) == -1
+    assert lib.nq_perm_frontier(3, rows, 4, None, 0, ct.byref(out)) == -1
+    assert lib.nq_perm_frontier(3, None, 1, None, 0, ct.byref(out)) == -1
+    assert lib.nq_perm_frontier(3, rows, 1, None, 0, None) == -1
+    wide = (ct.c_uint32 * 3)(0b111, 0b1000, 0b111)                      # a column off the board
+    assert lib.nq_perm_frontier(3, wide, 1, None, 0, ct.byref(out)) == -1
+    total = ct.c_uint64()
+    assert lib.nq_perm_count(0, rows, None, ct.byref(total)) == -1
+    assert lib.nq_perm_count(3, wide, None, ct.byref(total)) == -1
+    assert lib.nq_perm_count(3, rows, None, None) == -1
+    o = nq._native.NqOpts()
+    o.flags = 1
+    assert lib.nq_perm_count(3, rows, ct.byref(o), ct.byref(total)) == -1
+    assert lib.nq_perm_count_subproblems(3, rows, None, 5, 1, None, None, None) == -1
+    assert lib.nq_perm_count_subproblems(3, rows, None, 0, 4, None, None, None) == -1
+    assert lib.nq_perm_count_subproblems(21, rows, None, 0, 1, None, None, None) == -1
+    with pytest.raises(ValueError):
+        nq.perm_rows(np.ones((3, 4)))
+    assert nq.perm_rows([[1, 0, 1], [0, 1, 0], [1, 1, 1]]).tolist() == [0b101, 0b010, 0b111]

@@ -54,3 +54,37 @@ def test_autotune_rejects_bad_ranges():
         nq.autotune(3)
     with pytest.raises(nq.NQError):
         nq.autotune(12, 6, 4)
+
+
+def test_chunked_board_is_tuned_on_one_chunk(known_counts):
+    """N = 21 counts in 16 chunks of its depth-5 frontier: the tuner times the
+    middle chunk at depths 9..11 (every depth must give that chunk the same
+    count), and nq_count then runs the chunked count at the tuned depth,
+    exactly.  The chunk's count is also taken by a launch over the same
+    depth-5 entries without any expansion."""
+    import numpy as np
+    import paper_2511_12009_amd as nq
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    n = 21
+    print("[gpu-tune] autotune n=21 (chunked)", flush=True)
+    best = nq.autotune(n, table=True)
+    assert best["chunks"] == 16 and 9 <= best["depth"] <= 11
+    table = best["table"]
+    assert [r["depth"] for r in table] == [9, 9, 10, 11]
+    assert all(r["chunks"] == 16 and r["ms"] > 0 for r in table)
+    assert min(r["ms"] for r in table) == best["ms"]
+    assert nq.tuned_lookup(n) == {k: v for k, v in best.items() if k != "table"}
+    cols, ld, rd, w = nq.frontier(n, 5)
+    F = len(cols)
+    lo, hi = F * 8 // 16, F * 9 // 16
+    dev = [torch.from_numpy(np.ascontiguousarray(a[lo:hi]).view(np.int32)).cuda()
+           for a in (cols, ld, rd)]
+    wt = torch.from_numpy(np.ascontiguousarray(w[lo:hi])).cuda()
+    total = torch.zeros(1, dtype=torch.int64, device="cuda")
+    print("[gpu-tune] middle chunk at depth 5", flush=True)
+    nq.count_subproblems(n, *dev, weight=wt, counts=False, total=total, depth=5)
+    torch.cuda.synchronize()
+    assert int(total.item()) == best["count"]
+    print("[gpu-tune] count(21) with the tuned chunk plan", flush=True)
+    assert nq.count(n) == known_counts[n]
