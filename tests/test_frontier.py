@@ -170,6 +170,12 @@ def test_batch_serve_tune_entry_points_validate_before_touching_the_gpu():
     req = nq._native.NqRequest()
     tk = ct.c_uint64()
     assert lib.nq_serve_create(None, 0, None) == -1
+    # unknown flag bits are refused before any device work
+    srv = ct.c_void_p()
+    so = nq._native.NqOpts()
+    so.flags = 8
+    assert lib.nq_serve_create(ct.byref(so), 0, ct.byref(srv)) == -1
+    assert lib.nq_count(12, ct.byref(so), ct.byref(tk)) == -1
     assert lib.nq_serve_submit(None, ct.byref(req), ct.byref(tk)) == -1
     assert lib.nq_serve_poll(None, 0, ct.byref(res)) == -1
     assert lib.nq_serve_wait(None, 0, ct.byref(res), 1000) == -1
