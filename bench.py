@@ -257,18 +257,21 @@ def perm_stored():
     return out
 
 
-def bench_perm(nq, torch, n=20, density=0.5):
+def bench_perm(nq, torch, n=20, density=0.5, depths=(9,), reps=2):
     """The third search on the same engine: the permanent of the seeded n x n
     0/1 matrix of the given density (two-word frames, two-row leaf rule), one
-    persistent launch over the host frontier resident on the device, at depths
-    6..8; kernel time from HIP events, nodes (placements in rows k..n-3) from
-    one node-counting launch per depth, the total checked against the stored
-    permanent."""
+    persistent launch over the host frontier resident on the device, at the
+    given depths (the line: 9, the best; --perm-only: 7..9; at depth 6 the
+    330,541 subtrees of n = 20 leave most lanes idle behind the largest);
+    kernel time from HIP events (best of `reps`), nodes (placements in rows
+    k..n-3) from one node-counting launch per depth, the total checked
+    against the stored permanent."""
     import seeded_inputs
     a = np.array(seeded_inputs.matrix01(n, density), np.uint8)
     want = perm_stored()[(n, density, 0)]
     rows = []
-    for k in (6, 7, 8):
+    for k in depths:
+        print(f"[bench] permanent n={n} depth {k}", file=sys.stderr, flush=True)
         cols = nq.perm_frontier(a, k)
         d = torch.from_numpy(np.ascontiguousarray(cols).view(np.int32)).cuda()
         nodes = torch.empty(len(cols), dtype=torch.int64, device="cuda")
@@ -278,7 +281,7 @@ def bench_perm(nq, torch, n=20, density=0.5):
             raise SystemExit(f"bench.py: permanent {int(tot.item())} != {want} (node run, k={k})")
         below = int(nodes.sum().item())
         best = None
-        for _ in range(3):
+        for _ in range(reps):
             _, tot, ms = nq.perm_count_subproblems(a, d, k, counts=False, timing=True)
             if int(tot.item()) != want:
                 raise SystemExit(f"bench.py: permanent {int(tot.item())} != {want} (k={k})")
@@ -663,8 +666,14 @@ def main():
                     help="comma list of boards (21..23) counted whole by nq_count's automatic "
                          "chunked path; one JSON line per board")
     ap.add_argument("--resumable", type=int, default=0,
-                    help="count this board with nq_count_resumable, one chunk per call, "
-                         "printing a line per chunk (with --resumable-path, --resumable-upto)")
+                    help="count this board with nq_count_resumable, --resumable-batch chunks "
+                         "per call, printing a line per call (with --resumable-path, "
+                         "--resumable-upto)")
+    ap.add_argument("--resumable-batch", type=int, default=4,
+                    help="chunks per nq_count_resumable call (its buffers live for one call)")
+    ap.add_argument("--chunked-repeat", default=None,
+                    help="N:depth:chunks:reps - time `reps` whole chunked counts (fresh "
+                         "progress files, all chunks in one call) in this process")
     ap.add_argument("--resumable-path", default="n.progress")
     ap.add_argument("--resumable-upto", type=int, default=0, help="stop after this many chunks")
     ap.add_argument("--resumable-chunks", type=int, default=64)
@@ -709,12 +718,26 @@ def main():
                 raise SystemExit(f"bench.py: Q({n}) = {got}, expected {known.get(n)}")
             print(json.dumps(row), flush=True)
         return
+    if args.chunked_repeat:
+        import tempfile
+        n, depth, chunks, reps = (int(x) for x in args.chunked_repeat.split(":"))
+        for rep in range(reps):
+            path = os.path.join(tempfile.mkdtemp(), "count.progress")
+            t = time.perf_counter()
+            total, done, fin = nq.count_resumable(n, path, chunks=chunks, depth=depth)
+            wall = time.perf_counter() - t
+            if not fin or total != known_counts()[n]:
+                raise SystemExit(f"bench.py: chunked Q({n}) = {total}, expected {known_counts()[n]}")
+            print(json.dumps({"n": n, "depth": depth, "chunks": chunks, "rep": rep,
+                              "wall_s": wall, "exact": True}), flush=True)
+        return
     if args.resumable:
         t0 = time.perf_counter()
         while True:
             t = time.perf_counter()
             total, done, fin = nq.count_resumable(args.resumable, args.resumable_path,
-                                                  chunks=args.resumable_chunks, max_chunks=1,
+                                                  chunks=args.resumable_chunks,
+                                                  max_chunks=max(1, args.resumable_batch),
                                                   depth=args.resumable_depth)
             print(json.dumps({"n": args.resumable, "chunks_done": done, "total": total,
                               "chunk_s": time.perf_counter() - t,
@@ -727,7 +750,7 @@ def main():
                              f"{known_counts()[args.resumable]}")
         return
     if args.perm_only:
-        print(json.dumps({"perm": bench_perm(nq, torch)}), flush=True)
+        print(json.dumps({"perm": bench_perm(nq, torch, depths=(7, 8, 9), reps=3)}), flush=True)
         return
     if args.serving_only:
         rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]

@@ -58,6 +58,7 @@ namespace {
 // Device buffer released on scope exit.
 struct DevBuf {
     void* p = nullptr;
+    size_t cap = 0;
     ~DevBuf() {
         if (p) (void)hipFree(p);
     }
@@ -67,9 +68,22 @@ struct DevBuf {
         if (e != hipSuccess) {
             set_hip_error((int)e);
             p = nullptr;
+            cap = 0;
             return e == hipErrorOutOfMemory ? NQ_ENOMEM : NQ_EDEVICE;
         }
+        cap = bytes;
         return NQ_OK;
+    }
+    // Keeps the buffer when it holds `bytes`, else replaces it (contents lost).
+    int ensure(size_t bytes) {
+        if (p && cap >= bytes) return NQ_OK;
+        if (p) {
+            hipError_t e = hipFree(p);
+            p = nullptr;
+            cap = 0;
+            if (e != hipSuccess) { set_hip_error((int)e); return NQ_EDEVICE; }
+        }
+        return alloc(bytes);
     }
     template <class T>
     T* as() const { return static_cast<T*>(p); }
@@ -199,21 +213,38 @@ static int run_device(uint32_t n, const uint32_t* d_cols, const uint32_t* d_ld,
 
 namespace {
 
-// Allocates the arrays of a frontier of `len` entries (cols | ld | rd | weight).
-int alloc_frontier(uint64_t len, DeviceFrontier* f) {
-    const size_t o_ld = len * 4, o_rd = 2 * len * 4, o_w = 3 * len * 4;
+// Allocates the arrays of a frontier of `len` entries (cols | ld | rd | weight)
+// with room for `cap` >= len (the arrays are laid out for cap entries).
+int alloc_frontier(uint64_t len, DeviceFrontier* f, uint64_t cap = 0) {
+    cap = std::max(cap, len);
+    const size_t o_ld = cap * 4, o_rd = 2 * cap * 4, o_w = 3 * cap * 4;
     DevBuf arr;
-    int rc = arr.alloc(o_w + len + 16);
+    int rc = arr.alloc(o_w + cap + 16);
     if (rc != NQ_OK) return rc;
     char* b = arr.as<char>();
+    *f = DeviceFrontier();                        // frees what it held
     f->dev = arr.p;
     arr.p = nullptr;
     f->len = len;
+    f->cap = cap;
     f->cols = reinterpret_cast<uint32_t*>(b);
     f->ld = reinterpret_cast<uint32_t*>(b + o_ld);
     f->rd = reinterpret_cast<uint32_t*>(b + o_rd);
     f->w = reinterpret_cast<uint8_t*>(b + o_w);
     return NQ_OK;
+}
+
+// A frontier of `len` entries in `f`, keeping f's arrays when they have room
+// (contents lost); a new allocation gets 1/8 more room, so that the next
+// chunks of a chunked count, a little larger or smaller, reuse it.
+int reuse_frontier(uint64_t len, DeviceFrontier* f) {
+    if (f->dev && f->cap >= len) {
+        f->len = len;
+        f->first_row.clear();
+        return NQ_OK;
+    }
+    *f = DeviceFrontier();                        // free before the larger allocation
+    return alloc_frontier(len, f, len + len / 8);
 }
 
 // The host frontier of depth `depth` (nq_frontier) uploaded to the device.
@@ -243,16 +274,25 @@ int host_frontier(uint32_t n, uint32_t depth, hipStream_t s, DeviceFrontier* out
 // `in` expanded by `rows` (1..3) on the device into `out`; the row-0 runs are
 // carried over, and `offsets` (nullable) receives the index of the first child
 // of every entry of `in` (offsets[in.len] = out->len).
+// The frontier `rows` rows below `in`, in `out`.  With `keep` (chunked
+// counts) out's arrays and the scan scratch *keep are reused when they have
+// room, so that a count of many chunks does not allocate and free its
+// largest buffers once per chunk (on this runtime such frees and
+// allocations of several GB slow down after a few dozen, to 0.2-2 s each).
 int expand_frontier(uint32_t n, const DeviceFrontier& in, uint32_t rows, hipStream_t s,
-                    DeviceFrontier* out, std::vector<uint64_t>* offsets) {
+                    DeviceFrontier* out, std::vector<uint64_t>* offsets,
+                    DevBuf* keep = nullptr) {
     TraceRange t("expand");
     if (in.len == 0) {                            // nothing to expand
         if (offsets) offsets->assign(1, 0);
+        int rc0 = keep ? reuse_frontier(0, out) : alloc_frontier(0, out);
         out->first_row.assign(in.first_row.size(), 0);
-        return alloc_frontier(0, out);
+        return rc0;
     }
-    DevBuf scratch;
-    int rc = scratch.alloc(expand_scratch_bytes(in.len));
+    DevBuf local;
+    DevBuf& scratch = keep ? *keep : local;
+    int rc = keep ? scratch.ensure(expand_scratch_bytes(in.len))
+                  : scratch.alloc(expand_scratch_bytes(in.len));
     if (rc != NQ_OK) return rc;
     uint64_t F = 0;
     rc = expand_device(n, rows, in.cols, in.ld, in.rd, in.w, in.len, nullptr, nullptr, nullptr,
@@ -271,7 +311,7 @@ int expand_frontier(uint32_t n, const DeviceFrontier& in, uint32_t rows, hipStre
             o = v;
         }
     }
-    if ((rc = alloc_frontier(F, out)) != NQ_OK) return rc;
+    if ((rc = keep ? reuse_frontier(F, out) : alloc_frontier(F, out)) != NQ_OK) return rc;
     uint64_t got = 0;
     rc = expand_device(n, rows, in.cols, in.ld, in.rd, in.w, in.len, out->cols, out->ld, out->rd,
                        out->w, F, &got, scratch.p, s);
@@ -290,10 +330,11 @@ DeviceFrontier::~DeviceFrontier() {
 DeviceFrontier& DeviceFrontier::operator=(DeviceFrontier&& o) noexcept {
     if (this != &o) {
         if (dev) (void)hipFree(dev);
-        dev = o.dev; len = o.len; cols = o.cols; ld = o.ld; rd = o.rd; w = o.w;
+        dev = o.dev; len = o.len; cap = o.cap; cols = o.cols; ld = o.ld; rd = o.rd; w = o.w;
         first_row = std::move(o.first_row);
         o.dev = nullptr;
         o.len = 0;
+        o.cap = 0;
     }
     return *this;
 }
@@ -368,29 +409,37 @@ int count_chunks(uint32_t n, const nq_opts& local, uint32_t depth, uint32_t host
     auto* d_total = tot.as<unsigned long long>();   // low word, high word
     nq_opts wide = local;
     wide.flags |= NQ_FLAG_WIDE_TOTAL;
+    // Device buffers kept across chunks and grown when a chunk needs more:
+    // the uploaded host range, two frontiers that the expansions alternate
+    // between, and the expansion's scan scratch.
+    DeviceFrontier up, pingpong[2];
+    DevBuf scan;
     uint32_t ran = 0;
     for (uint32_t i = first; i < chunks && (max_run == 0 || ran < max_run); ++i, ++ran) {
         const uint64_t lo = Fh * i / chunks, hi = Fh * (i + 1) / chunks;
         unsigned __int128 part = 0;
         TraceRange chunk_range("chunk");
         if (hi > lo) {
-            DeviceFrontier cur;
-            if ((rc = alloc_frontier(hi - lo, &cur)) != NQ_OK) return rc;
-            NQ_HIP(hipMemcpyAsync(cur.cols, hc.data() + lo, (hi - lo) * 4, hipMemcpyHostToDevice, s));
-            NQ_HIP(hipMemcpyAsync(cur.ld, hl.data() + lo, (hi - lo) * 4, hipMemcpyHostToDevice, s));
-            NQ_HIP(hipMemcpyAsync(cur.rd, hr.data() + lo, (hi - lo) * 4, hipMemcpyHostToDevice, s));
-            NQ_HIP(hipMemcpyAsync(cur.w, hw.data() + lo, hi - lo, hipMemcpyHostToDevice, s));
+            if ((rc = reuse_frontier(hi - lo, &up)) != NQ_OK) return rc;
+            NQ_HIP(hipMemcpyAsync(up.cols, hc.data() + lo, (hi - lo) * 4, hipMemcpyHostToDevice, s));
+            NQ_HIP(hipMemcpyAsync(up.ld, hl.data() + lo, (hi - lo) * 4, hipMemcpyHostToDevice, s));
+            NQ_HIP(hipMemcpyAsync(up.rd, hr.data() + lo, (hi - lo) * 4, hipMemcpyHostToDevice, s));
+            NQ_HIP(hipMemcpyAsync(up.w, hw.data() + lo, hi - lo, hipMemcpyHostToDevice, s));
+            const DeviceFrontier* cur = &up;
+            int which = 0;
             for (uint32_t have = host_depth; have < depth;) {
                 const uint32_t left = depth - have, steps = (left + 2) / 3;
                 const uint32_t rows = (left + steps - 1) / steps;
-                DeviceFrontier next;
-                if ((rc = expand_frontier(n, cur, rows, s, &next, nullptr)) != NQ_OK) return rc;
-                cur = std::move(next);
+                DeviceFrontier* next = &pingpong[which];
+                which ^= 1;
+                if ((rc = expand_frontier(n, *cur, rows, s, next, nullptr, &scan)) != NQ_OK)
+                    return rc;
+                cur = next;
                 have += rows;
             }
             double ms = 0.0;
             if ((rc = launch_zero_u64(d_total, 2, s)) != NQ_OK) return rc;
-            if ((rc = run_device(n, cur.cols, cur.ld, cur.rd, cur.w, cur.len, nullptr, d_total,
+            if ((rc = run_device(n, cur->cols, cur->ld, cur->rd, cur->w, cur->len, nullptr, d_total,
                                  depth, &wide, kernel_ms ? &ms : nullptr)) != NQ_OK)
                 return rc;
             uint64_t words[2] = {0, 0};

@@ -126,6 +126,7 @@ void set_hip_error(int err);
 struct DeviceFrontier {
     void* dev = nullptr;
     uint64_t len = 0;
+    uint64_t cap = 0;               // entries the arrays are laid out for (>= len)
     uint32_t* cols = nullptr;
     uint32_t* ld = nullptr;
     uint32_t* rd = nullptr;
@@ -135,7 +136,7 @@ struct DeviceFrontier {
     DeviceFrontier(const DeviceFrontier&) = delete;
     DeviceFrontier& operator=(const DeviceFrontier&) = delete;
     DeviceFrontier(DeviceFrontier&& o) noexcept
-        : dev(o.dev), len(o.len), cols(o.cols), ld(o.ld), rd(o.rd), w(o.w),
+        : dev(o.dev), len(o.len), cap(o.cap), cols(o.cols), ld(o.ld), rd(o.rd), w(o.w),
           first_row(std::move(o.first_row)) {
         o.dev = nullptr;
     }
