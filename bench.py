@@ -64,7 +64,7 @@ def golden_nodes(n, k):
 
 
 KERNEL_FILES = ("paper_2511_12009_amd/csrc/nq_dfs.hip", "paper_2511_12009_amd/csrc/nq_kernel.h",
-                "paper_2511_12009_amd/build.py")
+                "paper_2511_12009_amd/csrc/nq_wave.h", "paper_2511_12009_amd/build.py")
 
 
 def kernel_digest():

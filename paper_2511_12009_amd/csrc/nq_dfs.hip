@@ -36,6 +36,7 @@
 #include <cstdlib>
 
 #include "nq_internal.h"
+#include "nq_wave.h"
 
 namespace nqi {
 
@@ -45,26 +46,6 @@ constexpr int kLoopForms = 6;          // forms 0..5
 // LDS frames per lane that a form needs beyond N - 2 - placed.
 constexpr uint32_t kFormExtraFrames[kLoopForms] = {0, 0, 0, 1, 1, 1};
 
-namespace {
-
-__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
-    uint32_t lo = __shfl((int)(uint32_t)v, src, 64);
-    uint32_t hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
-    uint32_t lo = __shfl_xor((int)(uint32_t)v, mask, 64);
-    uint32_t hi = __shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-}  // namespace
 
 // Serving: the wave's retirements, added to their requests.  A request's total
 // and remaining count are only touched by device-scope atomics; the lane whose
@@ -464,39 +445,9 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         if (SERVE)
             retire_to_requests(held, P.remaining, P.totals, P.inst_gen, P.host_val, P.host_flag,
                                req_retire, req_slot, req_val, lane);
-        if (PERSISTENT && !exhausted) {
-            // Idle lanes take, in rank order, the wave's unused claimed
-            // entries [qlo, qhi) first, then a fresh block of at least
-            // P.claim entries claimed with one atomic add.
-            const uint64_t idle = __ballot(!has_task);
-            if (idle != 0) {
-                const uint32_t want = (uint32_t)__popcll(idle);
-                const uint64_t have = qhi - qlo;
-                uint64_t nlo = 0, nhi = 0;
-                if (have < want && !claimed_all) {
-                    const uint64_t grab = max((uint64_t)(want - have), (uint64_t)P.claim);
-                    const int leader = __ffsll((unsigned long long)idle) - 1;
-                    uint64_t first = 0;
-                    if ((int)lane == leader) first = atomicAdd(P.head, (unsigned long long)grab);
-                    first = shfl_u64(first, leader);
-                    nlo = min(first, P.len);
-                    nhi = min(first + grab, P.len);
-                    if (first + grab >= P.len) claimed_all = true;
-                }
-                if (!has_task) {
-                    const uint64_t rk = lane_rank(idle);
-                    if (rk < have) take(qlo + rk);
-                    else if (nlo + (rk - have) < nhi) take(nlo + (rk - have));
-                }
-                if (want <= have) {
-                    qlo += want;
-                } else {
-                    qlo = min(nlo + (want - have), nhi);
-                    qhi = nhi;
-                }
-                if (claimed_all && qlo >= qhi) exhausted = true;
-            }
-        }
+        if (PERSISTENT && !exhausted)
+            refill_idle_lanes(qlo, qhi, claimed_all, exhausted, has_task, lane, P.head, P.len,
+                              P.claim, take);
         if (!__any(v != 0u)) {
             if (exhausted && !__any(has_task)) break;
             continue;

@@ -20,9 +20,9 @@
 // to lane: the matrix's rows sit in LDS and a lane reads the word of its row
 // (the row is the popcount of the used columns).
 //
-// Scheduling is the queens kernel's protocol: plain launches take one entry
-// per lane; persistent launches keep a resident grid whose waves visit a
-// scheduler every `refill_every` steps (or once `idle_min` lanes are idle),
+// Scheduling is the queens kernel's (nq_wave.h): plain launches take one
+// entry per lane; persistent launches keep a resident grid whose waves visit
+// a scheduler every `refill_every` steps (or once `idle_min` lanes are idle),
 // retire finished lanes, and hand idle lanes entries by rank from a block
 // claimed with one atomic add on a global head.
 #include <hip/hip_runtime.h>
@@ -33,6 +33,7 @@
 
 #include "nq_internal.h"
 #include "nq_trace.h"
+#include "nq_wave.h"
 
 namespace nqi {
 
@@ -55,17 +56,6 @@ struct PermParams {
     uint32_t claim;
     uint32_t rows[32];           // row r's allowed columns (bit c)
 };
-
-__device__ __forceinline__ uint32_t perm_lane_rank(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-__device__ __forceinline__ uint64_t perm_shfl_u64(uint64_t v, int src) {
-    const uint32_t lo = __shfl((int)(uint32_t)v, src, 64);
-    const uint32_t hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
 
 // A frame: (used columns, untried columns), one 8-byte LDS slot.
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
@@ -147,36 +137,9 @@ __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
             if (sum != kCountInvalid) wtotal += sum;
             has_task = false;
         }
-        if (PERSISTENT && !exhausted) {
-            const uint64_t idle = __ballot(!has_task);
-            if (idle != 0) {
-                const uint32_t want = (uint32_t)__popcll(idle);
-                const uint64_t have = qhi - qlo;
-                uint64_t nlo = 0, nhi = 0;
-                if (have < want && !claimed_all) {
-                    const uint64_t grab = max((uint64_t)(want - have), (uint64_t)P.claim);
-                    const int leader = __ffsll((unsigned long long)idle) - 1;
-                    uint64_t first = 0;
-                    if ((int)lane == leader) first = atomicAdd(P.head, (unsigned long long)grab);
-                    first = perm_shfl_u64(first, leader);
-                    nlo = min(first, P.len);
-                    nhi = min(first + grab, P.len);
-                    if (first + grab >= P.len) claimed_all = true;
-                }
-                if (!has_task) {
-                    const uint64_t rk = perm_lane_rank(idle);
-                    if (rk < have) take(qlo + rk);
-                    else if (nlo + (rk - have) < nhi) take(nlo + (rk - have));
-                }
-                if (want <= have) {
-                    qlo += want;
-                } else {
-                    qlo = min(nlo + (want - have), nhi);
-                    qhi = nhi;
-                }
-                if (claimed_all && qlo >= qhi) exhausted = true;
-            }
-        }
+        if (PERSISTENT && !exhausted)
+            refill_idle_lanes(qlo, qhi, claimed_all, exhausted, has_task, lane, P.head, P.len,
+                              P.claim, take);
         if (!__any(v != 0u)) {
             if (exhausted && !__any(has_task)) break;
             continue;
@@ -219,11 +182,7 @@ __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
         }
     }
     if (P.total) {
-        for (int off = 32; off > 0; off >>= 1) {
-            const uint32_t lo = __shfl_xor((int)(uint32_t)wtotal, off, 64);
-            const uint32_t hi = __shfl_xor((int)(uint32_t)(wtotal >> 32), off, 64);
-            wtotal += ((uint64_t)hi << 32) | lo;
-        }
+        for (int off = 32; off > 0; off >>= 1) wtotal += shfl_xor_u64(wtotal, off);
         if (lane == 0 && wtotal != 0) atomicAdd(P.total, (unsigned long long)wtotal);
     }
 }
