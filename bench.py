@@ -257,11 +257,11 @@ def perm_stored():
     return out
 
 
-def bench_perm(nq, torch, n=20, density=0.5, depths=(9,), reps=2):
+def bench_perm(nq, torch, n=20, density=0.5, depths=(10,), reps=2):
     """The third search on the same engine: the permanent of the seeded n x n
     0/1 matrix of the given density (two-word frames, two-row leaf rule), one
     persistent launch over the host frontier resident on the device, at the
-    given depths (the line: 9, the best; --perm-only: 7..9; at depth 6 the
+    given depths (the line: 10, the best; --perm-only: 7..10; at depth 6 the
     330,541 subtrees of n = 20 leave most lanes idle behind the largest);
     kernel time from HIP events (best of `reps`), nodes (placements in rows
     k..n-3) from one node-counting launch per depth, the total checked
@@ -647,6 +647,8 @@ def main():
     ap.add_argument("--serve-rates", default="25,100,200", help="COUNT requests/s, comma list")
     ap.add_argument("--perm-only", action="store_true",
                     help="only the permanent search (third DFS workload; one JSON line)")
+    ap.add_argument("--perm-depths", default="7,8,9,10", help="with --perm-only: depths")
+    ap.add_argument("--perm-reps", type=int, default=3, help="with --perm-only: timed runs")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
@@ -750,7 +752,9 @@ def main():
                              f"{known_counts()[args.resumable]}")
         return
     if args.perm_only:
-        print(json.dumps({"perm": bench_perm(nq, torch, depths=(7, 8, 9), reps=3)}), flush=True)
+        depths = tuple(int(x) for x in args.perm_depths.split(",") if x.strip())
+        print(json.dumps({"perm": bench_perm(nq, torch, depths=depths, reps=args.perm_reps)}),
+              flush=True)
         return
     if args.serving_only:
         rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]

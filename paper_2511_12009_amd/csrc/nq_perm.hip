@@ -61,38 +61,48 @@ struct PermParams {
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) u32x2 lds_frame2;
 
-__device__ __forceinline__ lds_frame2* frame2_at(uint32_t addr) {
-    return (lds_frame2*)(uintptr_t)addr;
+__device__ __forceinline__ lds_frame2* frame2_at(int32_t addr) {
+    return (lds_frame2*)(uintptr_t)(uint32_t)addr;
 }
 
 // Completions of the last two rows when `left` holds the two unused columns
-// and ra, rb are the allowed columns of rows n-2 and n-1.
+// {x, y} and ra, rb are the allowed columns of rows n-2 and n-1: the number
+// of ways to give x and y to the two rows, [x in ra][y in rb] + [y in ra][x
+// in rb] = popc(A & swap(B)) with A = ra & left, B = rb & left, where swap
+// exchanges x and y: B itself when it holds both or neither, else left ^ B.
 __device__ __forceinline__ uint32_t two_rows(uint32_t left, uint32_t ra, uint32_t rb) {
-    const uint32_t x = left & (0u - left), y = left ^ x;
-    return (uint32_t)(((ra & x) != 0u) & ((rb & y) != 0u)) +
-           (uint32_t)(((ra & y) != 0u) & ((rb & x) != 0u));
+    const uint32_t a = ra & left, b = rb & left;
+    const uint32_t swapped = (__popc(b) == 1u) ? (b ^ left) : b;
+    return __popc(a & swapped);
 }
 
 template <bool PERSISTENT, bool STATS>
 __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
     extern __shared__ u32x2 perm_stack[];
-    __shared__ uint32_t mrows[32];
-    if (threadIdx.x < 32) mrows[threadIdx.x] = threadIdx.x < P.n ? P.rows[threadIdx.x] : 0u;
+    // the matrix's rows; row 32 (the "next row" of a parked lane, whose used
+    // set has all 32 bits) allows nothing
+    __shared__ uint32_t mrows[33];
+    if (threadIdx.x < 33) mrows[threadIdx.x] = threadIdx.x < P.n ? P.rows[threadIdx.x] : 0u;
     __syncthreads();
     const uint32_t lds = (uint32_t)(uintptr_t)(lds_frame2*)perm_stack;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
-    const uint32_t floor = lds + ((wave * (P.frames + 1u)) * 64u + lane) * kPermFrameBytes;
-    const uint32_t stride = 64u * kPermFrameBytes;
+    // Stack addresses are signed: LDS offsets are far below 2^31, and popping
+    // the sentinel computes floor - stride, which max() takes back to floor.
+    const int32_t floor =
+        (int32_t)(lds + ((wave * (P.frames + 1u)) * 64u + lane) * kPermFrameBytes);
+    const int32_t stride = (int32_t)(64u * kPermFrameBytes);
     const uint32_t n = P.n;
     const uint32_t board = (n >= 32u) ? 0xffffffffu : ((1u << n) - 1u);
     // the last two rows' allowed columns (wave-uniform)
     const uint32_t ra = n >= 2u ? mrows[n - 2u] : 0u, rb = mrows[(n - 1u) & 31u];
-    uint32_t top = floor;
+    const uint32_t leaf_row = n - 2u;     // reached with the last two rows left (n >= 3)
+    int32_t top = floor;
     *frame2_at(floor) = u32x2{kPermParked, 0u};
 
     uint32_t c = kPermParked, v = 0u;
     uint64_t idx = 0, sum = 0, steps = 0, wtotal = 0;
+    uint32_t sum32 = 0;                   // leaves since the last scheduler visit
     bool has_task = false;
     bool exhausted = !PERSISTENT;
     bool claimed_all = false;
@@ -131,6 +141,8 @@ __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
 
     for (;;) {
         // ---- scheduler visit: retire finished lanes, refill idle ones.
+        sum += sum32;                     // at most 2 per step: no 32-bit overflow
+        sum32 = 0;
         if (has_task && v == 0u) {
             if (P.counts) P.counts[idx] = sum;
             if (STATS) P.nodes[idx] = steps;
@@ -148,18 +160,19 @@ __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
         // A parked lane (sentinel popped) has every column used and nothing
         // untried: p = 0, its "next row" is 32 (read as row 0: nothing allowed
         // that is unused), no leaf, no descent, and its pops read the sentinel
-        // again (top stays at floor).
+        // again (top stays at floor).  A board of n <= 2 never gets here (its
+        // entries are settled when taken), so leaf_row never wraps into use.
         for (uint32_t it = 0; it < P.refill_every; it += 32u) {
             for (int s = 0; s < 32; ++s) {
                 const uint32_t p = v & (0u - v);
                 v ^= p;
                 const uint32_t nc = c | p;
-                const uint32_t row = __popc(nc);       // the row to fill next
+                const uint32_t row = __popc(nc);       // the row to fill next (32: parked)
                 const uint32_t left = ~nc & board;     // unused columns
-                const uint32_t a = mrows[row & 31u] & left;
-                const bool leaf = row + 2u == n;       // the last two rows are left
+                const uint32_t a = mrows[row] & left;
+                const bool leaf = row == leaf_row;     // the last two rows are left
                 if (STATS) steps += (p != 0u) ? 1u : 0u;
-                if (leaf && p != 0u) sum += two_rows(left, ra, rb);
+                if (leaf && p != 0u) sum32 += two_rows(left, ra, rb);
                 const bool desc = a != 0u && !leaf;
                 if (desc && v != 0u) {                 // keep the frame if it has work
                     top += stride;
@@ -172,7 +185,7 @@ __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
                     c = f.x;
                     v = f.y;
                     // unsigned addresses: never step below the sentinel
-                    top = (top > floor) ? top - stride : floor;
+                    top = max(top - stride, floor);
                 }
             }
             const uint64_t idle = __ballot(v == 0u);
@@ -259,7 +272,7 @@ int perm_run(uint32_t n, const uint32_t* rows, const uint32_t* d_cols, uint64_t 
     uint32_t wg = opts && opts->wg_size ? opts->wg_size : 64u;
     if (wg % 64u != 0 || wg > 1024u) return NQ_EINVAL;
     const uint64_t lds = (uint64_t)wg * (frames + 1u) * kPermFrameBytes;
-    if (lds + 32u * 4u > (uint64_t)dev.lds_per_block) return NQ_EINVAL;   // + the matrix
+    if (lds + 33u * 4u > (uint64_t)dev.lds_per_block) return NQ_EINVAL;   // + the matrix
     const bool stats = opts && opts->d_nodes;
     const void* fn = perm_kernel(mode == NQ_MODE_PERSISTENT, stats);
     uint32_t grid = 0;
@@ -285,7 +298,9 @@ int perm_run(uint32_t n, const uint32_t* rows, const uint32_t* d_cols, uint64_t 
     P.len = len;
     P.n = n;
     P.frames = frames;
-    P.refill_every = (opts && opts->refill_every) ? opts->refill_every : 512u;
+    // a lane adds at most two leaves per step to its 32-bit count between
+    // scheduler visits, so the visits stay well under 2^31 steps apart
+    P.refill_every = (opts && opts->refill_every) ? std::min(opts->refill_every, 1u << 30) : 512u;
     P.idle_min = default_idle_min();
     {
         const uint64_t waves = (uint64_t)grid * (wg / 64u);
