@@ -475,7 +475,7 @@ UB_LDS_OPS = {0: ("write b128 + read b128", 2), 1: ("read b128", 1), 2: ("write 
               11: ("read 16 B as read2_b64", 1)}
 
 
-def run_ubench(nq, args):
+def run_ubench(nq, args, occupancy_only=False):
     """The microbenchmarks behind the roofline (include/nq_ubench.h): the int32
     VALU rate of the DFS step's operations with eight independent chains per
     lane at 1..8 waves per SIMD (and one chain, one wave: the dependent
@@ -498,25 +498,30 @@ def run_ubench(nq, args):
         print(f"[bench] ubench valu {json.dumps(row)}", file=sys.stderr, flush=True)
         return row
 
-    for op in range(len(UB_OPS)):
+    for op in (() if occupancy_only else range(len(UB_OPS))):
         valu(op, 8, 1, 1 << 16)                              # warm the code object
         for wps in (1, 2, 4, 8):
             valu(op, 8, wps, 1 << 19)
         valu(op, 1, 1, 1 << 19)
 
-    def lds(layout, op, wpc, active):
+    def lds(layout, op, wpc, active, frames=10):
         iters = 1 << 16
-        nq.ubench_lds(layout, active, wpc, 10, 1 << 10, op=op)      # warm the code object
-        ms = nq.ubench_lds(layout, active, wpc, 10, iters, op=op)
+        nq.ubench_lds(layout, active, wpc, frames, 1 << 10, op=op)  # warm the code object
+        ms = nq.ubench_lds(layout, active, wpc, frames, iters, op=op)
         name, per_iter = UB_LDS_OPS[op]
         instr = cus * wpc * iters * per_iter
         row = {"layout": "interleaved" if layout == 0 else "contiguous", "op": name,
-               "waves_per_cu": wpc, "active_lanes": active, "frames": 10, "iters": iters,
+               "waves_per_cu": wpc, "active_lanes": active, "frames": frames, "iters": iters,
                "kernel_ms": ms, "lds_instr_per_cu_per_s": instr / cus / (ms / 1e3),
                "cycles_per_instr_per_cu_at_2_4GHz": 2.4e9 / (instr / cus / (ms / 1e3))}
         out["lds"].append(row)
         print(f"[bench] ubench lds {json.dumps(row)}", file=sys.stderr, flush=True)
 
+    # the write + read pair beyond 16 waves per CU: 5 frames (5 KB) per wave
+    for wpc in (8, 12, 16, 20, 24, 28, 32):
+        lds(0, 0, wpc, 64, frames=5)
+    if occupancy_only:
+        return out
     for layout in (0, 1):
         for wpc in (4, 8, 16):
             for active in (64, 32, 16):
@@ -544,7 +549,9 @@ ABLATION_PLAN = {
 }
 FORM_NAMES = {0: "registers, compiler-scheduled step", 1: "registers, hand-placed exec masks",
               2: "registers, negated untried set", 3: "registers, no selects (push, pop back)",
-              4: "frame re-read from LDS every step", 5: "registers, no last-row step"}
+              4: "frame re-read from LDS every step", 5: "registers, no last-row step",
+              6: "registers, no selects, push without exec mask",
+              7: "registers, no selects, push without exec mask, no sentinel frame"}
 
 
 def run_ablation(nq, torch, n):
@@ -595,7 +602,7 @@ def run_ablation(nq, torch, n):
         torch.cuda.empty_cache()
     best = min(out["depth_sweep"], key=lambda r: r["kernel_ms"])["depth"]
     t = device_frontier(nq, torch, dev, best, n)
-    for form in (1, 0, 2, 3, 4, 5):
+    for form in (7, 1, 0, 2, 3, 4, 5, 6):
         nq.set_loop_form(form)
         try:
             fm = best_of(t, best)
@@ -607,6 +614,40 @@ def run_ablation(nq, torch, n):
     del t
     torch.cuda.empty_cache()
     return out
+
+
+def run_form_sweep(nq, torch, spec, reps):
+    """Kernel time of the N=20 count for each (depth, inner-loop form, waves
+    per CU[, claim]) of `spec` ("k:form:waves[:claim],...", waves 0 = as many
+    as the LDS allows, claim 0 or absent = the library's block size),
+    `reps` launches each over one resident frontier per depth, every total
+    checked against Q(20); one JSON line per launch."""
+    dev = torch.device("cuda:0")
+    plan = [tuple(int(v) for v in x.split(":")) for x in spec.split(",") if x.strip()]
+    plan = [p if len(p) == 4 else p + (0,) for p in plan]
+    cur_k, t = None, None
+    try:
+        for k, form, waves, claim in sorted(plan, key=lambda x: x[0]):
+            if k != cur_k:
+                t = None
+                torch.cuda.empty_cache()
+                t = device_frontier(nq, torch, dev, k)
+                cur_k = k
+            nq.set_loop_form(form)
+            for rep in range(reps):
+                total = torch.zeros(1, dtype=torch.int64, device=dev)
+                _, _, ms = nq.count_subproblems(N, t[0], t[1], t[2], weight=t[3], counts=False,
+                                                total=total, depth=k, timing=True,
+                                                waves_per_cu=waves, claim=claim)
+                got = int(total.item())
+                if got != EXPECT:
+                    raise SystemExit(f"bench.py: sweep k={k} form={form} waves={waves}: "
+                                     f"{got} != {EXPECT}")
+                print(json.dumps({"n": N, "depth": k, "form": form, "waves_per_cu": waves,
+                                  "claim": claim, "rep": rep, "kernel_ms": round(ms, 2),
+                                  "exact": True}), flush=True)
+    finally:
+        nq.set_loop_form(-1)
 
 
 def cpu_baseline(k, budget_s):
@@ -684,6 +725,12 @@ def main():
                     help="only the serving loop at --serve-rates (one JSON line)")
     ap.add_argument("--ubench", action="store_true",
                     help="the VALU and LDS microbenchmarks behind the roofline, as one JSON line")
+    ap.add_argument("--form-sweep", default=None,
+                    help="k:form:waves,... - N=20 kernel time per depth, inner-loop form and "
+                         "waves per CU (0 = the LDS limit), --form-sweep-reps launches each")
+    ap.add_argument("--form-sweep-reps", type=int, default=2)
+    ap.add_argument("--ubench-lds-occupancy", action="store_true",
+                    help="only the LDS write + read pair at 8..32 waves per CU (one JSON line)")
     ap.add_argument("--ubench-counters", action="store_true",
                     help="one launch of each LDS layout and one VALU launch, for counter passes")
     ap.add_argument("--profile", action="store_true",
@@ -706,8 +753,12 @@ def main():
         res = [run_ablation(nq, torch, int(x)) for x in args.ablation_n.split(",") if x.strip()]
         print(json.dumps({"ablation": res}), flush=True)
         return
-    if args.ubench:
-        print(json.dumps({"ubench": run_ubench(nq, args)}), flush=True)
+    if args.form_sweep:
+        run_form_sweep(nq, torch, args.form_sweep, args.form_sweep_reps)
+        return
+    if args.ubench or args.ubench_lds_occupancy:
+        print(json.dumps({"ubench": run_ubench(nq, args, args.ubench_lds_occupancy)}),
+              flush=True)
         return
     if args.big_counts:
         known = known_counts()

@@ -397,8 +397,12 @@ int nq_tuned_lookup(uint32_t n, nq_tuned* out);
  * searched is replaced by a pop), 4 = the frame being expanded read from the
  * LDS stack at every step with its untried set written back (Algorithm 2 as
  * printed in Section 2, with the last-row step of Algorithm 3, Section
- * 3.2.3), 5 = form 0 without the last-row step (Algorithm 2 alone).  Forms 3,
- * 4 and 5 need one LDS frame more per lane.  *previous (nullable) receives the
+ * 3.2.3), 5 = form 0 without the last-row step (Algorithm 2 alone), 6 = form 3
+ * with a push that needs no exec mask (every lane writes the free slot above
+ * its stack), 7 = form 6 without the sentinel frame below each lane's stack
+ * (a lane whose search ends is parked in registers; the library's default).
+ * Forms 3 to 7 keep one LDS frame more per lane than forms 0 to 2; form 7 has
+ * no sentinel frame, one less than the others.  *previous (nullable) receives the
  * form in use.  NQ_EINVAL for any other form.
  * Process-wide; a launch keeps the form it was planned with (a server's epochs
  * or a batch plan made before the call keep theirs), so set it while no other

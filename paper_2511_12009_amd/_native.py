@@ -443,7 +443,7 @@ def count_resumable(n: int, path: str, chunks: int = 0, max_chunks: int = 0, dep
 
 def set_loop_form(form: int) -> int:
     """nq_set_loop_form: the DFS inner-loop form of launches planned from now on
-    (-1 = default; 0 to 5); returns the form that was in use."""
+    (-1 = default; 0 to 7); returns the form that was in use."""
     prev = ct.c_int(0)
     _check(lib().nq_set_loop_form(int(form), ct.byref(prev)), "nq_set_loop_form")
     return prev.value

@@ -11,10 +11,11 @@
 // frame with work and every loop trip places exactly one queen (one DFS node).
 //
 // LDS layout (the bank-conflict-free stack of Section 3.1, re-derived for a
-// 64-lane wave and 16-byte frames): wave w of a workgroup owns
-// (frames + 1) * 64 * 16 bytes; slot f of lane l is the 16-byte frame at index
-// (w * (frames + 1) + f) * 64 + l, slot 0 holding the lane's sentinel.  A
-// wave-wide ds_write_b128 / ds_read_b128 touches one 16-byte slot per lane,
+// 64-lane wave and 16-byte frames): wave w of a workgroup owns S * 64 * 16
+// bytes, S = the stack's frames plus, in every form but the default one, a
+// sentinel slot; slot f of lane l is the 16-byte frame at index
+// (w * S + f) * 64 + l, slot 0 holding the lane's sentinel where there is one.
+// A wave-wide ds_write_b128 / ds_read_b128 touches one 16-byte slot per lane,
 // and the slot's bank offset depends on l only (64 * 16 bytes is a multiple of
 // every bank-row size), so lanes at different depths never collide.
 //
@@ -41,10 +42,13 @@
 namespace nqi {
 
 // Default inner-loop form of the DFS kernels (see nq_dfs_kernel).
-constexpr int kDefaultLoop = 1;
-constexpr int kLoopForms = 6;          // forms 0..5
+constexpr int kDefaultLoop = 7;
+constexpr int kLoopForms = 8;          // forms 0..7
 // LDS frames per lane that a form needs beyond N - 2 - placed.
-constexpr uint32_t kFormExtraFrames[kLoopForms] = {0, 0, 0, 1, 1, 1};
+constexpr uint32_t kFormExtraFrames[kLoopForms] = {0, 0, 0, 1, 1, 1, 1, 1};
+// Sentinel slots per lane below its stack.  Form 7 parks a finished lane in
+// registers instead, which leaves each wave 1 KB more room for other waves.
+constexpr uint32_t kFormSentinel[kLoopForms] = {1, 1, 1, 1, 1, 1, 1, 0};
 
 
 // Serving: the wave's retirements, added to their requests.  A request's total
@@ -213,10 +217,36 @@ __device__ __forceinline__ void isa_take_lowest(uint32_t& v, uint32_t& p) {
         : [v] "+v"(v), [p] "=&v"(p), [n] "=&v"(neg));
 }
 
+// Forms 6 and 7's push: every lane writes its frame to [top + 1024], the slot
+// above its stack, which holds nothing (the lanes that do not push overwrite
+// free space).  No exec mask.
+__device__ __forceinline__ void isa_store_above(u32x4 st, int32_t top) {
+    asm volatile("ds_write_b128 %[top], %[st] offset:1024"
+                 : : [top] "v"(top), [st] "v"(st) : "memory");
+}
+
+// Lanes with a != 0, from a itself (one compare; the compiler would rather
+// recompute the OR of a's three sources, one instruction more).
+__device__ __forceinline__ uint64_t isa_nonzero(uint32_t a) {
+    uint64_t m;
+    asm("v_cmp_ne_u32 %0, 0, %1" : "=s"(m) : "v"(a));
+    return m;
+}
+
 // Select: d = m ? a : d per lane (v_cndmask with an SGPR lane mask).
 __device__ __forceinline__ uint32_t isa_sel(uint64_t m, uint32_t a, uint32_t d) {
     asm("v_cndmask_b32 %0, %0, %1, %2" : "+v"(d) : "v"(a), "s"(m));
     return d;
+}
+__device__ __forceinline__ uint32_t isa_sel_u(uint64_t m, uint32_t a, uint32_t d) {
+    uint32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(d), "v"(a), "s"(m));
+    return r;
+}
+__device__ __forceinline__ int32_t isa_sel_i(uint64_t m, int32_t a, int32_t d) {
+    int32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(d), "v"(a), "s"(m));
+    return r;
 }
 
 // sum += 1 for the lanes in `m` (carry-in add).
@@ -306,7 +336,8 @@ __device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, u
 // LOOP selects the inner-loop form: 0 = plain C++ (the compiler places the
 // exec masks), 1 = hand-placed exec masks, 2 = as 1 with the untried set kept
 // negated so that two lane masks come from carries, 3 = the step without
-// selects (see below).  Two
+// selects, 6 = form 3 with a push that needs no exec mask, 7 = form 6 without
+// the sentinel slot (the default; see below).  Two
 // more forms exist to measure the paper's own design choices: 4 keeps the
 // frame being expanded in the LDS stack too (read every step, its untried set
 // written back: Algorithm 2 as the paper prints it, with the last-row step of
@@ -318,17 +349,23 @@ __device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, u
 // of every other launch carries none of its code.  KINGS runs the second
 // search (n kings, one per row and column): the same stack, scheduler and
 // leaf test, with the next row's attacked squares taken from the placed king
-// alone (no diagonals carried down); it exists for the default form only.
+// alone (no diagonals carried down); it exists for form 1 only.
 template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP, bool SERVE, bool KINGS = false>
 __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
-    static_assert(!KINGS || LOOP == 1, "the kings search runs in the default form only");
+    static_assert(!KINGS || LOOP == 1, "the kings search runs in form 1 only");
+    constexpr bool F3 = LOOP == 3 || LOOP >= 6;      // the step without selects
+    constexpr bool SENT = kFormSentinel[LOOP] != 0u;
     extern __shared__ uint4 lds_stack[];
     const int32_t lds = (int32_t)(uint32_t)(uintptr_t)(lds_frame*)lds_stack;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
-    const int32_t floor = lds + (int32_t)(((wave * (P.frames + 1u)) * 64u + lane) * 16u);
-    int32_t top = floor;
-    *frame_at(floor) = u32x4{kParked, 0u, 0u, 0u};
+    // Slot 0 of the lane: its sentinel, or (form 6) its first frame; an empty
+    // stack has `top` one slot below it.
+    const int32_t floor =
+        lds + (int32_t)(((wave * (P.frames + kFormSentinel[LOOP])) * 64u + lane) * 16u);
+    const int32_t empty_top = SENT ? floor : floor - 1024;
+    int32_t top = empty_top;
+    if (SENT) *frame_at(floor) = u32x4{kParked, 0u, 0u, 0u};
 
     uint32_t c = kParked, l = 0, r = 0, v = 0, last = 0, nm1 = 0, step_k = 0;
     uint32_t leaf_lim = 0;                // form 3 with LEAFCTR: rd below this = leaf
@@ -367,28 +404,28 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         l = P.ld[i] & last;
         r = P.rd[i] & last;
         v = 0u;
-        top = floor;
+        top = empty_top;
         sum32 = 0; sum64 = 0; steps32 = 0; steps64 = 0;
         has_task = true;
         const uint32_t placed = __popc(c);
         const uint32_t avail = last & ~(c | l | r);
         step_k = LEAFCTR ? (1u << n) : 0u;
-        *frame_at(floor) = u32x4{kParked, 0u, 0u, 0u};
+        if (SENT) *frame_at(floor) = u32x4{kParked, 0u, 0u, 0u};
         if (bad_inst || n < 1u || n > NQ_MAX_N_WIDE) {
             sum64 = kCountInvalid;        // instance id or board size out of range
         } else if (placed >= nm1) {
             sum32 = (placed == n) ? 1u : __popc(avail);
         } else if (n - 2u - placed > P.frames - kFormExtraFrames[LOOP] ||
-                   (LEAFCTR && LOOP != 3 && nm1 - placed > (1u << (31u - n))) ||
-                   (LEAFCTR && LOOP == 3 && 2u * n - 1u - placed > 31u)) {
+                   (LEAFCTR && !F3 && nm1 - placed > (1u << (31u - n))) ||
+                   (LEAFCTR && F3 && 2u * n - 1u - placed > 31u)) {
             sum64 = kCountInvalid;        // does not fit this launch's stack or counter
         } else if (avail != 0u) {
             v = avail;
-            if (LOOP == 3) {
-                // form 3: the columns off the board count as taken, so the free
-                // squares of the next row are one 3-input NOR; with LEAFCTR a
-                // marker bit rides in rd, one place lower per row, and reaches
-                // bit n exactly in the frames of the last row
+            if (F3) {
+                // forms 3, 6 and 7: the columns off the board count as taken,
+                // so the free squares of the next row are one 3-input NOR; with
+                // LEAFCTR a marker bit rides in rd, one place lower per row,
+                // and reaches bit n exactly in the frames of the last row
                 c |= ~last;
                 if (LEAFCTR) {
                     r |= 1u << (2u * n - 1u - placed);
@@ -534,7 +571,7 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
             chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
             if (chunks == 0u || chunk_done(st.w)) break;
         }
-        } else if (LOOP == 3) {
+        } else if (LOOP == 3 || LOOP >= 6) {
         // Form 3: no selects.  Each step pushes the frame being expanded when
         // it still has an untried column, computes the child into the other
         // register frame, and pops when the child is not searched (no free
@@ -546,31 +583,72 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
         // counted: one LDS frame more than form 1.  Two register frames
         // alternate (two steps per trip), so the child is written without
         // moves and can be computed while the parent is being pushed.
+        //
+        // Form 6 is form 3 with a push that needs no exec mask.  At the start
+        // of a step a lane's stack holds at most the frames of the rows above
+        // the one being expanded, so the slot above its top is free and inside
+        // its column of the stack (the frame of row N-2, the deepest one
+        // pushed, is popped in the step that pushes it): every lane writes its
+        // frame there, and only the lanes with untried columns left advance
+        // `top`.  A pop reads from `top + 1024` in those lanes (a select made
+        // before the child is known) and from `top` in the others.  Two SALU
+        // instructions fewer per step than form 3, one VALU instruction more;
+        // the free squares are tested for zero directly (one compare instead
+        // of the OR of their three sources and a compare), and a loop trip
+        // runs four steps instead of two.
+        //
+        // Form 7 (the default) is form 6 without the sentinel slot: 1 KB of
+        // LDS per wave less (10 instead of 11 KB at N = 20, depth 9: 16
+        // resident waves per CU instead of 14).  A lane whose search ends
+        // (no untried column left, the child not searched, the stack empty)
+        // pops the slot above its empty stack, which holds the frame it has
+        // just written (no untried column: the `max` below keeps the address
+        // there), and a lane without an untried column takes every column as
+        // occupied, so its children have no free square and it never pushes,
+        // pops or counts again.  One select and one max per step more than
+        // form 6.
+        constexpr bool NOSENT = LOOP == 7;
+        constexpr bool UPUSH = LOOP == 6 || LOOP == 7;
         auto step3 = [&](u32x4& A, u32x4& B) {
             uint32_t p, rest = A.w;
             uint64_t alive;
             isa_take_alive(rest, p, alive);           // the untried rest keeps A.w's register
             A.w = rest;
             const uint64_t restm = __builtin_amdgcn_ballot_w64(A.w != 0u);
+            int32_t from = top;                       // forms 6 and 7: where a pop reads
+            if (NOSENT) {
+                // a lane without work computes a child with every column taken
+                // (no free square), and a pop from an empty stack reads the
+                // slot just written (its frame, with no untried column)
+                A.x = isa_sel_u(alive, A.x, ~0u);
+                from = isa_sel_i(restm, top + 1024, max(top, floor));
+            } else if (UPUSH) {
+                from = isa_sel_i(restm, top + 1024, top);
+            }
             B.x = A.x + p;                            // p is free: + is |
             B.y = (A.y + p) << 1;
             B.z = (A.z + p) >> 1;
             B.w = ~(B.x | B.y | B.z);                 // off-board columns are set in B.x
             const uint64_t leafm = __builtin_amdgcn_ballot_w64(
                 LEAFCTR ? B.z < leaf_lim : __popc(B.x) == 31u);
-            const uint64_t anym = __builtin_amdgcn_ballot_w64(B.w != 0u);
+            const uint64_t anym = UPUSH ? isa_nonzero(B.w) : __builtin_amdgcn_ballot_w64(B.w != 0u);
             if (STATS) isa_count(steps32, alive);
             isa_count(sum32, anym & leafm);
-            isa_push(A, top, restm);
-            isa_pop_free(B, top, alive & ~(anym & ~leafm));
+            if (UPUSH) isa_store_above(A, top); else isa_push(A, top, restm);
+            isa_pop_free(B, UPUSH ? from : top, alive & ~(anym & ~leafm));
+            if (UPUSH) top = from;
         };
         uint32_t chunks = __builtin_amdgcn_readfirstlane((P.refill_every + 63u) / 64u);
         u32x4 other;
         for (;;) {
-            uint32_t trips = 32u;
+            uint32_t trips = UPUSH ? 16u : 32u;       // 64 steps per chunk
             do {
                 step3(st, other);
                 step3(other, st);
+                if (UPUSH) {                          // four steps per trip
+                    step3(st, other);
+                    step3(other, st);
+                }
                 trips = __builtin_amdgcn_readfirstlane(trips - 1u);
             } while (trips != 0u);
             chunks = __builtin_amdgcn_readfirstlane(chunks - 1u);
@@ -755,7 +833,7 @@ static const void* select_kernel_loop(uint32_t mode, bool stats, bool leafctr, b
     if (serve) {
         if (!pers || stats) return nullptr;
         if (leafctr) return kernel_ptr<true, false, true, LOOP, true>();
-        return LOOP == 3 ? kernel_ptr<true, false, false, LOOP, true>() : nullptr;
+        return (LOOP == 3 || LOOP >= 6) ? kernel_ptr<true, false, false, LOOP, true>() : nullptr;
     }
     if (pers) {
         if (stats)
@@ -767,7 +845,7 @@ static const void* select_kernel_loop(uint32_t mode, bool stats, bool leafctr, b
     return leafctr ? kernel_ptr<false, false, true, LOOP>() : kernel_ptr<false, false, false, LOOP>();
 }
 
-// Inner-loop form of the launches planned from now on: NQ_DFS_LOOP=0..5 in the
+// Inner-loop form of the launches planned from now on: NQ_DFS_LOOP=0..7 in the
 // environment overrides the default, and set_loop_form (nq_set_loop_form) sets
 // it at run time (for measurements of the forms against each other).
 static std::atomic<int> g_loop_form{-1};
@@ -777,7 +855,7 @@ static int loop_form() {
     if (f >= 0) return f;
     const char* e = std::getenv("NQ_DFS_LOOP");
     f = kDefaultLoop;
-    if (e && e[0] >= '0' && e[0] <= '5' && e[1] == 0) f = e[0] - '0';
+    if (e && e[0] >= '0' && e[0] <= '7' && e[1] == 0) f = e[0] - '0';
     int expect = -1;
     g_loop_form.compare_exchange_strong(expect, f);
     return g_loop_form.load(std::memory_order_relaxed);
@@ -829,6 +907,8 @@ static const void* select_kernel(int form, uint32_t mode, bool stats, bool leafc
         case 3: return select_kernel_loop<3>(mode, stats, leafctr, serve);
         case 4: return select_kernel_loop<4>(mode, stats, leafctr, serve);
         case 5: return select_kernel_loop<5>(mode, stats, leafctr, serve);
+        case 6: return select_kernel_loop<6>(mode, stats, leafctr, serve);
+        case 7: return select_kernel_loop<7>(mode, stats, leafctr, serve);
         default: return nullptr;
     }
 }
@@ -871,18 +951,18 @@ int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t
     const int form = kings ? 1 : loop_form();
     // form 3's marker starts at bit 2n - 1 - placed = n + 1 + (frames of the
     // entry): it fits in 32 bits for every entry when max_n + frames <= 30
-    if (form == 3) leafctr = leafctr && max_n + frames <= 30u;
+    if (form == 3 || form >= 6) leafctr = leafctr && max_n + frames <= 30u;
     frames += kFormExtraFrames[form];
     if (wg_size == 0) {
         // Plain: up to 4 waves per workgroup, as many as the LDS stacks allow.
-        const uint64_t per_wave = 64ull * (frames + 1u) * 16u;
+        const uint64_t per_wave = 64ull * (frames + kFormSentinel[form]) * 16u;
         const uint64_t fit = per_wave ? (uint64_t)dev.lds_per_block / per_wave : 4;
         wg_size = (mode == NQ_MODE_PLAIN) ? 64u * (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(4, fit))
                                           : 64u;
     }
     if (wg_size % 64u != 0 || wg_size > 1024u) return NQ_EINVAL;
-    // One sentinel frame per lane below its stack.
-    const uint64_t lds = (uint64_t)wg_size * (frames + 1u) * 16u;
+    // The frames, and (all forms but 6) one sentinel frame per lane below them.
+    const uint64_t lds = (uint64_t)wg_size * (frames + kFormSentinel[form]) * 16u;
     if (lds > (uint64_t)dev.lds_per_block) return NQ_EINVAL;
     cfg->mode = mode;
     cfg->wg_size = wg_size;
@@ -959,7 +1039,9 @@ int launch_dfs(const LaunchCfg& cfg, const DfsParams& P, void* stream) {
     if (!fn) return NQ_EINVAL;
     DfsParams Q = P;
     Q.frames += kFormExtraFrames[cfg.form];
-    if ((uint64_t)cfg.lds_bytes < (uint64_t)cfg.wg_size * (Q.frames + 1u) * 16u) return NQ_EINVAL;
+    if ((uint64_t)cfg.lds_bytes <
+        (uint64_t)cfg.wg_size * (Q.frames + kFormSentinel[cfg.form]) * 16u)
+        return NQ_EINVAL;
     if (cfg.mode == NQ_MODE_PERSISTENT) {
         int rc = launch_zero_u64(P.head, 1, stream);
         if (rc != NQ_OK) return rc;

@@ -208,14 +208,16 @@ def test_loop_form_setter_validates_and_restores():
     prev = nq.set_loop_form(-1)
     default = nq.set_loop_form(-1)
     try:
-        assert default in (1, 3)
-        for bad in (-2, 6, 100):
+        assert default in (1, 3, 7)
+        for bad in (-2, 8, 100):
             with pytest.raises(nq.NQError):
                 nq.set_loop_form(bad)
         assert nq.set_loop_form(4) == default
         assert nq.set_loop_form(3) == 4
         assert nq.set_loop_form(5) == 3
-        assert nq.set_loop_form(-1) == 5
+        assert nq.set_loop_form(6) == 5
+        assert nq.set_loop_form(7) == 6
+        assert nq.set_loop_form(-1) == 7
         assert nq.set_loop_form(-1) == default
     finally:
         nq.set_loop_form(prev)

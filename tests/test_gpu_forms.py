@@ -1,10 +1,12 @@
 """GPU parity of every inner-loop form of the DFS kernel (nq_set_loop_form):
 the compiler-scheduled step (0), the hand-placed exec masks (1), the
 negated-untried-set form (2), the step without selects (3), the paper's loop
-with the frame read from the LDS stack at every step (4) and the step without
-the last-row shortcut (5) give the oracle's counts and node counts, in plain
+with the frame read from the LDS stack at every step (4), the step without
+the last-row shortcut (5), form 3 with a push that needs no exec mask (6) and
+form 6 without the sentinel frame below each lane's stack (7, the default)
+give the oracle's counts and node counts, in plain
 and persistent launches, batches and the serving loop, with the row counter
-(form 3: the rd marker) and with the popcount leaf test."""
+(forms 3, 6 and 7: the rd marker) and with the popcount leaf test."""
 import hashlib
 
 import numpy as np
@@ -17,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-FORMS = [0, 1, 2, 3, 4, 5]
+FORMS = [0, 1, 2, 3, 4, 5, 6, 7]
 
 
 def _say(*a):
@@ -111,9 +113,9 @@ def test_batch_and_serving(nq_form, known_counts):
 
 def test_shallow_promise_uses_popcount_leaf_test(nq_form):
     """Entries of the N=18 depth-6 frontier counted under a promise of only 2
-    queens placed: the launch sizes its stack for 14 frames, and form 3 cannot
-    use its rd marker for such entries (n + frames > 30), so its popcount leaf
-    test runs; counts and node counts equal the oracle's per entry."""
+    queens placed: the launch sizes its stack for 14 frames, and forms 3, 6 and
+    7 cannot use their rd marker for such entries (n + frames > 30), so their
+    popcount leaf test runs; counts and node counts equal the oracle's per entry."""
     nq, form = nq_form
     n, k = 18, 6
     pre_all, _ = oracle.frontier(n, k)
