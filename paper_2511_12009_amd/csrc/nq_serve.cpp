@@ -95,9 +95,12 @@ struct nq_server {
     nqi::DeviceInfo devinfo{};
     // Launch shape of an epoch whose deepest subproblem needs f stack frames
     // (planned on first use): the LDS stack, and so the waves per CU, is sized
-    // for the requests in the epoch, not for the server's limit.
-    nqi::LaunchCfg cfg_by_frames[NQ_MAX_N + 1] = {};
-    bool cfg_ready[NQ_MAX_N + 1] = {};
+    // for the requests in the epoch, not for the server's limit.  Index 1 of
+    // the first dimension: the epoch's boards are small enough for the row
+    // marker of the default step (largest board + f <= 30); index 0: any
+    // board (the kernel then tests the last row with a popcount).
+    nqi::LaunchCfg cfg_by_frames[2][NQ_MAX_N + 1] = {};
+    bool cfg_ready[2][NQ_MAX_N + 1] = {};
 
     // device memory
     void* dev = nullptr;
@@ -290,6 +293,11 @@ int admit_and_launch(nq_server* s, const std::vector<Candidate>& cand, std::vect
     Epoch ep;
     const uint64_t epoch_start = s->ring_tail;
     uint32_t frames = 0;                                  // deepest stack of the epoch
+    // Whether every request of the epoch fits the default step's row marker
+    // (board + its stack frames <= 30).  An epoch keeps to one kind: a run
+    // of small requests is not made to test its last row by popcount because
+    // a large one arrived among them; the large one starts the next epoch.
+    bool small_epoch = true;
     struct Copy { const Resident* res; uint64_t src, pos, len; uint32_t slot; };
     std::vector<Copy> copies;
     size_t idx = 0;
@@ -316,12 +324,16 @@ int admit_and_launch(nq_server* s, const std::vector<Candidate>& cand, std::vect
         if (F > s->ring_cap) { finish(NQ_ENOMEM, 0); continue; }  // can never fit
         if (s->ring_tail + F - s->ring_head > s->ring_cap) break;   // wait for space
         if (F == 0) { finish(NQ_OK, 0); continue; }       // nothing to search
+        const uint32_t fr = frames_needed(c.rq.n, c.depth + res->rows);
+        const bool small = c.rq.n + fr <= 30u;
+        if (!copies.empty() && small != small_epoch) break;   // the next epoch takes it
+        small_epoch = small;
         const uint32_t slot = s->free_slots.back();
         s->free_slots.pop_back();
         const uint32_t gen = ++s->slot_gen[slot];
         const uint64_t start = s->ring_tail;
         s->ring_tail += F;
-        frames = std::max(frames, frames_needed(c.rq.n, c.depth + res->rows));
+        frames = std::max(frames, fr);
         ep.inits.push_back({slot, c.rq.n, (uint32_t)F, gen});
         copies.push_back({res, src, start, F, slot});
         out->push_back({c.ticket, NQ_OK, true, 0, F, start, F, slot, gen, now_ns()});
@@ -379,14 +391,18 @@ int admit_and_launch(nq_server* s, const std::vector<Candidate>& cand, std::vect
     P.inst_gen = s->s_gen;
     P.host_val = s->d_val;
     P.host_flag = s->d_flag;
-    if (!s->cfg_ready[frames]) {
+    // plan_launch keeps the marker when its largest board + frames <= 30;
+    // here each request was checked against its own frames above
+    const int small = small_epoch ? 1 : 0;
+    if (!s->cfg_ready[small][frames]) {
         if ((rc = plan_launch(s->devinfo, NQ_MODE_PERSISTENT, s->launch.wg_size,
                               s->launch.waves_per_cu, frames, 1, false, true,
-                              &s->cfg_by_frames[frames], true)) != NQ_OK)
+                              &s->cfg_by_frames[small][frames], true, false,
+                              small ? 30u - frames : NQ_MAX_N_WIDE)) != NQ_OK)
             return rc;
-        s->cfg_ready[frames] = true;
+        s->cfg_ready[small][frames] = true;
     }
-    LaunchCfg cfg = s->cfg_by_frames[frames];
+    LaunchCfg cfg = s->cfg_by_frames[small][frames];
     const uint64_t waves = (n_entries + 63) / 64;
     const uint64_t per_wg = cfg.wg_size / 64u;
     cfg.grid = (uint32_t)std::min<uint64_t>(cfg.grid, (waves + per_wg - 1) / per_wg);
@@ -545,9 +561,9 @@ int serve_create(const nq_opts* opts, uint64_t hbm_budget, nq_server** out) {
     // refused at creation.
     if ((rc = plan_launch(s->devinfo, NQ_MODE_PERSISTENT, s->launch.wg_size,
                           s->launch.waves_per_cu, s->max_frames, 1, false, true,
-                          &s->cfg_by_frames[s->max_frames], true)) != NQ_OK)
+                          &s->cfg_by_frames[0][s->max_frames], true)) != NQ_OK)
         return fail(rc);
-    s->cfg_ready[s->max_frames] = true;
+    s->cfg_ready[0][s->max_frames] = true;
     const uint64_t R = s->ring_cap, S = s->max_slots;
     const size_t o_ld = R * 4, o_rd = R * 8, o_inst = R * 12, o_w = R * 16;
     const size_t o_sn = (o_w + R + 255) / 256 * 256, o_rem = o_sn + S * 4, o_gen = o_rem + S * 4;
