@@ -472,7 +472,7 @@ UB_LDS_OPS = {0: ("write b128 + read b128", 2), 1: ("read b128", 1), 2: ("write 
               3: ("exchange 16 B (wrxchg2_rtn_b64)", 1), 4: ("write b64 + read b64", 2),
               5: ("write b32 + read b32", 2), 6: ("write b64", 1), 7: ("write b32", 1),
               8: ("write b96", 1), 9: ("write 16 B as write2_b64", 1), 10: ("read b96", 1),
-              11: ("read 16 B as read2_b64", 1)}
+              11: ("read 16 B as read2_b64", 1), 12: ("write b96 + read b96", 2)}
 
 
 def run_ubench(nq, args, occupancy_only=False):
@@ -517,9 +517,11 @@ def run_ubench(nq, args, occupancy_only=False):
         out["lds"].append(row)
         print(f"[bench] ubench lds {json.dumps(row)}", file=sys.stderr, flush=True)
 
-    # the write + read pair beyond 16 waves per CU: 5 frames (5 KB) per wave
-    for wpc in (8, 12, 16, 20, 24, 28, 32):
-        lds(0, 0, wpc, 64, frames=5)
+    # the write + read pairs beyond 16 waves per CU: 5 frames (5 KB) per wave;
+    # 16-byte frames (the stack's), 12- and 8-byte frames for comparison
+    for op in (0, 12, 4):
+        for wpc in (8, 12, 16, 20, 24, 28, 32):
+            lds(0, op, wpc, 64, frames=5)
     if occupancy_only:
         return out
     for layout in (0, 1):

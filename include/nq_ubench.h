@@ -50,13 +50,14 @@ int nq_ubench_valu(uint32_t op, uint32_t chains, uint32_t waves_per_simd, uint64
  * one it replaces); 4 = as 0 with 8-byte accesses (b64); 5 = as 0 with 4-byte
  * accesses (b32); 6 = write b64 only; 7 = write b32 only; 8 = write b96 only;
  * 9 = write 16 bytes as ds_write2_b64 (two adjacent qwords) only; 10 = read
- * b96 only; 11 = read 16 bytes as ds_read2_b64 only; each iteration waits for
- * its accesses.  layout 0 =
+ * b96 only; 11 = read 16 bytes as ds_read2_b64 only; 12 = as 0 with 12-byte
+ * accesses (b96) in the same 16-byte slots; each iteration waits for its
+ * accesses.  layout 0 =
  * lane-interleaved (frame f of lane l at byte (f * 64 + l) * 16, the DFS
  * kernel's stack), 1 = per-lane contiguous (lane l's frames at
  * (l * frames + f) * 16).  *kernel_ms = the launch's event time.  LDS
- * instructions = CUs * waves_per_cu * iters * (2 for ops 0, 4, 5; 1 else).
- * op in [0, 11].
+ * instructions = CUs * waves_per_cu * iters * (2 for ops 0, 4, 5, 12; 1 else).
+ * op in [0, 12].
  */
 int nq_ubench_lds(uint32_t layout, uint32_t op, uint32_t active_lanes, uint32_t waves_per_cu,
                   uint32_t frames, uint64_t iters, double* kernel_ms);

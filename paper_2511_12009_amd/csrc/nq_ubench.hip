@@ -91,7 +91,8 @@ __global__ __launch_bounds__(64) void ubench_valu_kernel(uint64_t iters, uint32_
 // 16-byte exchange (ds_wrxchg2_rtn_b64 of two adjacent qwords at wa), 4 =
 // write b64 + read b64, 5 = write b32 + read b32, 6 = write b64, 7 = write
 // b32, 8 = write b96, 9 = 16 bytes as ds_write2_b64 (two adjacent qwords),
-// 10 = read b96, 11 = 16 bytes as ds_read2_b64.
+// 10 = read b96, 11 = 16 bytes as ds_read2_b64, 12 = write b96 + read b96 (a
+// 12-byte frame in the same 16-byte slots).
 template <int OP>
 __device__ __forceinline__ void lds_op(v4u& v, int32_t wa, int32_t ra) {
     if (OP == 0) {
@@ -148,11 +149,18 @@ __device__ __forceinline__ void lds_op(v4u& v, int32_t wa, int32_t ra) {
         asm volatile("ds_read_b96 %[x], %[ra]\n\ts_waitcnt lgkmcnt(0)"
                      : [x] "=v"(x) : [ra] "v"(ra) : "memory");
         v.x = x.x; v.y = x.y; v.z = x.z;
-    } else {
+    } else if (OP == 11) {
         v4u x;
         asm volatile("ds_read2_b64 %[x], %[ra] offset1:1\n\ts_waitcnt lgkmcnt(0)"
                      : [x] "=v"(x) : [ra] "v"(ra) : "memory");
         v = x;
+    } else {
+        typedef uint32_t v3u __attribute__((ext_vector_type(3)));
+        v3u x = {v.x, v.y, v.z};
+        asm volatile("ds_write_b96 %[wa], %[x]\n\tds_read_b96 %[x], %[ra]\n\ts_waitcnt lgkmcnt(0)"
+                     : [x] "+v"(x) : [wa] "v"(wa), [ra] "v"(ra) : "memory");
+        v.x = x.x; v.y = x.y; v.z = x.z;
+        v.w += v.x;
     }
 }
 
@@ -275,7 +283,7 @@ extern "C" int nq_ubench_valu(uint32_t op, uint32_t chains, uint32_t waves_per_s
 extern "C" int nq_ubench_lds(uint32_t layout, uint32_t op, uint32_t active_lanes,
                              uint32_t waves_per_cu, uint32_t frames, uint64_t iters,
                              double* kernel_ms) {
-    if (layout > 1 || op > 11 || active_lanes < 1 || active_lanes > 64 || waves_per_cu < 1 ||
+    if (layout > 1 || op > 12 || active_lanes < 1 || active_lanes > 64 || waves_per_cu < 1 ||
         waves_per_cu > 32 || frames < 2 || frames > 32 || iters == 0 || !kernel_ms)
         return NQ_EINVAL;
     DeviceInfo dev;
@@ -299,7 +307,8 @@ extern "C" int nq_ubench_lds(uint32_t layout, uint32_t op, uint32_t active_lanes
                          reinterpret_cast<const void*>(&ubench_lds_kernel<8>),
                          reinterpret_cast<const void*>(&ubench_lds_kernel<9>),
                          reinterpret_cast<const void*>(&ubench_lds_kernel<10>),
-                         reinterpret_cast<const void*>(&ubench_lds_kernel<11>)};
+                         reinterpret_cast<const void*>(&ubench_lds_kernel<11>),
+                         reinterpret_cast<const void*>(&ubench_lds_kernel<12>)};
     double ms = 0.0;
     rc = timed_launch(fns[op], grid, lds, args, &ms);
     (void)hipFree(sink);

@@ -369,7 +369,7 @@ def test_ubench_arguments_are_checked_before_any_device_work():
                                    (0, 8, 1, 0), (0, 8, 1, 12)):
         assert L.nq_ubench_valu(op, chains, wps, iters, ct.byref(d1), ct.byref(d2)) == -1
     assert L.nq_ubench_valu(0, 8, 1, 8, None, ct.byref(d2)) == -1
-    for layout, op, active, wpc, frames in ((2, 0, 64, 4, 10), (0, 12, 64, 4, 10),
+    for layout, op, active, wpc, frames in ((2, 0, 64, 4, 10), (0, 13, 64, 4, 10),
                                             (0, 0, 0, 4, 10), (0, 0, 65, 4, 10),
                                             (0, 0, 64, 0, 10), (0, 0, 64, 33, 10),
                                             (0, 0, 64, 4, 1), (0, 0, 64, 4, 33)):
