@@ -531,7 +531,10 @@ int nq_serve_destroy(nq_server* server);
  *
  * nq_perm_count_subproblems: counts below `len` device-resident entries
  * d_cols (used-column sets with exactly `depth` rows assigned; the launch's
- * stack is sized for n - 3 - depth frames, and an entry that needs more is
+ * stack is sized for the n - 3 - depth frames such an entry needs (one more
+ * with the default hand-scheduled step, whose frame of row n - 3 is written
+ * before its leaves are counted; NQ_PERM_STEP=0 in the environment selects
+ * the plain C++ step, for measurement), and an entry that needs more is
  * reported as UINT64_MAX in d_counts and left out of the total).  d_counts
  * (nullable, uint64[len]) receives each entry's count, *d_total (nullable) is
  * increased by their sum; opts: mode, wg_size, waves_per_cu, refill_every,

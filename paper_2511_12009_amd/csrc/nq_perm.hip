@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -76,13 +77,93 @@ __device__ __forceinline__ uint32_t two_rows(uint32_t left, uint32_t ra, uint32_
     return __popc(a & swapped);
 }
 
-template <bool PERSISTENT, bool STATS>
+// The hand-scheduled step (STEP 1) moves frames with these blocks; each one
+// that switches exec declares SCC clobbered (its SALU instructions write it).
+
+// p = lowest untried column of w, w loses it (in place), alive = lanes whose w
+// was not empty (the borrow of 0 - w).
+__device__ __forceinline__ void perm_take(uint32_t& w, uint32_t& p, uint64_t& alive) {
+    uint32_t neg;
+    asm("v_sub_co_u32 %[n], %[al], 0, %[w]\n\t"
+        "v_and_b32 %[p], %[w], %[n]\n\t"
+        "v_xor_b32 %[w], %[w], %[p]"
+        : [w] "+v"(w), [p] "=&v"(p), [n] "=&v"(neg), [al] "=&s"(alive));
+}
+
+// Lanes with a != 0 (one compare).
+__device__ __forceinline__ uint64_t perm_nonzero(uint32_t a) {
+    uint64_t m;
+    asm("v_cmp_ne_u32 %0, 0, %1" : "=s"(m) : "v"(a));
+    return m;
+}
+
+// m ? a : d per lane.
+__device__ __forceinline__ int32_t perm_sel(uint64_t m, int32_t a, int32_t d) {
+    int32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(d), "v"(a), "s"(m));
+    return r;
+}
+
+// Every lane writes its frame to the slot above its stack top (free space in
+// the lanes that do not push).  No exec mask.
+__device__ __forceinline__ void perm_store_above(u32x2 f, int32_t top) {
+    asm volatile("ds_write_b64 %[top], %[f] offset:512" : : [top] "v"(top), [f] "v"(f) : "memory");
+}
+
+// Pop for the lanes in m: frame <- [from], from -= one slot; waited for.
+__device__ __forceinline__ void perm_pop(u32x2& f, int32_t& from, uint64_t m) {
+    uint64_t sv;
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[m]\n\t"
+        "ds_read_b64 %[f], %[from]\n\t"
+        "v_add_u32 %[from], 0xfffffe00, %[from]\n\t"
+        "s_mov_b64 exec, %[sv]\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : [f] "+v"(f), [from] "+v"(from), [sv] "=&s"(sv)
+        : [m] "s"(m)
+        : "memory", "scc");
+}
+
+// For the lanes in m, sum += the completions of the last two rows (two_rows
+// below): B = rb & left; swapped = left ^ B when B holds one of the two
+// columns, else B; sum += popc(ra & swapped) (swapped lies inside left).
+__device__ __forceinline__ void perm_leaf(uint32_t& sum, uint32_t left, uint32_t ra,
+                                          uint32_t rb, uint64_t m) {
+    uint64_t sv;
+    uint32_t b, t, u;
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[m]\n\t"
+        "v_and_b32 %[b], %[rb], %[left]\n\t"
+        "v_bcnt_u32_b32 %[t], %[b], 0\n\t"
+        "v_cmp_eq_u32 vcc, 1, %[t]\n\t"
+        "v_cndmask_b32 %[u], 0, %[left], vcc\n\t"
+        "v_bitop3_b32 %[t], %[u], %[ra], %[b] bitop3:0x48\n\t"   // ra & (u ^ b)
+        "v_bcnt_u32_b32 %[sum], %[t], %[sum]\n\t"
+        "s_mov_b64 exec, %[sv]"
+        : [sum] "+v"(sum), [sv] "=&s"(sv), [b] "=&v"(b), [t] "=&v"(t), [u] "=&v"(u)
+        : [m] "s"(m), [left] "v"(left), [ra] "v"(ra), [rb] "v"(rb)
+        : "vcc", "scc");
+}
+
+// STEP selects the inner loop: 0 = the step in plain C++ (the compiler places
+// the exec masks and selects), 1 = hand-scheduled (the default): two register
+// frames alternate, the child is computed into the other one, every lane
+// writes its frame to the free slot above its stack (the lanes with an
+// untried column left advance the stack pointer), and a lane whose child is
+// not searched (no allowed column, or the last two rows reached) pops, which
+// returns the frame just written when it had an untried column left; the
+// next row's allowed columns are read from LDS before the child is known (the
+// child's row is one more than the frame's), and the last two rows'
+// completions are counted under an exec mask.  Step 1 needs one frame more
+// per lane (the frame of row n - 3 is written before its leaves are counted).
+template <bool PERSISTENT, bool STATS, int STEP>
 __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
+    constexpr uint32_t extra = STEP == 1 ? 1u : 0u;
     extern __shared__ u32x2 perm_stack[];
-    // the matrix's rows; row 32 (the "next row" of a parked lane, whose used
-    // set has all 32 bits) allows nothing
-    __shared__ uint32_t mrows[33];
-    if (threadIdx.x < 33) mrows[threadIdx.x] = threadIdx.x < P.n ? P.rows[threadIdx.x] : 0u;
+    // the matrix's rows; rows 32 and 33 (the "next row" of a parked lane,
+    // whose used set has all 32 bits) allow nothing
+    __shared__ uint32_t mrows[34];
+    if (threadIdx.x < 34) mrows[threadIdx.x] = threadIdx.x < P.n ? P.rows[threadIdx.x] : 0u;
     __syncthreads();
     const uint32_t lds = (uint32_t)(uintptr_t)(lds_frame2*)perm_stack;
     const uint32_t lane = threadIdx.x & 63u;
@@ -126,7 +207,7 @@ __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
             sum = __popc(rb & ~c & board);             // the last row
         } else if (placed + 2u == n) {
             sum = two_rows(~c & board, ra, rb);        // the last two rows
-        } else if (n - 3u - placed > P.frames) {
+        } else if (n - 3u - placed > P.frames - extra) {
             sum = kCountInvalid;                       // does not fit this launch's stack
         } else {
             v = mrows[placed] & ~c & board;
@@ -158,10 +239,49 @@ __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
         }
         // ---- DFS steps: place the lowest untried column of the current row.
         // A parked lane (sentinel popped) has every column used and nothing
-        // untried: p = 0, its "next row" is 32 (read as row 0: nothing allowed
-        // that is unused), no leaf, no descent, and its pops read the sentinel
-        // again (top stays at floor).  A board of n <= 2 never gets here (its
-        // entries are settled when taken), so leaf_row never wraps into use.
+        // untried: p = 0, its "next row" is 32 (33 in step 1), which allows
+        // nothing, no leaf, no descent; in step 0 its pops read the sentinel
+        // again (top stays at floor), in step 1 it does not pop.  A board of
+        // n <= 2 never gets here (its entries are settled when taken), so
+        // leaf_row never wraps into use.
+        if (STEP == 1) {
+            auto step = [&](u32x2& A, u32x2& B) {
+                const uint32_t row = __popc(A.x) + 1u;     // the child's row
+                const uint32_t mrow = mrows[row];
+                uint32_t p, rest = A.y;
+                uint64_t alive;
+                perm_take(rest, p, alive);
+                A.y = rest;
+                const uint64_t restm = __builtin_amdgcn_ballot_w64(rest != 0u);
+                int32_t from = perm_sel(restm, top + stride, top);   // where a pop reads
+                B.x = A.x | p;
+                const uint32_t left = board & ~B.x;        // unused columns
+                B.y = mrow & left;
+                const uint64_t leafm = __builtin_amdgcn_ballot_w64(row == leaf_row);
+                const uint64_t anym = perm_nonzero(B.y);
+                if (STATS) steps += (p != 0u) ? 1u : 0u;
+                perm_leaf(sum32, left, ra, rb, leafm & alive);
+                perm_store_above(A, top);
+                perm_pop(B, from, alive & ~(anym & ~leafm));
+                top = from;
+            };
+            u32x2 st = {c, v}, other;
+            for (uint32_t it = 0; it < P.refill_every; it += 32u) {
+                for (int s = 0; s < 8; ++s) {
+                    step(st, other);
+                    step(other, st);
+                    step(st, other);
+                    step(other, st);
+                }
+                const uint64_t idle = __ballot(st.y == 0u);
+                const uint32_t lanes = (uint32_t)__popcll(__ballot(true));
+                const uint32_t nidle = (uint32_t)__popcll(idle);
+                if (nidle == lanes || (PERSISTENT && !exhausted && nidle >= P.idle_min)) break;
+            }
+            c = st.x;
+            v = st.y;
+            continue;
+        }
         for (uint32_t it = 0; it < P.refill_every; it += 32u) {
             for (int s = 0; s < 32; ++s) {
                 const uint32_t p = v & (0u - v);
@@ -200,12 +320,28 @@ __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
     }
 }
 
-const void* perm_kernel(bool persistent, bool stats) {
+template <int STEP>
+const void* perm_kernel_step(bool persistent, bool stats) {
     if (persistent)
-        return stats ? reinterpret_cast<const void*>(&nq_perm_kernel<true, true>)
-                     : reinterpret_cast<const void*>(&nq_perm_kernel<true, false>);
-    return stats ? reinterpret_cast<const void*>(&nq_perm_kernel<false, true>)
-                 : reinterpret_cast<const void*>(&nq_perm_kernel<false, false>);
+        return stats ? reinterpret_cast<const void*>(&nq_perm_kernel<true, true, STEP>)
+                     : reinterpret_cast<const void*>(&nq_perm_kernel<true, false, STEP>);
+    return stats ? reinterpret_cast<const void*>(&nq_perm_kernel<false, true, STEP>)
+                 : reinterpret_cast<const void*>(&nq_perm_kernel<false, false, STEP>);
+}
+
+// The inner loop of later launches: NQ_PERM_STEP=0 in the environment selects
+// the plain C++ step (for measurement), otherwise the hand-scheduled one.
+int perm_step() {
+    static const int step = [] {
+        const char* e = std::getenv("NQ_PERM_STEP");
+        return (e && e[0] == '0' && e[1] == 0) ? 0 : 1;
+    }();
+    return step;
+}
+
+const void* perm_kernel(bool persistent, bool stats, int step) {
+    return step == 1 ? perm_kernel_step<1>(persistent, stats)
+                     : perm_kernel_step<0>(persistent, stats);
 }
 
 // Rows of an n x n matrix: every bit is a column of the board.
@@ -267,14 +403,16 @@ int perm_run(uint32_t n, const uint32_t* rows, const uint32_t* d_cols, uint64_t 
     int rc = device_info(&dev);
     if (rc != NQ_OK) return rc;
     // frames for rows depth..n-4 (the current frame is in registers and the
-    // last two rows are never entered)
-    const uint32_t frames = std::max<uint32_t>(1, n >= depth + 3u ? n - 3u - depth : 0u);
+    // last two rows are never entered), plus step 1's frame of row n - 3
+    const int step = perm_step();
+    const uint32_t frames = std::max<uint32_t>(1, n >= depth + 3u ? n - 3u - depth : 0u) +
+                            (step == 1 ? 1u : 0u);
     uint32_t wg = opts && opts->wg_size ? opts->wg_size : 64u;
     if (wg % 64u != 0 || wg > 1024u) return NQ_EINVAL;
     const uint64_t lds = (uint64_t)wg * (frames + 1u) * kPermFrameBytes;
-    if (lds + 33u * 4u > (uint64_t)dev.lds_per_block) return NQ_EINVAL;   // + the matrix
+    if (lds + 34u * 4u > (uint64_t)dev.lds_per_block) return NQ_EINVAL;   // + the matrix
     const bool stats = opts && opts->d_nodes;
-    const void* fn = perm_kernel(mode == NQ_MODE_PERSISTENT, stats);
+    const void* fn = perm_kernel(mode == NQ_MODE_PERSISTENT, stats, step);
     uint32_t grid = 0;
     if (mode == NQ_MODE_PLAIN) {
         const uint64_t g = (len + wg - 1) / wg;
