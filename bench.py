@@ -235,14 +235,25 @@ def bench_kings(nq, n=16):
     """The second search on the same engine: n non-attacking kings, one per row
     and column, automatic depth (host frontier), one persistent launch."""
     want = kings_count(n)
-    best = None
-    for _ in range(2):
-        got, ms = nq.count(n, kings=True, timing=True)
-        if got != want:
-            raise SystemExit(f"bench.py: kings({n}) = {got}, not {want}")
-        best = ms if best is None else min(best, ms)
+
+    def best_ms():
+        best = None
+        for _ in range(2):
+            got, ms = nq.count(n, kings=True, timing=True)
+            if got != want:
+                raise SystemExit(f"bench.py: kings({n}) = {got}, not {want}")
+            best = ms if best is None else min(best, ms)
+        return best
+
+    best = best_ms()                      # the default step (form 7, popcount leaf test)
+    nq.set_loop_form(1)                   # the kings run form 1 while the queens do
+    try:
+        form1 = best_ms()
+    finally:
+        nq.set_loop_form(-1)
     return {"n": n, "solutions": want, "kernel_ms": best, "solutions_per_s": want / (best / 1e3),
-            "exact": True, "form": "kings search on the queens lane-stack engine (NQ_FLAG_KINGS)"}
+            "form1_kernel_ms": form1, "exact": True,
+            "form": "kings search on the queens lane-stack engine (NQ_FLAG_KINGS), step of form 7"}
 
 
 def perm_stored():
@@ -692,6 +703,8 @@ def main():
                     help="only the permanent search (third DFS workload; one JSON line)")
     ap.add_argument("--perm-depths", default="7,8,9,10", help="with --perm-only: depths")
     ap.add_argument("--perm-reps", type=int, default=3, help="with --perm-only: timed runs")
+    ap.add_argument("--kings-only", type=int, default=0, metavar="N",
+                    help="only the kings search on an N x N board (second DFS workload; one JSON line)")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
@@ -808,6 +821,9 @@ def main():
         depths = tuple(int(x) for x in args.perm_depths.split(",") if x.strip())
         print(json.dumps({"perm": bench_perm(nq, torch, depths=depths, reps=args.perm_reps)}),
               flush=True)
+        return
+    if args.kings_only:
+        print(json.dumps({"kings": bench_kings(nq, args.kings_only)}), flush=True)
         return
     if args.serving_only:
         rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]

@@ -154,8 +154,9 @@ enum nq_flags {
      * candidates for its method).  A king attacks only the adjacent row, so the
      * Somers triple of an entry is (columns taken, the square right of the last
      * king, the square left of it), as nq_kings_frontier writes it.  It runs
-     * inner-loop form 1 whatever form nq_set_loop_form selects; batches,
-     * servers and resumable counts refuse the flag (NQ_EINVAL). */
+     * the step of inner-loop form 1 while nq_set_loop_form selects form 1, and
+     * the step of form 7 with the popcount leaf test under every other form;
+     * batches, servers and resumable counts refuse the flag (NQ_EINVAL). */
     NQ_FLAG_KINGS = 2u,
     /* nq_count_subproblems: d_total is uint64[2], a 128-bit total (low word
      * first) increased with carry.  Required when n > 28 and d_total is set:

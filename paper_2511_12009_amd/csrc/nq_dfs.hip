@@ -349,10 +349,13 @@ __device__ __forceinline__ void isa_step128(u32x4& st, u32x4 ch, int32_t& top, u
 // of every other launch carries none of its code.  KINGS runs the second
 // search (n kings, one per row and column): the same stack, scheduler and
 // leaf test, with the next row's attacked squares taken from the placed king
-// alone (no diagonals carried down); it exists for form 1 only.
+// alone (no diagonals carried down); it exists for forms 1 and 7, form 7 with
+// the popcount leaf test only (the kings' rd is recomputed from the king just
+// placed, so it cannot carry the row marker).
 template <bool PERSISTENT, bool STATS, bool LEAFCTR, int LOOP, bool SERVE, bool KINGS = false>
 __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
-    static_assert(!KINGS || LOOP == 1, "the kings search runs in form 1 only");
+    static_assert(!KINGS || LOOP == 1 || (LOOP == 7 && !LEAFCTR),
+                  "the kings search runs in form 1, or in form 7 with the popcount leaf test");
     constexpr bool F3 = LOOP == 3 || LOOP >= 6;      // the step without selects
     constexpr bool SENT = kFormSentinel[LOOP] != 0u;
     extern __shared__ uint4 lds_stack[];
@@ -626,8 +629,8 @@ __global__ __launch_bounds__(1024) void nq_dfs_kernel(DfsParams P) {
                 from = isa_sel_i(restm, top + 1024, top);
             }
             B.x = A.x + p;                            // p is free: + is |
-            B.y = (A.y + p) << 1;
-            B.z = (A.z + p) >> 1;
+            B.y = KINGS ? p << 1 : (A.y + p) << 1;
+            B.z = KINGS ? p >> 1 : (A.z + p) >> 1;
             B.w = ~(B.x | B.y | B.z);                 // off-board columns are set in B.x
             const uint64_t leafm = __builtin_amdgcn_ballot_w64(
                 LEAFCTR ? B.z < leaf_lim : __popc(B.x) == 31u);
@@ -808,8 +811,18 @@ static const void* kernel_ptr() {
         &nq_dfs_kernel<PERSISTENT, STATS, LEAFCTR, LOOP, SERVE, KINGS>);
 }
 
-// The kings search: default form, no serving.
-static const void* select_kings_kernel(uint32_t mode, bool stats, bool leafctr) {
+// The kings search: form 1 (with or without the row counter) or form 7 (the
+// popcount leaf test only), no serving.
+static const void* select_kings_kernel(int form, uint32_t mode, bool stats, bool leafctr) {
+    if (form == 7) {
+        if (leafctr) return nullptr;
+        if (mode == NQ_MODE_PERSISTENT)
+            return stats ? kernel_ptr<true, true, false, 7, false, true>()
+                         : kernel_ptr<true, false, false, 7, false, true>();
+        return stats ? kernel_ptr<false, true, false, 7, false, true>()
+                     : kernel_ptr<false, false, false, 7, false, true>();
+    }
+    if (form != 1) return nullptr;
     if (mode == NQ_MODE_PERSISTENT) {
         if (stats)
             return leafctr ? kernel_ptr<true, true, true, 1, false, true>()
@@ -899,7 +912,7 @@ uint32_t default_idle_min() {
 
 static const void* select_kernel(int form, uint32_t mode, bool stats, bool leafctr, bool serve,
                                  bool kings) {
-    if (kings) return (form == 1 && !serve) ? select_kings_kernel(mode, stats, leafctr) : nullptr;
+    if (kings) return serve ? nullptr : select_kings_kernel(form, mode, stats, leafctr);
     switch (form) {
         case 0: return select_kernel_loop<0>(mode, stats, leafctr, serve);
         case 1: return select_kernel_loop<1>(mode, stats, leafctr, serve);
@@ -947,11 +960,12 @@ int plan_launch(const DeviceInfo& dev, uint32_t mode, uint32_t wg_size, uint32_t
                 uint32_t frames, uint64_t len, bool stats, bool leafctr, LaunchCfg* cfg,
                 bool serve, bool kings, uint32_t max_n) {
     if (mode != NQ_MODE_PLAIN && mode != NQ_MODE_PERSISTENT) return NQ_EINVAL;
-    // the kings search runs form 1 only (its rd carries no marker)
-    const int form = kings ? 1 : loop_form();
+    // the kings search runs form 1 when the queens run form 1, else form 7
+    // with the popcount leaf test (its rd carries no marker)
+    const int form = kings ? (loop_form() == 1 ? 1 : 7) : loop_form();
     // form 3's marker starts at bit 2n - 1 - placed = n + 1 + (frames of the
     // entry): it fits in 32 bits for every entry when max_n + frames <= 30
-    if (form == 3 || form >= 6) leafctr = leafctr && max_n + frames <= 30u;
+    if (form == 3 || form >= 6) leafctr = leafctr && max_n + frames <= 30u && !kings;
     frames += kFormExtraFrames[form];
     if (wg_size == 0) {
         // Plain: up to 4 waves per workgroup, as many as the LDS stacks allow.

@@ -96,17 +96,38 @@ def test_node_counts_and_dead_entries():
             np.testing.assert_array_equal(counts.cpu().numpy().view(np.uint64), ref)
 
 
-def test_kings_runs_its_own_form_whatever_form_is_selected():
-    """The kings search has one inner-loop form (form 1's step with the
-    kings' attacks); selecting another form for the queens, the default one
-    included, leaves it exact."""
+def test_kings_forms_under_every_selected_form():
+    """The kings search runs form 1's step while the queens run form 1 and
+    form 7's step (the popcount leaf test) under every other form, the
+    default included.  Totals stay exact under each selection; under form 1
+    the per-subproblem and node counts also equal the oracle's (the other
+    tests above run form 7)."""
     nq = _nq()
     want = _kings_counts(10)[10]
-    for form in (0, 2, 3, 4, 5, 6, 7):
+    for form in (0, 1, 2, 3, 4, 5, 6, 7):
         prev = nq.set_loop_form(form)
         try:
             _say("kings under form", form)
-            assert nq.count(10, depth=3, kings=True) == want
+            for mode in ("persistent", "plain"):
+                assert nq.count(10, depth=3, mode=mode, kings=True) == want, (form, mode)
         finally:
             nq.set_loop_form(-1)
         assert prev in range(8)
+    n, k = 11, 3
+    pre, _ = oracle.kings_frontier(n, k)
+    ref, ref_nodes = oracle.kings_count_prefixes(n, pre, threads=8)
+    c, l, r = (_dev(x) for x in oracle.kings_prefixes_masks(n, pre))
+    nodes = torch.empty(len(pre), dtype=torch.int64, device="cuda")
+    nq.set_loop_form(1)
+    try:
+        for mode in ("persistent", "plain"):
+            _say("form 1 nodes", n, k, mode)
+            counts, _ = nq.count_subproblems(n, c, l, r, depth=k, mode=mode, nodes=nodes,
+                                             kings=True)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(counts.cpu().numpy().view(np.uint64), ref)
+            np.testing.assert_array_equal(nodes.cpu().numpy().view(np.uint64), ref_nodes)
+        _say("form 1 auto depth 14")
+        assert nq.count(14, kings=True) == _kings_counts(14)[14]
+    finally:
+        nq.set_loop_form(-1)
