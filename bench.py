@@ -347,7 +347,7 @@ def _slice_check(nq, torch, n, k, cols, ld, rd, w, start, length, entries):
     return int(tot.item()), c.numel(), int(nodes.sum())
 
 
-def bench_serving(nq, torch, known, rates, seconds):
+def bench_serving(nq, torch, known, rates, seconds, waves_per_cu=0):
     """Poisson COUNT(N in 10..18) requests with N=21 depth-6 4096-entry slices
     interleaved; per rate: p50/p99 latency (all COUNTs, per N, slices),
     throughput in requests/s and in served DFS nodes/s.  Every COUNT result is
@@ -361,7 +361,9 @@ def bench_serving(nq, torch, known, rates, seconds):
     c21, l21, r21, w21 = nq.frontier(n21, k21)
     res = {"solo_count_ms": {}, "rates": []}
     count_nodes, slice_ref = {}, {}
-    with nq.Server(hbm_budget=64 << 30) as srv:
+    if waves_per_cu:
+        res["waves_per_cu"] = waves_per_cu                 # cap on each epoch's resident waves
+    with nq.Server(hbm_budget=64 << 30, waves_per_cu=waves_per_cu) as srv:
         srv.wait(srv.submit_slice(n21, k21, 0, 1))          # builds the resident frontier
         for n in range(10, 19):
             srv.wait(srv.submit_count(n))                     # builds this N's frontier
@@ -828,7 +830,8 @@ def main():
     if args.serving_only:
         rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
         print(json.dumps({"serving": bench_serving(nq, torch, known_counts(), rates,
-                                                   args.serve_seconds)}), flush=True)
+                                                   args.serve_seconds, args.waves_per_cu)}),
+              flush=True)
         return
     if args.ubench_counters:
         for layout in (0, 1):

@@ -456,8 +456,10 @@ int nq_batch_destroy(nq_batch* batch);
  * A scheduler thread owned by the server admits requests in arrival order while
  * request slots (4096), work-ring space and the LDS stack of the epoch kernel
  * allow, and launches bounded persistent "epochs" over the newly admitted
- * subproblems on four rotating streams, so new work overlaps the tail of
- * older work.  A request's result is published to pinned host memory by the
+ * subproblems on one of four streams, so new work overlaps the tail of
+ * older work.  An epoch starts only on a stream with no epoch in flight; the
+ * last stream takes only epochs of quick requests (COUNTs of boards up to
+ * 16), which may start before older requests of other kinds.  A request's result is published to pinned host memory by the
  * GPU lane that retires its last subproblem (retirements are added to the
  * request's total and remaining count once per wave and request).
  *

@@ -22,6 +22,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -71,11 +72,20 @@ struct Resident {
 
 struct Epoch {
     hipEvent_t done = nullptr;
+    uint32_t stream = 0;                   // index of its stream in nq_server::streams
     std::vector<nqi::SlotInit> inits;      // host staging kept alive until `done`
 };
 
 constexpr uint32_t kHeads = 64;
 constexpr uint32_t kStreams = 4;             // epochs in flight at once (divides kHeads)
+constexpr uint32_t kHeadStride = kHeads / kStreams;   // work heads of two streams: 128 B apart
+// The latency lane: the last stream takes only epochs of quick requests
+// (COUNTs of boards up to kQuickMaxN, at most about 1.3 ms alone on the whole
+// GPU), so that a quick request never waits for a free stream behind epochs
+// of N = 17, 18 counts or slices, which take 5 to 20 ms each.  Quick epochs
+// may also take any other free stream; the others never take the last one.
+constexpr uint32_t kQuickStream = kStreams - 1;
+constexpr uint32_t kQuickMaxN = 16;
 constexpr size_t kRingEntryBytes = 4 * 4 + 1;   // cols, ld, rd, inst + weight
 constexpr uint64_t kCountEntries = 1u << 18;    // COUNT: shallowest depth with this many
 constexpr uint64_t kSliceSplit = 1u << 16;      // SLICE residents: expand when a slice of
@@ -138,6 +148,7 @@ struct nq_server {
     uint64_t next_ticket = 1;
     uint64_t ring_head = 0, ring_tail = 0;  // logical positions, tail - head in use
     uint64_t epoch_no = 0;
+    bool round_robin = false;               // epoch i on stream i mod kStreams, busy or not
     std::deque<Epoch> epochs;
     std::thread worker;
 };
@@ -280,17 +291,59 @@ int retire_epochs(nq_server* s) {
     return err;
 }
 
-// Admits candidates in arrival order while request slots and ring space
-// allow and launches one epoch over them (scheduler thread, mu not held:
-// resident frontier builds and the enqueued copies and launch do not block
-// submitters).  *used receives how many candidates were decided (admitted or
-// finished); the others wait for ring space.
+bool quick_request(const nq_request& rq) {
+    return rq.kind == NQ_REQ_COUNT && rq.n <= kQuickMaxN;
+}
+
+// The stream for the next epoch: one with no epoch in flight, so that an
+// epoch never waits in stream order behind another (a short epoch queued
+// behind an N = 18 count would wait for all of it), or -1 when every stream
+// the epoch may take is busy (the candidates then wait in the queue, and the
+// next epoch takes all that arrived meanwhile).  A quick epoch tries the
+// latency lane first, and the other streams only when `lane_only` is false
+// (no other request waits for them, so quick ones cannot starve them).  With
+// `round_robin` (NQ_SERVE_ROUND_ROBIN=1 in the environment, for measurement)
+// epoch i goes to stream i mod kStreams, busy or not, whatever its requests.
+int pick_stream(nq_server* s, bool quick, bool lane_only) {
+    if (s->round_robin) return (int)(s->epoch_no % kStreams);
+    bool busy[kStreams] = {};
+    for (const Epoch& ep : s->epochs)
+        if (!busy[ep.stream] && hipEventQuery(ep.done) == hipErrorNotReady) busy[ep.stream] = true;
+    if (quick && !busy[kQuickStream]) return (int)kQuickStream;
+    if (quick && lane_only) return -1;
+    for (uint32_t i = 0; i < kStreams - 1; ++i) {
+        const uint32_t k = (uint32_t)((s->epoch_no + i) % (kStreams - 1));
+        if (!busy[k]) return (int)k;
+    }
+    return -1;
+}
+
+// Admits candidates of one class (quick or not) in arrival order while
+// request slots and ring space allow and launches one epoch over them
+// (scheduler thread, mu not held: resident frontier builds and the enqueued
+// copies and launch do not block submitters).  Quick requests go first when
+// the latency lane (or, with no other request waiting, another stream) is
+// free for them: they may overtake older requests of the other class, never
+// one of their own.  decided[i]
+// is set for every candidate admitted or finished; the others stay queued.
 int admit_and_launch(nq_server* s, const std::vector<Candidate>& cand, std::vector<Outcome>* out,
-                     size_t* used) {
-    *used = 0;
+                     std::vector<char>* decided) {
+    decided->assign(cand.size(), 0);
     if (cand.empty() || s->free_slots.empty()) return NQ_OK;
+    bool any_quick = false, any_other = false;
+    for (const Candidate& c : cand) (quick_request(c.rq) ? any_quick : any_other) = true;
+    const bool split = !s->round_robin;                   // round robin: one class
+    int sidx = -1;
+    bool quick_epoch = any_quick;
+    if (any_quick) sidx = pick_stream(s, true, any_other);
+    if (sidx < 0 && any_other) {
+        sidx = pick_stream(s, false, false);
+        quick_epoch = false;
+    }
+    if (sidx < 0) return NQ_OK;                           // every stream busy: wait
     TraceRange t("epoch");
     Epoch ep;
+    ep.stream = (uint32_t)sidx;
     const uint64_t epoch_start = s->ring_tail;
     uint32_t frames = 0;                                  // deepest stack of the epoch
     // Whether every request of the epoch fits the default step's row marker
@@ -303,9 +356,11 @@ int admit_and_launch(nq_server* s, const std::vector<Candidate>& cand, std::vect
     size_t idx = 0;
     for (; idx < cand.size() && !s->free_slots.empty(); ++idx) {
         const Candidate& c = cand[idx];
+        if (split && quick_request(c.rq) != quick_epoch) continue;   // the other class's epoch
         auto finish = [&](int status, uint64_t count) {
             const uint64_t now = now_ns();
             out->push_back({c.ticket, status, false, count, 0, 0, 0, 0, 0, now});
+            (*decided)[idx] = 1;
         };
         Resident* res = nullptr;
         int rc = ensure_resident(s, c.rq.n, c.depth, c.rq.kind, &res);
@@ -337,16 +392,16 @@ int admit_and_launch(nq_server* s, const std::vector<Candidate>& cand, std::vect
         ep.inits.push_back({slot, c.rq.n, (uint32_t)F, gen});
         copies.push_back({res, src, start, F, slot});
         out->push_back({c.ticket, NQ_OK, true, 0, F, start, F, slot, gen, now_ns()});
+        (*decided)[idx] = 1;
         s->admitted.push_back({c.ticket, start, F, slot, gen, false});
     }
-    *used = idx;
     if (copies.empty()) return NQ_OK;
     const uint64_t n_entries = s->ring_tail - epoch_start;
-    hipStream_t st = s->streams[s->epoch_no % kStreams];
+    hipStream_t st = s->streams[sidx];
     hipError_t e = hipSuccess;
     // 1. slot records, 2. every request's entries (device to device out of its
     // resident frontier) and instance ids, in ring order.
-    const size_t init_off = (s->epoch_no % kStreams) * s->max_slots;
+    const size_t init_off = (size_t)sidx * s->max_slots;
     nqi::SlotInit* d_init = s->d_init + init_off;
     if ((e = hipMemcpyAsync(d_init, ep.inits.data(), ep.inits.size() * sizeof(SlotInit),
                             hipMemcpyHostToDevice, st)) != hipSuccess) {
@@ -379,7 +434,7 @@ int admit_and_launch(nq_server* s, const std::vector<Candidate>& cand, std::vect
     P.cols = s->r_cols; P.ld = s->r_ld; P.rd = s->r_rd; P.weight = s->r_w;
     P.inst = s->r_inst; P.inst_n = s->s_n; P.ninst = s->max_slots;
     P.totals = s->s_tot;
-    P.head = s->heads + (s->epoch_no % kHeads);
+    P.head = s->heads + (size_t)sidx * kHeadStride;        // one head per stream, in its order
     P.len = n_entries;
     P.frames = frames;
     P.refill_every = s->launch.refill_every ? s->launch.refill_every : 512u;
@@ -419,9 +474,10 @@ int admit_and_launch(nq_server* s, const std::vector<Candidate>& cand, std::vect
 }
 
 // Applies admission outcomes and returns undecided candidates to the front of
-// the queue (or drops them when the server is being destroyed, as the queue
-// itself was).  mu held.
-void apply(nq_server* s, const std::vector<Candidate>& cand, const std::vector<Outcome>& out) {
+// the queue in their order (or drops them when the server is being
+// destroyed, as the queue itself was).  mu held.
+void apply(nq_server* s, const std::vector<Candidate>& cand, const std::vector<Outcome>& out,
+           const std::vector<char>& decided) {
     for (const Outcome& o : out) {
         auto it = s->reqs.find(o.ticket);
         if (it == s->reqs.end()) continue;
@@ -441,7 +497,8 @@ void apply(nq_server* s, const std::vector<Candidate>& cand, const std::vector<O
             r.state = ReqState::Done;
         }
     }
-    for (size_t i = cand.size(); i-- > out.size();) {
+    for (size_t i = cand.size(); i-- > 0;) {
+        if (i < decided.size() && decided[i]) continue;
         if (s->stop)
             s->reqs.erase(cand[i].ticket);
         else
@@ -453,10 +510,12 @@ void apply(nq_server* s, const std::vector<Candidate>& cand, const std::vector<O
 void worker_main(nq_server* s) {
     std::vector<Candidate> cand;
     std::vector<Outcome> out;
+    std::vector<char> decided;
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         cand.clear();
         out.clear();
+        decided.clear();
         int rc = NQ_OK, hip = 0;
         try {
             collect(s);
@@ -478,8 +537,7 @@ void worker_main(nq_server* s) {
                 rc = NQ_EDEVICE;
                 hip = ev;
             } else if (!cand.empty()) {
-                size_t used = 0;
-                rc = admit_and_launch(s, cand, &out, &used);
+                rc = admit_and_launch(s, cand, &out, &decided);
                 if (rc != NQ_OK) hip = nq_last_hip_error();   // set on this (the worker) thread
             }
         } catch (...) {                 // a host allocation failed: stop admitting
@@ -487,7 +545,7 @@ void worker_main(nq_server* s) {
             hip = 0;
         }
         if (!lk.owns_lock()) lk.lock();
-        apply(s, cand, out);
+        apply(s, cand, out, decided);
         if (rc != NQ_OK && s->fatal == NQ_OK) {
             s->fatal = rc;
             s->fatal_hip = hip;
@@ -536,6 +594,7 @@ int serve_create(const nq_opts* opts, uint64_t hbm_budget, nq_server** out) {
     nq_server* s = new (std::nothrow) nq_server();
     if (!s) return NQ_ENOMEM;
     if (opts) s->launch = *opts;
+    if (const char* rr = std::getenv("NQ_SERVE_ROUND_ROBIN")) s->round_robin = rr[0] == '1';
     s->budget = hbm_budget ? hbm_budget : (8ull << 30);
     // Frames: requests whose subproblems need more are refused at submit.
     s->max_frames = (opts && opts->depth) ? opts->depth : 14u;
