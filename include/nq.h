@@ -535,9 +535,8 @@ int nq_serve_destroy(nq_server* server);
  * nq_perm_count_subproblems: counts below `len` device-resident entries
  * d_cols (used-column sets with exactly `depth` rows assigned; the launch's
  * stack is sized for the n - 3 - depth frames such an entry needs (one more
- * with the default hand-scheduled step, whose frame of row n - 3 is written
- * before its leaves are counted; NQ_PERM_STEP=0 in the environment selects
- * the plain C++ step, for measurement), and an entry that needs more is
+ * with the hand-scheduled steps, whose frame of row n - 3 is written before
+ * its leaves are counted), and an entry that needs more is
  * reported as UINT64_MAX in d_counts and left out of the total).  d_counts
  * (nullable, uint64[len]) receives each entry's count, *d_total (nullable) is
  * increased by their sum; opts: mode, wg_size, waves_per_cu, refill_every,
@@ -548,6 +547,17 @@ int nq_serve_destroy(nq_server* server);
  * opts->depth (0 = the shallowest depth with at least 2^20 entries, at most
  * n - 2 and 2^26 entries), copies it to the device and counts it;
  * synchronous.  opts->flags, counts_out and d_nodes must be 0.
+ *
+ * nq_perm_set_step: the inner step of the permanent launches from now on, to
+ * measure the steps against each other; all give the same counts.  step: -1
+ * = the default (NQ_PERM_STEP=0 or 1 from the environment, else 2), 0 = the
+ * step in plain C++, 1 = hand-scheduled (two register frames, a push without
+ * exec mask, the next row's allowed columns read before the child is known,
+ * the last two rows counted under an exec mask), 2 = step 1 with the
+ * children's row kept in the high bits of the used columns (the library's
+ * default: two VALU instructions fewer per step).  *previous (nullable)
+ * receives the step in use; NQ_EINVAL for any other step.  Process-wide, read
+ * when a launch is made; touches no device.
  */
 #define NQ_PERM_MAX_N 20
 int nq_perm_frontier(uint32_t n, const uint32_t* rows, uint32_t depth, uint32_t* cols,
@@ -556,6 +566,7 @@ int nq_perm_count_subproblems(uint32_t n, const uint32_t* rows, const uint32_t* 
                               uint64_t len, uint32_t depth, uint64_t* d_counts,
                               unsigned long long* d_total, const nq_opts* opts);
 int nq_perm_count(uint32_t n, const uint32_t* rows, const nq_opts* opts, uint64_t* out_total);
+int nq_perm_set_step(int step, int* previous);
 
 #ifdef __cplusplus
 }

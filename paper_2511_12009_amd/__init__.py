@@ -22,6 +22,7 @@ Functions (same names as the C entry points, without the ``nq_`` prefix):
   ubench_valu / ubench_lds                   -> the microbenchmarks behind the roofline
   perm_count / perm_frontier / perm_count_subproblems -> the third search: permanents of
                                                0/1 matrices on the same engine
+  perm_set_step(step)                        -> the permanent kernel's inner step (measurement)
 """
 from ._native import (  # noqa: F401
     Batch,
@@ -45,6 +46,7 @@ from ._native import (  # noqa: F401
     perm_count_subproblems,
     perm_frontier,
     perm_rows,
+    perm_set_step,
     ubench_lds,
     ubench_valu,
 )

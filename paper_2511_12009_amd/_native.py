@@ -171,6 +171,8 @@ def lib():
         L.nq_perm_count_subproblems.restype = ct.c_int
         L.nq_perm_count.argtypes = [u32, pu32, ct.POINTER(NqOpts), pu64]
         L.nq_perm_count.restype = ct.c_int
+        L.nq_perm_set_step.argtypes = [ct.c_int, ct.POINTER(ct.c_int)]
+        L.nq_perm_set_step.restype = ct.c_int
         _LIB = L
     return _LIB
 
@@ -446,6 +448,14 @@ def set_loop_form(form: int) -> int:
     (-1 = default; 0 to 7); returns the form that was in use."""
     prev = ct.c_int(0)
     _check(lib().nq_set_loop_form(int(form), ct.byref(prev)), "nq_set_loop_form")
+    return prev.value
+
+
+def perm_set_step(step: int) -> int:
+    """nq_perm_set_step: the permanent kernel's inner step of launches from now
+    on (-1 = default; 0, 1 or 2); returns the step that was in use."""
+    prev = ct.c_int(0)
+    _check(lib().nq_perm_set_step(int(step), ct.byref(prev)), "nq_perm_set_step")
     return prev.value
 
 

@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <new>
 #include <vector>
@@ -41,6 +42,18 @@ namespace nqi {
 namespace {
 
 constexpr uint32_t kPermParked = 0xffffffffu;     // sentinel: all columns used, nothing untried
+// Step 2 keeps the row of a frame's children in bits 27..31 of its used
+// columns (boards have at most 20 columns, bits 20..26 stay zero), so that
+// bits 25..31 are the byte offset of that row's allowed columns in a table
+// of 32 rows, one per LDS bank.  Its sentinel has every column used and row
+// 31; the row of a parked lane's child wraps through 0..31, all inside the
+// table, and a parked lane reading row r reads the word of the live lanes
+// at row r (a 64-row table put rows r and r + 32 in one bank: 1.5 % of the
+// LDS instructions conflicted).
+constexpr uint32_t kPermRowShift = 27;
+constexpr uint32_t kPermRowOne = 1u << kPermRowShift;
+constexpr uint32_t kPermParked2 = 0xf80fffffu;
+constexpr uint32_t kPermTableRows = 34;
 constexpr uint32_t kPermFrameBytes = 8;
 
 struct PermParams {
@@ -104,6 +117,13 @@ __device__ __forceinline__ int32_t perm_sel(uint64_t m, int32_t a, int32_t d) {
     return r;
 }
 
+// a + b + c in one instruction (the compiler splits it otherwise).
+__device__ __forceinline__ uint32_t perm_add3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
 // Every lane writes its frame to the slot above its stack top (free space in
 // the lanes that do not push).  No exec mask.
 __device__ __forceinline__ void perm_store_above(u32x2 f, int32_t top) {
@@ -154,16 +174,24 @@ __device__ __forceinline__ void perm_leaf(uint32_t& sum, uint32_t left, uint32_t
 // returns the frame just written when it had an untried column left; the
 // next row's allowed columns are read from LDS before the child is known (the
 // child's row is one more than the frame's), and the last two rows'
-// completions are counted under an exec mask.  Step 1 needs one frame more
-// per lane (the frame of row n - 3 is written before its leaves are counted).
+// completions are counted under an exec mask.  Step 2 (the default) is step
+// 1 with the children's row carried in the high bits of the used columns
+// (kPermRowShift): the row's allowed columns are read at that byte offset
+// and the leaf test compares the word, where step 1 counts the used columns
+// twice (for the address and for the test).  Steps 1 and 2 need one frame
+// more per lane (the frame of row n - 3 is written before its leaves are
+// counted).
 template <bool PERSISTENT, bool STATS, int STEP>
 __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
-    constexpr uint32_t extra = STEP == 1 ? 1u : 0u;
+    constexpr uint32_t extra = STEP >= 1 ? 1u : 0u;
+    constexpr uint32_t parked = STEP == 2 ? kPermParked2 : kPermParked;
     extern __shared__ u32x2 perm_stack[];
-    // the matrix's rows; rows 32 and 33 (the "next row" of a parked lane,
-    // whose used set has all 32 bits) allow nothing
-    __shared__ uint32_t mrows[34];
-    if (threadIdx.x < 34) mrows[threadIdx.x] = threadIdx.x < P.n ? P.rows[threadIdx.x] : 0u;
+    // the matrix's rows, then rows that allow nothing: rows 32 and 33 are the
+    // "next row" of a parked lane in steps 0 and 1 (its used set has all 32
+    // bits), any of rows 0..31 that of a parked lane in step 2
+    __shared__ uint32_t mrows[kPermTableRows];
+    if (threadIdx.x < kPermTableRows)
+        mrows[threadIdx.x] = threadIdx.x < P.n ? P.rows[threadIdx.x] : 0u;
     __syncthreads();
     const uint32_t lds = (uint32_t)(uintptr_t)(lds_frame2*)perm_stack;
     const uint32_t lane = threadIdx.x & 63u;
@@ -179,9 +207,9 @@ __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
     const uint32_t ra = n >= 2u ? mrows[n - 2u] : 0u, rb = mrows[(n - 1u) & 31u];
     const uint32_t leaf_row = n - 2u;     // reached with the last two rows left (n >= 3)
     int32_t top = floor;
-    *frame2_at(floor) = u32x2{kPermParked, 0u};
+    *frame2_at(floor) = u32x2{parked, 0u};
 
-    uint32_t c = kPermParked, v = 0u;
+    uint32_t c = parked, v = 0u;
     uint64_t idx = 0, sum = 0, steps = 0, wtotal = 0;
     uint32_t sum32 = 0;                   // leaves since the last scheduler visit
     bool has_task = false;
@@ -197,7 +225,7 @@ __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
         top = floor;
         sum = 0;
         steps = 0;
-        *frame2_at(floor) = u32x2{kPermParked, 0u};
+        *frame2_at(floor) = u32x2{parked, 0u};
         c = P.cols[i] & board;
         v = 0u;
         const uint32_t placed = __popc(c);
@@ -211,8 +239,9 @@ __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
             sum = kCountInvalid;                       // does not fit this launch's stack
         } else {
             v = mrows[placed] & ~c & board;
+            if (STEP == 2) c |= (placed + 1u) << kPermRowShift;   // the children's row
         }
-        if (v == 0u) c = kPermParked;
+        if (v == 0u) c = parked;
     };
 
     if (!PERSISTENT) {
@@ -239,25 +268,35 @@ __global__ __launch_bounds__(1024) void nq_perm_kernel(PermParams P) {
         }
         // ---- DFS steps: place the lowest untried column of the current row.
         // A parked lane (sentinel popped) has every column used and nothing
-        // untried: p = 0, its "next row" is 32 (33 in step 1), which allows
-        // nothing, no leaf, no descent; in step 0 its pops read the sentinel
-        // again (top stays at floor), in step 1 it does not pop.  A board of
-        // n <= 2 never gets here (its entries are settled when taken), so
-        // leaf_row never wraps into use.
-        if (STEP == 1) {
+        // untried: p = 0, its "next row" is 32 (33 in step 1; in step 2 one
+        // of rows 0..31, one more each step), which gives it no unused
+        // allowed column, so no descent (and no count: it is not
+        // alive); in step 0 its pops read the sentinel again (top stays at
+        // floor), in steps 1 and 2 it does not pop.  A board of n <= 2 never
+        // gets here (its entries are settled when taken), so leaf_row never
+        // wraps into use.
+        if (STEP >= 1) {
+            const uint32_t leaf_word = leaf_row << kPermRowShift;   // step 2's leaf test
             auto step = [&](u32x2& A, u32x2& B) {
-                const uint32_t row = __popc(A.x) + 1u;     // the child's row
-                const uint32_t mrow = mrows[row];
+                const uint32_t row = STEP == 2 ? 0u : __popc(A.x) + 1u;   // the child's row
+                const uint32_t mrow =
+                    STEP == 2 ? *reinterpret_cast<const uint32_t*>(
+                                    reinterpret_cast<const char*>(mrows) + (A.x >> 25))
+                              : mrows[row];
                 uint32_t p, rest = A.y;
                 uint64_t alive;
                 perm_take(rest, p, alive);
                 A.y = rest;
                 const uint64_t restm = __builtin_amdgcn_ballot_w64(rest != 0u);
                 int32_t from = perm_sel(restm, top + stride, top);   // where a pop reads
-                B.x = A.x | p;
-                const uint32_t left = board & ~B.x;        // unused columns
-                B.y = mrow & left;
-                const uint64_t leafm = __builtin_amdgcn_ballot_w64(row == leaf_row);
+                // p is unused, so + is |; step 2 computes the unused and the
+                // allowed unused columns from A.x and p, off the add's path
+                B.x = STEP == 2 ? perm_add3(A.x, p, kPermRowOne) : (A.x | p);
+                const uint32_t left = STEP == 2 ? board & ~(A.x | p) : board & ~B.x;
+                B.y = STEP == 2 ? mrow & ~(A.x | p) : mrow & left;   // a row lies in the board
+                // step 2: a live frame's children are at most at the leaf row
+                const uint64_t leafm = __builtin_amdgcn_ballot_w64(
+                    STEP == 2 ? A.x >= leaf_word : row == leaf_row);
                 const uint64_t anym = perm_nonzero(B.y);
                 if (STATS) steps += (p != 0u) ? 1u : 0u;
                 perm_leaf(sum32, left, ra, rb, leafm & alive);
@@ -329,19 +368,26 @@ const void* perm_kernel_step(bool persistent, bool stats) {
                  : reinterpret_cast<const void*>(&nq_perm_kernel<false, false, STEP>);
 }
 
-// The inner loop of later launches: NQ_PERM_STEP=0 in the environment selects
-// the plain C++ step (for measurement), otherwise the hand-scheduled one.
+// The inner loop of the launches from now on: NQ_PERM_STEP=0 or 1 in the
+// environment selects the plain C++ step or the hand-scheduled step without
+// the row field (for measurement), otherwise step 2; nq_perm_set_step sets it
+// at run time.
+std::atomic<int> g_perm_step{-1};
+
 int perm_step() {
-    static const int step = [] {
-        const char* e = std::getenv("NQ_PERM_STEP");
-        return (e && e[0] == '0' && e[1] == 0) ? 0 : 1;
-    }();
-    return step;
+    int st = g_perm_step.load(std::memory_order_relaxed);
+    if (st >= 0) return st;
+    const char* e = std::getenv("NQ_PERM_STEP");
+    st = (e && (e[0] == '0' || e[0] == '1') && e[1] == 0) ? e[0] - '0' : 2;
+    int expect = -1;
+    g_perm_step.compare_exchange_strong(expect, st);
+    return g_perm_step.load(std::memory_order_relaxed);
 }
 
 const void* perm_kernel(bool persistent, bool stats, int step) {
-    return step == 1 ? perm_kernel_step<1>(persistent, stats)
-                     : perm_kernel_step<0>(persistent, stats);
+    return step == 2   ? perm_kernel_step<2>(persistent, stats)
+           : step == 1 ? perm_kernel_step<1>(persistent, stats)
+                       : perm_kernel_step<0>(persistent, stats);
 }
 
 // Rows of an n x n matrix: every bit is a column of the board.
@@ -403,14 +449,14 @@ int perm_run(uint32_t n, const uint32_t* rows, const uint32_t* d_cols, uint64_t 
     int rc = device_info(&dev);
     if (rc != NQ_OK) return rc;
     // frames for rows depth..n-4 (the current frame is in registers and the
-    // last two rows are never entered), plus step 1's frame of row n - 3
+    // last two rows are never entered), plus steps 1 and 2's frame of row n - 3
     const int step = perm_step();
     const uint32_t frames = std::max<uint32_t>(1, n >= depth + 3u ? n - 3u - depth : 0u) +
-                            (step == 1 ? 1u : 0u);
+                            (step >= 1 ? 1u : 0u);
     uint32_t wg = opts && opts->wg_size ? opts->wg_size : 64u;
     if (wg % 64u != 0 || wg > 1024u) return NQ_EINVAL;
     const uint64_t lds = (uint64_t)wg * (frames + 1u) * kPermFrameBytes;
-    if (lds + 34u * 4u > (uint64_t)dev.lds_per_block) return NQ_EINVAL;   // + the matrix
+    if (lds + kPermTableRows * 4u > (uint64_t)dev.lds_per_block) return NQ_EINVAL;   // + the matrix
     const bool stats = opts && opts->d_nodes;
     const void* fn = perm_kernel(mode == NQ_MODE_PERSISTENT, stats, step);
     uint32_t grid = 0;
@@ -496,6 +542,13 @@ int perm_run(uint32_t n, const uint32_t* rows, const uint32_t* d_cols, uint64_t 
 }  // namespace nqi
 
 using namespace nqi;
+
+extern "C" int nq_perm_set_step(int step, int* previous) {
+    if (step < -1 || step > 2) return NQ_EINVAL;
+    if (previous) *previous = nqi::perm_step();
+    nqi::g_perm_step.store(step, std::memory_order_relaxed);   // -1: read again on next use
+    return NQ_OK;
+}
 
 extern "C" int nq_perm_frontier(uint32_t n, const uint32_t* rows, uint32_t depth, uint32_t* cols,
                                 uint64_t capacity, uint64_t* out_len) {

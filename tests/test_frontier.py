@@ -223,6 +223,26 @@ def test_loop_form_setter_validates_and_restores():
         nq.set_loop_form(prev)
 
 
+def test_perm_step_setter_validates_and_restores():
+    """nq_perm_set_step touches no device: unknown steps are refused, and -1
+    restores the default (step 2 unless NQ_PERM_STEP selects 0 or 1)."""
+    import paper_2511_12009_amd as nq
+    prev = nq.perm_set_step(-1)
+    default = nq.perm_set_step(-1)
+    try:
+        assert default in (0, 1, 2)
+        for bad in (-2, 3, 100):
+            with pytest.raises(nq.NQError):
+                nq.perm_set_step(bad)
+        assert nq.perm_set_step(0) == default
+        assert nq.perm_set_step(1) == 0
+        assert nq.perm_set_step(2) == 1
+        assert nq.perm_set_step(-1) == 2
+        assert nq.perm_set_step(-1) == default
+    finally:
+        nq.perm_set_step(prev)
+
+
 def _progress_record(n, depth, host_depth, chunks, done, total):
     """The text of one nq_count_resumable progress record (its file format)."""
     body = (f"nq-progress 1 n={n} depth={depth} host_depth={host_depth} chunks={chunks} "

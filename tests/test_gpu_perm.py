@@ -168,3 +168,35 @@ def test_largest_board_sampled_entries():
     from conftest import read_table
     stored = {(int(r[0]), float(r[1]), int(r[2])): int(r[3]) for r in read_table("perm_totals.txt")}
     assert int(total.item()) == stored[(20, 0.5, 0)]
+
+
+@pytest.mark.parametrize("step", [0, 1, 2])
+def test_every_inner_step_matches_the_oracle(step):
+    """The three inner steps (nq_perm_set_step: plain C++, hand-scheduled, and
+    the default with the children's row in the used-column word) give the
+    oracle's per-entry counts, node counts and totals, persistent and plain,
+    including full matrices (n!) and boards whose rows run out early."""
+    nq = _nq()
+    prev = nq.perm_set_step(step)
+    try:
+        a = _matrix(13, 0.6, 7)
+        for k in (3, 5):
+            pre = oracle.perm_frontier(a, k)
+            ref, ref_nodes = oracle.perm_count_prefixes(a, pre, threads=8)
+            d = _dev(nq.perm_frontier(a, k))
+            nodes = torch.empty(len(pre), dtype=torch.int64, device="cuda")
+            for mode in ("persistent", "plain"):
+                _say("step", step, "entries", k, mode)
+                counts, total = nq.perm_count_subproblems(a, d, k, nodes=nodes, mode=mode)
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(counts.cpu().numpy().view(np.uint64), ref)
+                np.testing.assert_array_equal(nodes.cpu().numpy().view(np.uint64), ref_nodes)
+                assert int(total.item()) == int(ref.sum())
+        for n in (1, 2, 3, 4, 9, 12):
+            assert nq.perm_count(np.ones((n, n), dtype=np.uint8)) == math.factorial(n), n
+        for n, dens, seed in ((8, 0.2, 5), (14, 0.5, 3), (18, 0.4, 11), (20, 0.3, 1)):
+            m = _matrix(n, dens, seed)
+            _say("step", step, "total", n, dens)
+            assert nq.perm_count(m) == oracle.permanent_ryser(m), (n, dens)
+    finally:
+        nq.perm_set_step(prev)
