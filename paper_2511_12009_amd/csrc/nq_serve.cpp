@@ -281,12 +281,17 @@ void collect(nq_server* s) {
 // publish.
 int retire_epochs(nq_server* s) {
     int err = 0;
-    while (!s->epochs.empty()) {
-        const hipError_t q = hipEventQuery(s->epochs.front().done);
-        if (q == hipErrorNotReady) break;
+    // every finished epoch, not only a prefix: quick epochs end behind a long
+    // one on another stream, and the list stays as short as the work in flight
+    for (auto it = s->epochs.begin(); it != s->epochs.end();) {
+        const hipError_t q = hipEventQuery(it->done);
+        if (q == hipErrorNotReady) {
+            ++it;
+            continue;
+        }
         if (q != hipSuccess && err == 0) err = (int)q;
-        (void)hipEventDestroy(s->epochs.front().done);
-        s->epochs.pop_front();
+        (void)hipEventDestroy(it->done);
+        it = s->epochs.erase(it);
     }
     return err;
 }
