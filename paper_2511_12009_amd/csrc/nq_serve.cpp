@@ -83,7 +83,8 @@ constexpr uint32_t kHeadStride = kHeads / kStreams;   // work heads of two strea
 // (COUNTs of boards up to kQuickMaxN, at most about 1.3 ms alone on the whole
 // GPU), so that a quick request never waits for a free stream behind epochs
 // of N = 17, 18 counts or slices, which take 5 to 20 ms each.  Quick epochs
-// may also take any other free stream; the others never take the last one.
+// take another free stream only while no other request waits; the others
+// never take the last one.
 constexpr uint32_t kQuickStream = kStreams - 1;
 constexpr uint32_t kQuickMaxN = 16;
 constexpr size_t kRingEntryBytes = 4 * 4 + 1;   // cols, ld, rd, inst + weight
@@ -329,8 +330,8 @@ int pick_stream(nq_server* s, bool quick, bool lane_only) {
 // copies and launch do not block submitters).  Quick requests go first when
 // the latency lane (or, with no other request waiting, another stream) is
 // free for them: they may overtake older requests of the other class, never
-// one of their own.  decided[i]
-// is set for every candidate admitted or finished; the others stay queued.
+// one of their own.  decided[i] is set for every candidate admitted or
+// finished; the others stay queued.
 int admit_and_launch(nq_server* s, const std::vector<Candidate>& cand, std::vector<Outcome>* out,
                      std::vector<char>* decided) {
     decided->assign(cand.size(), 0);
