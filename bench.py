@@ -347,7 +347,7 @@ def _slice_check(nq, torch, n, k, cols, ld, rd, w, start, length, entries):
     return int(tot.item()), c.numel(), int(nodes.sum())
 
 
-def bench_serving(nq, torch, known, rates, seconds, waves_per_cu=0):
+def bench_serving(nq, torch, known, rates, seconds, waves_per_cu=0, reserve=False):
     """Poisson COUNT(N in 10..18) requests with N=21 depth-6 4096-entry slices
     interleaved; per rate: p50/p99 latency (all COUNTs, per N, slices),
     throughput in requests/s and in served DFS nodes/s.  Every COUNT result is
@@ -363,7 +363,9 @@ def bench_serving(nq, torch, known, rates, seconds, waves_per_cu=0):
     count_nodes, slice_ref = {}, {}
     if waves_per_cu:
         res["waves_per_cu"] = waves_per_cu                 # cap on each epoch's resident waves
-    with nq.Server(hbm_budget=64 << 30, waves_per_cu=waves_per_cu) as srv:
+    if reserve:
+        res["reserve"] = True                              # NQ_FLAG_SERVE_RESERVE
+    with nq.Server(hbm_budget=64 << 30, waves_per_cu=waves_per_cu, reserve=reserve) as srv:
         srv.wait(srv.submit_slice(n21, k21, 0, 1))          # builds the resident frontier
         for n in range(10, 19):
             srv.wait(srv.submit_count(n))                     # builds this N's frontier
@@ -708,6 +710,8 @@ def main():
     ap.add_argument("--kings-only", type=int, default=0, metavar="N",
                     help="only the kings search on an N x N board (second DFS workload; one JSON line)")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--serve-reserve", action="store_true",
+                    help="with --serving-only: a server created with NQ_FLAG_SERVE_RESERVE")
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
@@ -830,7 +834,8 @@ def main():
     if args.serving_only:
         rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
         print(json.dumps({"serving": bench_serving(nq, torch, known_counts(), rates,
-                                                   args.serve_seconds, args.waves_per_cu)}),
+                                                   args.serve_seconds, args.waves_per_cu,
+                                                   args.serve_reserve)}),
               flush=True)
         return
     if args.ubench_counters:

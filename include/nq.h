@@ -161,9 +161,22 @@ enum nq_flags {
     /* nq_count_subproblems: d_total is uint64[2], a 128-bit total (low word
      * first) increased with carry.  Required when n > 28 and d_total is set:
      * Q(29) already exceeds 2^64 (Section 4.5). */
-    NQ_FLAG_WIDE_TOTAL = 4u
+    NQ_FLAG_WIDE_TOTAL = 4u,
+    /* nq_serve_create only (the counting entry points refuse it): favour the
+     * latency of quick requests (COUNTs of boards up to 16) over throughput.
+     * At most one epoch of other requests runs at a time, with one resident
+     * wave per CU fewer than its LDS stack allows, so that an epoch of quick
+     * requests always finds room on every CU.  Measured on a mix of COUNT
+     * N = 10..18 and N = 21 slices: the quick COUNTs' p99 at 200 requests per
+     * second 8-13 ms instead of 26-53 ms, 15-31 ms instead of 146-194 ms
+     * beyond saturation, for 8 % less throughput at saturation and longer
+     * waits of the other requests. */
+    NQ_FLAG_SERVE_RESERVE = 8u
 };
-#define NQ_FLAGS_ALL 7u
+#define NQ_FLAGS_ALL 15u
+/* The flags nq_count, nq_count_subproblems(_noalloc), the batch and the
+ * resumable entry points accept; any other bit is NQ_EINVAL there. */
+#define NQ_FLAGS_COUNT 7u
 
 /*
  * Options shared by the counting entry points.  A NULL options pointer, or a
@@ -459,11 +472,15 @@ int nq_batch_destroy(nq_batch* batch);
  * subproblems on one of four streams, so new work overlaps the tail of
  * older work.  An epoch starts only on a stream with no epoch in flight; the
  * last stream takes only epochs of quick requests (COUNTs of boards up to
- * 16), which may start before older requests of other kinds.  A request's result is published to pinned host memory by the
+ * 16), which may start before older requests of other kinds.  With
+ * NQ_FLAG_SERVE_RESERVE the other epochs run one at a time and leave a wave
+ * slot per CU to quick ones (lower latency for quick requests, less
+ * throughput).  A request's result is published to pinned host memory by the
  * GPU lane that retires its last subproblem (retirements are added to the
  * request's total and remaining count once per wave and request).
  *
- * nq_serve_create: opts may set depth (= the LDS stack frames per lane of the
+ * nq_serve_create: opts may set flags (NQ_FLAG_SERVE_RESERVE; NQ_FLAG_KINGS
+ * and NQ_FLAG_WIDE_TOTAL are NQ_EINVAL), depth (= the LDS stack frames per lane of the
  * epoch kernel, default 14, at most 26 (NQ_EINVAL beyond): a request whose
  * subproblems need more stack than that is refused with NQ_EINVAL at submit;
  * each epoch's LDS stack is sized for the deepest request in it), wg_size,

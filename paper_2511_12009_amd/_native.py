@@ -189,6 +189,7 @@ def _check(rc: int, what: str):
 FLAG_FORWARD_ORDER = 1
 FLAG_KINGS = 2
 FLAG_WIDE_TOTAL = 4
+FLAG_SERVE_RESERVE = 8
 
 
 def _opts(depth=0, mode="persistent", wg_size=0, waves_per_cu=0, refill_every=0, stream=None,
@@ -576,14 +577,18 @@ def tuned_lookup(n: int):
 class Server:
     """Continuous-batching count server (nq_serve_*).
 
+    reserve=True (NQ_FLAG_SERVE_RESERVE) favours the latency of quick requests
+    (COUNTs of boards up to 16) over throughput.
     submit_count(n, depth=0) / submit_slice(n, depth, start, length) return a
     ticket; poll(ticket) returns None while the request runs, else a dict with
     status, count, entries and the submit/admit/done timestamps (ns).
     """
 
     def __init__(self, hbm_budget: int = 0, max_frames: int = 0, wg_size: int = 0,
-                 waves_per_cu: int = 0, refill_every: int = 0):
+                 waves_per_cu: int = 0, refill_every: int = 0, reserve: bool = False):
         o = _opts(max_frames, "persistent", wg_size, waves_per_cu, refill_every, None)
+        if reserve:                      # NQ_FLAG_SERVE_RESERVE: latency of quick requests first
+            o.flags |= FLAG_SERVE_RESERVE
         h = ct.c_void_p()
         _check(lib().nq_serve_create(ct.byref(o), hbm_budget, ct.byref(h)), "nq_serve_create")
         self._h = h

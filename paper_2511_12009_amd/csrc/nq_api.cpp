@@ -525,7 +525,7 @@ extern "C" int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const ui
                                     const uint32_t* d_rd, const uint8_t* d_weight, uint64_t len,
                                     uint64_t* d_counts, uint64_t* d_total, const nq_opts* opts) {
     if (n < 1 || n > NQ_MAX_N_WIDE) return NQ_EINVAL;
-    if (opts && (opts->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
+    if (opts && (opts->flags & ~NQ_FLAGS_COUNT) != 0) return NQ_EINVAL;
     const uint32_t min_placed = opts ? std::min(opts->depth, n) : 0u;
     if (n > NQ_MAX_N) {
         // beyond 64-bit totals: a 128-bit d_total, and at most 20 rows below
@@ -546,7 +546,7 @@ extern "C" int nq_count_subproblems(uint32_t n, const uint32_t* d_cols, const ui
 
 extern "C" int nq_count(uint32_t n, const nq_opts* opts_in, uint64_t* out_total) {
     if (n < 1 || n > NQ_MAX_N || !out_total) return NQ_EINVAL;
-    if (opts_in && (opts_in->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
+    if (opts_in && (opts_in->flags & ~NQ_FLAGS_COUNT) != 0) return NQ_EINVAL;
     if (opts_in && (opts_in->flags & NQ_FLAG_WIDE_TOTAL)) return NQ_EINVAL;  // no device total
     // Automatic depth: the autotuner's choice for this n if it ran, else the
     // frontier-size rule.  A tuned launch shape fills fields left at 0.
@@ -783,7 +783,7 @@ static int count_resumable(uint32_t n, const nq_opts* opts_in, const char* path,
                            uint32_t max_chunks, uint32_t max_n, unsigned __int128* out_total,
                            uint32_t* out_done) {
     if (n < 1 || n > max_n || !path || !*path || !out_total || !out_done) return NQ_EINVAL;
-    if (opts_in && (opts_in->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
+    if (opts_in && (opts_in->flags & ~NQ_FLAGS_COUNT) != 0) return NQ_EINVAL;
     if (opts_in && (opts_in->counts_out || opts_in->d_nodes)) return NQ_EINVAL;
     if (opts_in && (opts_in->flags & NQ_FLAG_KINGS)) return NQ_EINVAL;
     nq_opts local{};

@@ -62,7 +62,7 @@ uint32_t batch_default_depth(uint32_t n, uint32_t requested) {
 int batch_create(uint32_t ninst, const uint32_t* ns, const uint32_t* depths, const nq_opts* opts,
                  nq_batch** out) {
     if (!out || ninst == 0 || !ns) return NQ_EINVAL;
-    if (opts && (opts->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
+    if (opts && (opts->flags & ~NQ_FLAGS_COUNT) != 0) return NQ_EINVAL;
     // queens only; per-instance totals are 64-bit (every board <= 28)
     if (opts && (opts->flags & (NQ_FLAG_KINGS | NQ_FLAG_WIDE_TOTAL))) return NQ_EINVAL;
     for (uint32_t i = 0; i < ninst; ++i) {

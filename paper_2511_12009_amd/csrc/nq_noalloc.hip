@@ -56,7 +56,7 @@ extern "C" int nq_count_subproblems_noalloc(uint32_t n, const uint32_t* d_cols,
                                             uint64_t* d_counts, uint64_t* d_total,
                                             const nq_opts* opts) {
     if (n < 1 || n > NQ_MAX_N_WIDE) return NQ_EINVAL;
-    if (opts && (opts->flags & ~NQ_FLAGS_ALL) != 0) return NQ_EINVAL;
+    if (opts && (opts->flags & ~NQ_FLAGS_COUNT) != 0) return NQ_EINVAL;
     // timing would create events; the caller times the stream itself
     if (opts && opts->kernel_ms_out) return NQ_EINVAL;
     const uint32_t min_placed = opts ? std::min(opts->depth, n) : 0u;

@@ -150,6 +150,8 @@ struct nq_server {
     uint64_t ring_head = 0, ring_tail = 0;  // logical positions, tail - head in use
     uint64_t epoch_no = 0;
     bool round_robin = false;               // epoch i on stream i mod kStreams, busy or not
+    bool reserve = false;                   // NQ_FLAG_SERVE_RESERVE: one large epoch at a
+                                            // time, a wave per CU left for quick ones
     std::deque<Epoch> epochs;
     std::thread worker;
 };
@@ -308,6 +310,8 @@ bool quick_request(const nq_request& rq) {
 // next epoch takes all that arrived meanwhile).  A quick epoch tries the
 // latency lane first, and the other streams only when `lane_only` is false
 // (no other request waits for them, so quick ones cannot starve them).  With
+// `reserve` (NQ_FLAG_SERVE_RESERVE) other epochs take only the first stream,
+// one at a time, and quick ones the lane and the two streams between.  With
 // `round_robin` (NQ_SERVE_ROUND_ROBIN=1 in the environment, for measurement)
 // epoch i goes to stream i mod kStreams, busy or not, whatever its requests.
 int pick_stream(nq_server* s, bool quick, bool lane_only) {
@@ -316,6 +320,12 @@ int pick_stream(nq_server* s, bool quick, bool lane_only) {
     for (const Epoch& ep : s->epochs)
         if (!busy[ep.stream] && hipEventQuery(ep.done) == hipErrorNotReady) busy[ep.stream] = true;
     if (quick && !busy[kQuickStream]) return (int)kQuickStream;
+    if (s->reserve) {
+        if (!quick) return busy[0] ? -1 : 0;
+        for (uint32_t k = 1; k + 1 < kStreams; ++k)
+            if (!busy[k]) return (int)k;
+        return -1;
+    }
     if (quick && lane_only) return -1;
     for (uint32_t i = 0; i < kStreams - 1; ++i) {
         const uint32_t k = (uint32_t)((s->epoch_no + i) % (kStreams - 1));
@@ -466,6 +476,11 @@ int admit_and_launch(nq_server* s, const std::vector<Candidate>& cand, std::vect
     LaunchCfg cfg = s->cfg_by_frames[small][frames];
     const uint64_t waves = (n_entries + 63) / 64;
     const uint64_t per_wg = cfg.wg_size / 64u;
+    if (s->reserve && !quick_epoch && split) {
+        // one resident wave per CU fewer than the LDS allows: room for quick epochs
+        const uint32_t per_cu = cfg.grid / s->cu_count;  // resident workgroups per CU
+        if (per_cu > 1) cfg.grid = (per_cu - 1) * s->cu_count;
+    }
     cfg.grid = (uint32_t)std::min<uint64_t>(cfg.grid, (waves + per_wg - 1) / per_wg);
     P.claim = default_claim(n_entries, cfg);
     if ((rc = launch_dfs(cfg, P, st)) != NQ_OK) return rc;
@@ -601,6 +616,7 @@ int serve_create(const nq_opts* opts, uint64_t hbm_budget, nq_server** out) {
     if (!s) return NQ_ENOMEM;
     if (opts) s->launch = *opts;
     if (const char* rr = std::getenv("NQ_SERVE_ROUND_ROBIN")) s->round_robin = rr[0] == '1';
+    s->reserve = opts && (opts->flags & NQ_FLAG_SERVE_RESERVE);
     s->budget = hbm_budget ? hbm_budget : (8ull << 30);
     // Frames: requests whose subproblems need more are refused at submit.
     s->max_frames = (opts && opts->depth) ? opts->depth : 14u;

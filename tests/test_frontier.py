@@ -170,12 +170,19 @@ def test_batch_serve_tune_entry_points_validate_before_touching_the_gpu():
     req = nq._native.NqRequest()
     tk = ct.c_uint64()
     assert lib.nq_serve_create(None, 0, None) == -1
-    # unknown flag bits are refused before any device work
+    # unknown flag bits are refused before any device work, and the serving
+    # flag by the counting entry points
     srv = ct.c_void_p()
     so = nq._native.NqOpts()
-    so.flags = 8
+    so.flags = 16
     assert lib.nq_serve_create(ct.byref(so), 0, ct.byref(srv)) == -1
     assert lib.nq_count(12, ct.byref(so), ct.byref(tk)) == -1
+    so.flags = nq._native.FLAG_SERVE_RESERVE
+    assert lib.nq_count(12, ct.byref(so), ct.byref(tk)) == -1
+    assert lib.nq_count_subproblems(12, None, None, None, None, 0, None, None,
+                                    ct.byref(so)) == -1
+    assert lib.nq_count_batch(1, (ct.c_uint32 * 1)(12), None, ct.byref(so),
+                              (ct.c_uint64 * 1)()) == -1
     assert lib.nq_serve_submit(None, ct.byref(req), ct.byref(tk)) == -1
     assert lib.nq_serve_poll(None, 0, ct.byref(res)) == -1
     assert lib.nq_serve_wait(None, 0, ct.byref(res), 1000) == -1

@@ -22,10 +22,14 @@ def _say(*a):
     print("[gpu-serve]", *a, flush=True)
 
 
-def test_counts_alone_and_in_a_mix(known_counts):
+@pytest.mark.parametrize("reserve", [False, True])
+def test_counts_alone_and_in_a_mix(known_counts, reserve):
+    """Counts and slices give the same results alone and in a mix; with
+    NQ_FLAG_SERVE_RESERVE (reserve=True) the quick COUNTs overtake the others
+    and large epochs run one at a time, with the same results."""
     nq = _nq()
     ns = seeded_inputs.serve_count_ns(40)
-    with nq.Server() as srv:
+    with nq.Server(reserve=reserve) as srv:
         alone = {}
         for n in sorted(set(ns)):
             _say("alone", n)
