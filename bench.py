@@ -23,7 +23,8 @@ same engine, n = 16), the permanent of a seeded 20 x 20 0/1 matrix (a third
 DFS, with two-word frames), one GPU's share of an N=21 count
 dealt round-robin over 8 GPUs (all 8 shares run in turn; their totals must add
 up to Q(21)), the serving loop at a few request rates (p50/p99 latency,
-throughput) and the oracle timed on the host cores.
+throughput; then the latency-first server, NQ_FLAG_SERVE_RESERVE, at one
+rate) and the oracle timed on the host cores.
 """
 import argparse
 import json
@@ -712,6 +713,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--serve-reserve", action="store_true",
                     help="with --serving-only: a server created with NQ_FLAG_SERVE_RESERVE")
+    ap.add_argument("--serve-reserve-rates", default="200",
+                    help="COUNT requests/s for the latency-first server in the full run")
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
@@ -1001,6 +1004,12 @@ def main():
     if rates:
         print("[bench] serving", file=sys.stderr, flush=True)
         out["serving"] = bench_serving(nq, torch, known, rates, args.serve_seconds)
+    rates = [float(x) for x in args.serve_reserve_rates.split(",") if x.strip()]
+    if rates:
+        print("[bench] serving, latency-first server (NQ_FLAG_SERVE_RESERVE)", file=sys.stderr,
+              flush=True)
+        out["serving_reserve"] = bench_serving(nq, torch, known, rates, args.serve_seconds,
+                                               reserve=True)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(k, args.cpu_seconds)
